@@ -1,0 +1,43 @@
+"""Seeded workload generator: shapes, determinism, and that on-target reads
+really come from the reference (checked with the oracle)."""
+import numpy as np
+
+import oracle
+import synth
+
+
+def test_shapes_and_determinism():
+    w = synth.workload(1)
+    assert w.reads.nq == 4096 and np.all(w.reads.lengths == 250)
+    assert w.genome.size == 29_903 and w.table.size == 4096
+    w2 = synth.workload(1)
+    assert np.array_equal(w.reads.values, w2.reads.values)
+    assert 0.45 < w.reads.on_target.mean() < 0.55
+    w2 = synth.workload(2)
+    L = w2.reads.lengths
+    assert w2.reads.nq == 8192 and L.min() >= 100 and L.max() <= 2000
+    assert 0.65 < w2.reads.on_target.mean() < 0.75
+    sub = synth.workload(1, nq=10)
+    assert np.array_equal(sub.reads.values, w.reads.values[:2500])
+
+
+def test_reference_size_is_two_strands_of_kmers():
+    w = synth.workload(0)
+    z, codes, nsat = oracle.prepare_reference(w.genome, w.table, w.k)
+    assert z.size == 2 * (29_903 - 6 + 1) == 59_796
+    assert abs(float(z.astype(np.float64).mean())) < 1e-6
+    assert nsat == 0 and codes.dtype == np.int16
+
+
+def test_on_target_reads_map_to_their_origin():
+    w = synth.workload(1, nq=24)
+    z, codes, _ = oracle.prepare_reference(w.genome, w.table, w.k)
+    qz, qc, _ = oracle.prepare_queries(w.reads.values, w.reads.offsets)
+    cost, end, _ = oracle.batch(oracle.F32, qz, w.reads.offsets, z)
+    on = w.reads.on_target
+    assert on.any() and (~on).any()
+    assert np.all(np.abs(end[on] - w.reads.end_true[on]) <= 2)
+    # on-target reads align far more cheaply than off-target ones
+    assert cost[on].max() < cost[~on].min()
+    ci, ei, _ = oracle.batch(oracle.I64, qc, w.reads.offsets, codes)
+    assert np.all(np.abs(ei[on] - w.reads.end_true[on]) <= 2)
