@@ -1,0 +1,212 @@
+"""sDTW benchmark on one MI355X: prints one JSON line.
+
+A step is one pass of the hot path over one batch: per-read normalisation and
+fixed-point scaling of the raw events (sdtw_prepare_queries) followed by the
+batched alignment of every read against the reference (sdtw_align_batch).
+The reference is prepared once on the device (sdtw_prepare_reference) before
+the timed region; all inputs are resident in HBM when timing starts.
+
+Workload (default): 4,096 reads of 250 events against the 59,796-value
+forward+reverse signal of a 29,903-base genome (seeded synthetic data of the
+SARS-CoV-2 workload's shape), int16 inputs with 32-bit accumulation.
+
+`value` is GCUPS (cells = sum over reads of M x N, per second of step time).
+The roofline object reports the alignment kernel's cell rate, timed with HIP
+events on the launch stream, against the VALU roof: 256 CUs x 64 lanes x
+2.4 GHz / (VALU instructions per cell: 2 for int16, 3 for float32).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+CUS, LANES, CLOCK_GHZ = 256, 64, 2.4
+INSTR_PER_CELL = {"i16": 2, "f32": 3}
+
+
+def valu_peak_tcups(dtype: str) -> float:
+    return CUS * LANES * CLOCK_GHZ * 1e9 / INSTR_PER_CELL[dtype] / 1e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=1, choices=[1, 2, 3])
+    ap.add_argument("--dtype", default="i16", choices=["i16", "f32"])
+    ap.add_argument("--strip", type=int, default=0)
+    ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the float32 and one-read-per-launch comparison legs")
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="reads in the oracle's timed sample (0: sized for ~10 s)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the sDTW path "
+              "is built and measured for a single MI355X", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import synth
+    import paper_2211_07340_amd as sd
+
+    dev = torch.device("cuda:0")
+    w = synth.workload(args.config)
+    reads = w.reads
+    nq = reads.nq
+    dt = sd.I16 if args.dtype == "i16" else sd.F32
+
+    # one-time reference preparation on the device (section 4.1)
+    g = torch.from_numpy(w.genome).to(dev)
+    tab = torch.from_numpy(w.table).to(dev)
+    zref, cref, _ = sd.prepare_reference(g, tab, w.k, 64.0)
+    ref = sd.Reference(cref if dt == sd.I16 else zref)
+    N = ref.n
+    raw = torch.from_numpy(reads.values).to(dev)
+    offs_dev = torch.from_numpy(reads.offsets).to(dev)
+    plan = sd.Plan(reads.offsets, dt)
+    if args.strip or args.waves:
+        plan.set_config(args.strip, args.waves)
+    cost = torch.empty(nq, dtype=torch.int32 if dt == sd.I16 else torch.float32, device=dev)
+    end = torch.empty(nq, dtype=torch.int32, device=dev)
+    cells = float(reads.lengths.sum()) * N
+
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        z, codes, _ = sd.prepare_queries(raw, offs_dev, 64.0)
+        q = codes if dt == sd.I16 else z
+        if ev is not None:
+            ev[0].record(stream)
+        sd.align_batch(ref, plan, q, cost, end)
+        if ev is not None:
+            ev[1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    gcups = cells / (ms_step * 1e-3) / 1e9
+    kern_tcups = cells / (kern_ms * 1e-3) / 1e12
+    peak = valu_peak_tcups(args.dtype)
+    strip, waves = plan.config
+
+    out = {
+        "metric": "sDTW GCUPS at 1 GPU (% VALU peak)",
+        "value": round(gcups, 1),
+        "unit": "GCUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i16/i32" if dt == sd.I16 else "f32",
+        "data": "synthetic (seeded genome, stand-in 6-mer pore model, simulated reads)",
+        "config": {"workload": w.name, "reads": nq, "query_values": int(reads.values.size),
+                   "reference_values": N, "cells_per_step": cells,
+                   "strip": strip, "waves_per_cu": waves},
+        "reads_per_s": round(nq / (ms_step * 1e-3), 1),
+        "pct_valu_peak": round(100 * gcups / (peak * 1e3), 2),
+        "roofline": {"bound": "alu", "kernel": "sdtw_align_batch",
+                     "achieved": round(kern_tcups, 3), "peak": round(peak, 3),
+                     "unit": "TCUPS", "frac": round(kern_tcups / peak, 4),
+                     "kernel_ms": round(kern_ms, 4), "traffic": None},
+    }
+
+    if not args.no_extras:
+        out["extras"] = extras(sd, torch, dev, w, reads, zref, cref, args, stream)
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, reads, args)
+    print(json.dumps(out), flush=True)
+
+
+def extras(sd, torch, dev, w, reads, zref, cref, args, stream):
+    """The other number format and the one-read-per-launch baseline."""
+    res = {}
+    other = "f32" if args.dtype == "i16" else "i16"
+    dt = sd.F32 if other == "f32" else sd.I16
+    ref = sd.Reference(zref if dt == sd.F32 else cref)
+    raw = torch.from_numpy(reads.values).to(dev)
+    offs_dev = torch.from_numpy(reads.offsets).to(dev)
+    z, codes, _ = sd.prepare_queries(raw, offs_dev, 64.0)
+    q = z if dt == sd.F32 else codes
+    plan = sd.Plan(reads.offsets, dt)
+    cost, end = sd.align_batch(ref, plan, q)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(5):
+        sd.align_batch(ref, plan, q, cost, end)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / 5
+    cells = float(reads.lengths.sum()) * ref.n
+    res[other] = {"kernel_ms": round(ms, 4), "gcups": round(cells / ms / 1e6, 1),
+                  "frac_valu_peak": round(cells / ms / 1e9 / valu_peak_tcups(other), 4)}
+    # one read per launch with the single-wave kernel, on the main dtype
+    dt0 = sd.I16 if args.dtype == "i16" else sd.F32
+    ref0 = sd.Reference(cref if dt0 == sd.I16 else zref)
+    q0 = codes if dt0 == sd.I16 else z
+    n1 = min(256, reads.nq)
+    offs = reads.offsets
+    sd.align_one(ref0, q0[offs[0]:offs[1]])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(n1):
+        sd.align_one(ref0, q0[offs[r]:offs[r + 1]])
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    c1 = float(reads.lengths[:n1].sum()) * ref0.n
+    res["plain_one_read_per_launch"] = {"reads": n1, "ms_per_read": round(t * 1e3 / n1, 4),
+                                        "gcups": round(c1 / t / 1e9, 2)}
+    return res
+
+
+def cpu_baseline(w, reads, args):
+    """The oracle, untouched, on the host cores over a bounded sample."""
+    import oracle
+    z, codes, _ = oracle.prepare_reference(w.genome, w.table, w.k)
+    qz, qc, _ = oracle.prepare_queries(reads.values, reads.offsets)
+    cores = len(os.sched_getaffinity(0))
+    kind = oracle.I64 if args.dtype == "i16" else oracle.F32
+    q = qc if args.dtype == "i16" else qz
+    r = codes if args.dtype == "i16" else z
+    n = args.cpu_sample or max(8, min(reads.nq, 160 * cores))
+    idx = np.arange(n)
+    t0 = time.perf_counter()
+    _, _, used = oracle.batch(kind, q, reads.offsets, r, index=idx, nthreads=cores)
+    t = time.perf_counter() - t0
+    cells = float(reads.lengths[:n].sum()) * r.size
+    return {"value": round(cells / t / 1e9, 3), "unit": "GCUPS", "cores": used,
+            "kind": "oracle", "seconds": round(t, 2),
+            "sample": f"first {n} reads of the same batch, {'int64' if kind == oracle.I64 else 'float32'} oracle"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,213 @@
+/*
+ * sdtw.h -- C ABI of the MI355X (gfx950) subsequence-DTW library.
+ *
+ * What it computes.  For a query X[1..M] (a read's normalised events) and a
+ * reference Y[1..N] (the expected current of a genome, forward strand
+ * followed by the reverse-complement strand), the sDTW cost
+ *
+ *     gamma(i,j) = |X[i] - Y[j]| + min(gamma(i-1,j), gamma(i-1,j-1), gamma(i,j-1))
+ *     gamma(0,j) = 0,  gamma(i,0) = +inf
+ *
+ * (section 2.3, Eq. 1 and its boundary conditions: free start and free end
+ * in the reference, Manhattan distance), and returns per read
+ *
+ *     cost = min_j gamma(M,j)     end = (first j attaining it) - 1   (0-based)
+ *
+ * which is the (score, position) pair that Algorithms 1 and 2 return
+ * (sections 2.3 and 4.3); the start position / warp path is not computed,
+ * as in section 4.3 ("cost matrix memory optimization").
+ *
+ * Number formats.  SDTW_I16: int16 inputs (the fixed-point scaling of
+ * section 4.1 / section 4.3), exact 32-bit accumulation, int32 costs in
+ * input units.  SDTW_F32: float32 inputs, each cell rounded as
+ * fl(|fl(x - y)| + min(...)), float32 costs.  Results never depend on launch
+ * configuration, batch composition or tiling: they are bit-identical to a
+ * sequential evaluation of Eq. 1 in the same number format.
+ *
+ * Conventions.
+ *   - Every call returns an sdtw_status.  On a non-OK return nothing was
+ *     launched and no output was written; sdtw_last_error() gives a message
+ *     (thread-local, valid until the next call on the same thread).
+ *   - "*_dev" pointers are device memory owned by the caller (for example
+ *     torch tensors).  They must stay valid until the enqueued work on
+ *     `stream` has completed.  "*_host" pointers are host memory read
+ *     synchronously before the call returns.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Every
+ *     call that launches work is asynchronous on that stream.
+ *   - Device faults surface as SDTW_EDEVICE from the call that observes them.
+ *   - Objects (sdtw_ref, sdtw_plan, sdtw_stream) belong to the device that
+ *     was current when they were created; use them with that device current.
+ */
+#ifndef SDTW_H
+#define SDTW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sdtw_ref_s* sdtw_ref;       /* device copy of a reference signal */
+typedef struct sdtw_plan_s* sdtw_plan;     /* validated, scheduled batch layout */
+typedef struct sdtw_stream_s* sdtw_stream; /* one read extended chunk by chunk  */
+
+enum sdtw_dtype {
+  SDTW_F32 = 0, /* float32 inputs, float32 costs                     */
+  SDTW_I16 = 1  /* int16 inputs, 32-bit accumulation, int32 costs    */
+};
+
+enum sdtw_status {
+  SDTW_OK = 0,
+  SDTW_EINVAL = 1,  /* bad argument (null pointer, size, dtype, ...)      */
+  SDTW_ENOMEM = 2,  /* device allocation failed                           */
+  SDTW_EBUDGET = 3, /* resident-row pool budget exhausted                 */
+  SDTW_EDEVICE = 4, /* HIP runtime / kernel error                         */
+  SDTW_ESTATE = 5   /* object in the wrong state (closed, still in use)   */
+};
+
+/* Largest query length accepted by sdtw_plan_create (rows per read). */
+#define SDTW_MAX_QUERY 4096
+
+/* Message for the last non-OK status returned on this thread. */
+const char* sdtw_last_error(void);
+
+/* Library ABI version (increments on incompatible changes). */
+int sdtw_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Preparation (section 4.1; section 2.2 k-mer model)                        */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Reference preparation, once per reference (section 4.1: the k-mer model
+ * turns the base reference into a synthetic signal for the forward and the
+ * reverse strand, which is z-score normalised and scaled to fixed point;
+ * section 2.2: a window of k bases slides over the sequence and each k-mer is
+ * looked up in the model).
+ *
+ *   genome_dev  uint8[L], bases coded A=0 C=1 G=2 T=3 (the low two bits of
+ *               each byte are used; other bits are ignored, not checked).
+ *   L           genome length, L >= k.
+ *   table_dev   float32[4^k] expected current per k-mer; k-mer index is
+ *               sum_m b[m] 4^(k-1-m), first base most significant.
+ *   k           1 <= k <= 12.
+ *   scale       fixed-point scaling factor (> 0), e.g. 64.
+ *   z_dev       out float32[2(L-k+1)]: forward strand k-mers 0..L-k, then
+ *               the reverse-complement strand read 5'->3', jointly z-scored
+ *               (mean and population standard deviation of the whole
+ *               concatenation, accumulated in double; sd == 0 gives zeros).
+ *   codes_dev   out int16[2(L-k+1)] or NULL: saturate(rint(z * scale)), the
+ *               product and rounding in double, round-half-even.
+ *   nsat_dev    out int64[1] or NULL: number of saturated codes.
+ */
+int sdtw_prepare_reference(const uint8_t* genome_dev, int64_t L,
+                           const float* table_dev, int k, double scale,
+                           float* z_dev, int16_t* codes_dev, int64_t* nsat_dev,
+                           void* stream);
+
+/*
+ * Query preparation, per read (section 4.1: each read's events are
+ * normalised and scaled with the same factor as the reference).
+ *
+ *   raw_dev       float32 events of all reads, concatenated (CSR).
+ *   offsets_dev   int64[nq+1] on the device, read r is
+ *                 raw[offsets[r] .. offsets[r+1]).  A read whose end is not
+ *                 after its start is empty and produces nothing (the offsets
+ *                 are not otherwise checked: they must lie inside raw/z).
+ *   nq            >= 1.
+ *   z_dev         out float32, same layout: (v - mean_r) / sd_r with the
+ *                 read's own mean and population sd, both accumulated in
+ *                 double in index order (sd == 0 gives zeros).
+ *   codes_dev     out int16 or NULL: saturate(rint(z * scale)) as above.
+ *   nsat_dev      out int64[1] or NULL: number of saturated codes (all reads).
+ */
+int sdtw_prepare_queries(const float* raw_dev, const int64_t* offsets_dev,
+                         int32_t nq, double scale, float* z_dev,
+                         int16_t* codes_dev, int64_t* nsat_dev, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Reference handle                                                          */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Copy a prepared reference signal into library-owned device memory, laid
+ * out for the alignment kernels (section 4.3 keeps the reference resident
+ * and streams it past the processing elements; here it stays in HBM).
+ *
+ *   ref        int16[n] (SDTW_I16) or float32[n] (SDTW_F32) values.
+ *   ref_is_device  1 if `ref` is device memory, 0 if host memory.
+ *   n          >= 1.  Float values must be finite (checked; EINVAL).
+ *   out        receives the handle.  The call synchronises `stream`; the
+ *              caller may free `ref` when it returns.
+ */
+int sdtw_load_reference(const void* ref, int64_t n, int dtype,
+                        int ref_is_device, void* stream, sdtw_ref* out);
+
+/* Length and dtype of a loaded reference. */
+int sdtw_reference_info(sdtw_ref ref, int64_t* n, int* dtype);
+
+/* Release a reference.  ESTATE while streams opened on it are still open. */
+int sdtw_free_reference(sdtw_ref ref);
+
+/* ------------------------------------------------------------------------ */
+/* Batched alignment (sections 2.3 / 4.3; many query processors, section 7)  */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Validate and schedule a batch layout once; reuse it for every batch with
+ * the same read lengths.  Reads are ordered longest first and pulled by a
+ * persistent grid; reads shorter than 64 rows go to the one-wave kernel.
+ *
+ *   offsets_host  int64[nq+1] CSR offsets of the query values, read r is
+ *                 q[offsets[r] .. offsets[r+1]); every read 1 <= M <=
+ *                 SDTW_MAX_QUERY (EINVAL otherwise).
+ *   nq            >= 1.
+ *   dtype         SDTW_F32 or SDTW_I16 (the query dtype of later calls).
+ *   out           receives the plan (device memory is allocated here).
+ */
+int sdtw_plan_create(const int64_t* offsets_host, int32_t nq, int dtype,
+                     sdtw_plan* out);
+
+/* Number of reads and dtype of a plan. */
+int sdtw_plan_info(sdtw_plan plan, int32_t* nq, int* dtype, int32_t* max_m);
+
+/*
+ * Override the kernel configuration chosen for a plan (autotuning).
+ *   strip  columns per lane: 8, 16 or 32 (0 = keep).
+ *   waves_per_cu  resident waves per compute unit for the persistent grid,
+ *                 1..32 (0 = keep).
+ */
+int sdtw_plan_set_config(sdtw_plan plan, int strip, int waves_per_cu);
+int sdtw_plan_get_config(sdtw_plan plan, int* strip, int* waves_per_cu);
+
+/* Release a plan (synchronise the streams that used it first). */
+int sdtw_plan_destroy(sdtw_plan plan);
+
+/*
+ * Align every read of the plan against the reference.
+ *
+ *   q_dev     query values in the plan's layout: int16 (SDTW_I16) or float32
+ *             (SDTW_F32); the plan's dtype must equal the reference's.
+ *   cost_dev  out int32[nq] (SDTW_I16) or float32[nq] (SDTW_F32).
+ *   end_dev   out int32[nq], 0-based end column in the reference.
+ *
+ * Only kernels are enqueued (no allocation, no host synchronisation), so the
+ * call may be captured in a hipGraph.  Two calls with the same plan must not
+ * overlap in time (the plan holds the work counter).
+ */
+int sdtw_align_batch(sdtw_ref ref, sdtw_plan plan, const void* q_dev,
+                     void* cost_dev, int32_t* end_dev, void* stream);
+
+/*
+ * One read per launch with the single-wave kernel (the plain baseline the
+ * batched engine is measured against).  Same semantics as a one-read batch.
+ *   q_dev  M values; 1 <= M <= SDTW_MAX_QUERY.
+ */
+int sdtw_align_one(sdtw_ref ref, const void* q_dev, int32_t M, void* cost_dev,
+                   int32_t* end_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SDTW_H */

@@ -1,0 +1,14 @@
+"""MI355X (gfx950) subsequence DTW for signal-level Read Until.
+
+Python binding of the C ABI in ``include/sdtw.h`` (``libsdtw.so``, built by
+``__graft_entry__.build()`` or ``python paper_2211_07340_amd/build.py``).
+This module only marshals arguments: every step runs in the HIP library.
+Device memory and streams come from PyTorch (``torch.cuda``).
+"""
+from .binding import (F32, I16, Plan, Reference, SdtwError, align_batch, align_one,
+                      library_path, load_library, prepare_queries, prepare_reference,
+                      version)
+
+__all__ = ["F32", "I16", "Plan", "Reference", "SdtwError", "align_batch", "align_one",
+           "library_path", "load_library", "prepare_queries", "prepare_reference",
+           "version"]

@@ -1,0 +1,257 @@
+"""ctypes binding of libsdtw.so: same names as the C ABI, argument marshalling only.
+
+Tensors are torch tensors; device pointers are ``tensor.data_ptr()`` and the
+stream is ``torch.cuda.current_stream().cuda_stream`` unless one is given.
+If the library is missing every call raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+F32, I16 = 0, 1
+_STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EBUDGET", 4: "EDEVICE", 5: "ESTATE"}
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libsdtw.so")
+_lib = None
+
+
+class SdtwError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        self.code = _STATUS.get(status, str(status))
+        super().__init__(f"{self.code}: {message}")
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Load libsdtw.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950)")
+    lib = C.CDLL(_LIB_PATH)
+    p, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "sdtw_last_error": ([], C.c_char_p),
+        "sdtw_version": ([], C.c_int),
+        "sdtw_prepare_reference": ([p, i64, p, C.c_int, dbl, p, p, p, p], C.c_int),
+        "sdtw_prepare_queries": ([p, p, i32, dbl, p, p, p, p], C.c_int),
+        "sdtw_load_reference": ([p, i64, C.c_int, C.c_int, p, C.POINTER(p)], C.c_int),
+        "sdtw_reference_info": ([p, C.POINTER(i64), C.POINTER(C.c_int)], C.c_int),
+        "sdtw_free_reference": ([p], C.c_int),
+        "sdtw_plan_create": ([p, i32, C.c_int, C.POINTER(p)], C.c_int),
+        "sdtw_plan_info": ([p, C.POINTER(i32), C.POINTER(C.c_int), C.POINTER(i32)], C.c_int),
+        "sdtw_plan_set_config": ([p, C.c_int, C.c_int], C.c_int),
+        "sdtw_plan_get_config": ([p, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
+        "sdtw_plan_destroy": ([p], C.c_int),
+        "sdtw_align_batch": ([p, p, p, p, p, p], C.c_int),
+        "sdtw_align_one": ([p, p, i32, p, p, p], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        msg = load_library().sdtw_last_error().decode(errors="replace")
+        raise SdtwError(status, msg)
+
+
+def version() -> int:
+    return load_library().sdtw_version()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(stream if isinstance(stream, int) else stream.cuda_stream)
+    return C.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype=None, name="tensor"):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _offsets_host(offsets) -> np.ndarray:
+    if hasattr(offsets, "detach"):
+        offsets = offsets.detach().cpu().numpy()
+    return np.ascontiguousarray(offsets, dtype=np.int64)
+
+
+# ---------------------------------------------------------------------------
+# preparation
+# ---------------------------------------------------------------------------
+
+def prepare_reference(genome, table, k: int = 6, scale: float = 64.0, stream=None):
+    """Section 4.1 reference preparation on the device.
+
+    genome: uint8 device tensor (A=0 C=1 G=2 T=3); table: float32 [4**k].
+    Returns (z float32[2(L-k+1)], codes int16[...], nsat int64[1]) device tensors.
+    """
+    torch = _torch()
+    lib = load_library()
+    L = genome.numel()
+    n = 2 * (L - k + 1)
+    if n < 2:
+        raise ValueError("genome shorter than k")
+    z = torch.empty(n, dtype=torch.float32, device=genome.device)
+    codes = torch.empty(n, dtype=torch.int16, device=genome.device)
+    nsat = torch.empty(1, dtype=torch.int64, device=genome.device)
+    _check(lib.sdtw_prepare_reference(_dev(genome, torch.uint8, "genome"), L,
+                                      _dev(table, torch.float32, "table"), int(k), float(scale),
+                                      _dev(z), _dev(codes), _dev(nsat), _stream(stream)))
+    return z, codes, nsat
+
+
+def prepare_queries(raw, offsets, scale: float = 64.0, stream=None):
+    """Section 4.1 per-read normalisation and scaling on the device.
+
+    raw: float32 device tensor (CSR values); offsets: int64 device tensor [nq+1].
+    Returns (z float32, codes int16, nsat int64[1]) device tensors.
+    """
+    torch = _torch()
+    lib = load_library()
+    nq = offsets.numel() - 1
+    z = torch.empty_like(raw)
+    codes = torch.empty(raw.numel(), dtype=torch.int16, device=raw.device)
+    nsat = torch.empty(1, dtype=torch.int64, device=raw.device)
+    _check(lib.sdtw_prepare_queries(_dev(raw, torch.float32, "raw"),
+                                    _dev(offsets, torch.int64, "offsets"), nq, float(scale),
+                                    _dev(z), _dev(codes), _dev(nsat), _stream(stream)))
+    return z, codes, nsat
+
+
+# ---------------------------------------------------------------------------
+# reference and plans
+# ---------------------------------------------------------------------------
+
+class Reference:
+    """Device copy of a prepared reference signal (sdtw_load_reference)."""
+
+    def __init__(self, values, stream=None):
+        torch = _torch()
+        lib = load_library()
+        if values.dtype == torch.int16:
+            self.dtype = I16
+        elif values.dtype == torch.float32:
+            self.dtype = F32
+        else:
+            raise ValueError("reference must be int16 or float32")
+        values = values.contiguous()
+        self.n = values.numel()
+        h = C.c_void_p()
+        _check(lib.sdtw_load_reference(C.c_void_p(values.data_ptr()), self.n, self.dtype,
+                                       1 if values.is_cuda else 0, _stream(stream),
+                                       C.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise SdtwError(5, "reference is closed")
+        return self._h
+
+    def close(self):
+        if self._h is not None:
+            _check(load_library().sdtw_free_reference(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """Validated, longest-first batch layout (sdtw_plan_create)."""
+
+    def __init__(self, offsets, dtype: int):
+        lib = load_library()
+        offs = _offsets_host(offsets)
+        self.offsets = offs
+        self.nq = offs.size - 1
+        self.dtype = dtype
+        h = C.c_void_p()
+        _check(lib.sdtw_plan_create(offs.ctypes.data_as(C.c_void_p), self.nq, dtype,
+                                    C.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise SdtwError(5, "plan is closed")
+        return self._h
+
+    def set_config(self, strip: int = 0, waves_per_cu: int = 0):
+        _check(load_library().sdtw_plan_set_config(self.handle, strip, waves_per_cu))
+
+    @property
+    def config(self):
+        s, w = C.c_int(), C.c_int()
+        _check(load_library().sdtw_plan_get_config(self.handle, C.byref(s), C.byref(w)))
+        return s.value, w.value
+
+    def close(self):
+        if self._h is not None:
+            _check(load_library().sdtw_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _outputs(nq, dtype, device, cost, end):
+    torch = _torch()
+    if cost is None:
+        cost = torch.empty(nq, dtype=torch.int32 if dtype == I16 else torch.float32,
+                           device=device)
+    if end is None:
+        end = torch.empty(nq, dtype=torch.int32, device=device)
+    return cost, end
+
+
+def align_batch(ref: Reference, plan: Plan, q, cost=None, end=None, stream=None):
+    """sdtw_align_batch: returns (cost, end) device tensors (int32/float32, int32)."""
+    torch = _torch()
+    qdt = torch.int16 if plan.dtype == I16 else torch.float32
+    cost, end = _outputs(plan.nq, plan.dtype, q.device, cost, end)
+    _check(load_library().sdtw_align_batch(ref.handle, plan.handle, _dev(q, qdt, "q"),
+                                           _dev(cost), _dev(end, torch.int32, "end"),
+                                           _stream(stream)))
+    return cost, end
+
+
+def align_one(ref: Reference, q, cost=None, end=None, stream=None):
+    """sdtw_align_one (single-wave kernel, one read per launch)."""
+    torch = _torch()
+    qdt = torch.int16 if ref.dtype == I16 else torch.float32
+    cost, end = _outputs(1, ref.dtype, q.device, cost, end)
+    _check(load_library().sdtw_align_one(ref.handle, _dev(q, qdt, "q"), q.numel(), _dev(cost),
+                                         _dev(end, torch.int32, "end"), _stream(stream)))
+    return cost, end

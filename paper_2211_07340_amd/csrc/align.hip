@@ -1,0 +1,452 @@
+// sDTW alignment kernels for gfx950 (section 2.3 Eq. 1; section 4.3).
+//
+// Work decomposition.  One wave64 aligns one read.  The reference is cut
+// into tiles of T = 64*W columns; lane l owns the strip of W consecutive
+// columns [l*W, l*W + W) of the current tile and keeps the reference values
+// y[W] and the previous row gamma(i-1, strip) in registers.  The query sits
+// in LDS.  Rows advance one per step; lane l works one row behind lane l-1
+// (the oblique, anti-diagonal front of section 4.3 "operation pipelining",
+// here across lanes), so the value a lane needs from its left neighbour,
+// gamma(i, j0-1), is that neighbour's last column computed one step earlier
+// and arrives by a DPP wave_shr:1 move.  The value received one step earlier
+// is the diagonal gamma(i-1, j0-1).  Lane 0 takes its left boundary from an
+// LDS column B[0..M) that lane 63 fills while sweeping the previous tile
+// (gamma(., j) depends on Y[1..j] only, so tiling is exact).
+//
+// Per cell: int16 path  v_min3_u32 + v_sad_u32          (2 VALU)
+//           fp32 path   v_sub_f32 + v_min3_u32 + v_add_f32 |.|  (3 VALU)
+// Costs travel as uint32 bit patterns in both formats: every DP value is a
+// sum of absolute differences (>= +0) or +inf, and IEEE encodings of
+// non-negative floats order like their values, so one unsigned min3 serves
+// both and never changes a result.
+//
+// The last row of every tile is folded into a per-lane running (cost, j)
+// minimum with strict '<' in increasing j, and a lexicographic wave
+// reduction gives the first column attaining the minimum (the strict-less
+// last-row scan of Algorithms 1 and 2).
+//
+// k_align_skew (M >= 64): continuous skew.  Lanes never wait for each other
+// at tile boundaries: lane l enters tile p at step p*M + l, so each period
+// of M steps starts with 64 "switch" steps in which exactly one lane swaps
+// its strip (masked LDS moves: new y from a staged copy of the tile, its
+// finished last row out, zeros in as gamma(0, .)).  The wave runs ntiles*M
+// + 64 steps for ntiles*T*M cells.  Reads are pulled longest-first from a
+// work list by a persistent grid.
+//
+// k_align_plain (any M >= 1): synchronised tiles; every tile costs M + 63
+// steps with lanes idle during fill and drain.  Used for reads shorter than
+// 64 rows and as the one-read-per-launch baseline.
+#include <limits.h>
+
+#include "common.h"
+
+namespace sdtw {
+namespace {
+
+struct FmtI16 {
+  using qin = int16_t;
+  using xlds = uint16_t;  // biased copy of the query in LDS
+  static constexpr uint32_t kInf = 0xFFFFFFFFu;
+  __device__ static __forceinline__ xlds to_lds(int16_t v) {
+    return (uint16_t)((int32_t)v + (int32_t)kI16Bias);
+  }
+  __device__ static __forceinline__ uint32_t cell(uint32_t x, uint32_t y, uint32_t m) {
+    const uint32_t d = x > y ? x - y : y - x;  // with the add: v_sad_u32
+    return d + m;
+  }
+  __device__ static __forceinline__ void store_cost(void* cost, int32_t r, uint32_t v) {
+    ((int32_t*)cost)[r] = (int32_t)v;
+  }
+};
+
+struct FmtF32 {
+  using qin = float;
+  using xlds = uint32_t;
+  static constexpr uint32_t kInf = 0x7F800000u;
+  __device__ static __forceinline__ xlds to_lds(float v) { return __float_as_uint(v); }
+  __device__ static __forceinline__ uint32_t cell(uint32_t x, uint32_t y, uint32_t m) {
+    return __float_as_uint(fabsf(__uint_as_float(x) - __uint_as_float(y)) + __uint_as_float(m));
+  }
+  __device__ static __forceinline__ void store_cost(void* cost, int32_t r, uint32_t v) {
+    ((float*)cost)[r] = __uint_as_float(v);
+  }
+};
+
+__device__ __forceinline__ uint32_t min3u(uint32_t a, uint32_t b, uint32_t c) {
+  return min(min(a, b), c);
+}
+
+// nw[w] = gamma(i, j0+w) from up[w] = gamma(i-1, j0+w), the diagonal
+// dprev = gamma(i-1, j0-1) and left = gamma(i, j0-1).
+template <class F, int W>
+__device__ __forceinline__ void strip_row(uint32_t x, const uint32_t (&y)[W],
+                                          const uint32_t (&up)[W], uint32_t (&nw)[W],
+                                          uint32_t dprev, uint32_t left) {
+  nw[0] = F::cell(x, y[0], min3u(up[0], dprev, left));
+#pragma unroll
+  for (int w = 1; w < W; ++w) nw[w] = F::cell(x, y[w], min3u(up[w], up[w - 1], nw[w - 1]));
+}
+
+// Lane l receives lane l-1's `v`; lane 0 keeps `lane0` (DPP wave_shr:1 with
+// bound_ctrl off leaves the destination of the source-less lane unchanged).
+__device__ __forceinline__ uint32_t from_left_lane(uint32_t v, uint32_t lane0) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)lane0, (int)v, 0x138, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ void wave_argmin(uint32_t& best, int32_t& bestj) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const uint32_t ob = (uint32_t)__shfl_xor((int)best, off);
+    const int32_t oj = __shfl_xor(bestj, off);
+    if (ob < best || (ob == best && oj < bestj)) {
+      best = ob;
+      bestj = oj;
+    }
+  }
+}
+
+template <int W>
+__device__ __forceinline__ void load_strip(uint32_t (&dst)[W], const uint32_t* __restrict__ src) {
+#pragma unroll
+  for (int w = 0; w < W; w += 4) {
+    const uint4 v = *(const uint4*)(src + w);
+    dst[w] = v.x;
+    dst[w + 1] = v.y;
+    dst[w + 2] = v.z;
+    dst[w + 3] = v.w;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Continuous-skew kernel
+// ---------------------------------------------------------------------------
+
+template <class F, int W>
+struct SkewLds {
+  static constexpr int kStage = 64 * W;  // per-lane strips: next tile / last rows
+  static constexpr int kZeros = W;
+  // query/boundary pairs: max_m + 64 entries of 8 bytes
+  static size_t bytes(int max_m) {
+    size_t b = 4 * ((size_t)kStage + kZeros) + 8 * ((size_t)max_m + 64);
+    return (b + 15) & ~(size_t)15;
+  }
+};
+
+// LDS layout of the query and the left-boundary column (one 8-byte entry
+// per k in [0, M + 64)):
+//   bx[k].x = query row (k - 63) mod M      (biased int16 or float bits)
+//   bx[k].y = boundary gamma(row k - 63, last column of the previous tile)
+//             for k in [63, M + 63)
+// Lane l reads its row r of the current period at entry 63 + r - l, so one
+// per-lane address serves all three accesses of a step: every lane's query
+// value, lane 0's boundary value (entry 63 + r holds row r), and lane 63's
+// boundary write of its row r - 63 (entry r, its own entry).  Rows M-63..M-1
+// of lane 63 (written in the first 63 steps of a period) land at r + M.
+template <class F, int W>
+__global__ __launch_bounds__(64) void k_align_skew(AlignArgs args) {
+  constexpr int T = 64 * W;
+  extern __shared__ __align__(16) uint32_t smem[];
+  const int lane = (int)threadIdx.x;
+  uint32_t* const stage = smem;
+  uint32_t* const zeros = stage + SkewLds<F, W>::kStage;
+  uint2* const bx = (uint2*)(zeros + SkewLds<F, W>::kZeros);
+  uint32_t* const my_stage = stage + lane * W;
+  uint2* const bxl = bx + 63 - lane;
+
+  if (lane < W) zeros[lane] = 0u;
+  const int32_t N = (int32_t)args.n;
+  const int32_t ntiles = (N + T - 1) / T;
+
+  for (;;) {
+    // Work pull without a divergent branch: every lane takes part in the
+    // atomic and only lane 0 adds 1, so lane 0's return value is the item
+    // whatever order the lanes are serviced in.  (Guarding the atomic with
+    // `if (lane == 0)` lets the loop structurizer split the wave around the
+    // readfirstlane below, leaving lanes 1..63 to re-read a stale item.)
+    int32_t item = atomicAdd(args.counter, lane == 0 ? 1 : 0);
+    item = __builtin_amdgcn_readfirstlane(item);
+    if (item >= args.nwork) break;
+    const int32_t rd = __builtin_amdgcn_readfirstlane(args.order ? args.order[item] : item);
+    const int64_t q0 = args.offs ? args.offs[rd] : 0;
+    const int32_t M = __builtin_amdgcn_readfirstlane(
+        args.offs ? (int32_t)(args.offs[rd + 1] - q0) : args.single_m);
+    const typename F::qin* __restrict__ qv = (const typename F::qin*)args.q + q0;
+
+    __syncthreads();  // previous read's LDS use is complete
+    for (int k = lane; k < M + 64; k += 64) {
+      int s = k - 63;
+      s = s < 0 ? s + M : (s >= M ? s - M : s);
+      bx[k] = make_uint2((uint32_t)F::to_lds(qv[s]), F::kInf);  // gamma(i, 0) = +inf
+    }
+    {
+      uint32_t t0[W];
+      load_strip<W>(t0, args.ref + lane * W);
+#pragma unroll
+      for (int w = 0; w < W; ++w) my_stage[w] = t0[w];
+    }
+    __syncthreads();
+
+    uint32_t y[W], a[W], b[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) y[w] = a[w] = b[w] = 0u;
+    uint32_t dprev = F::kInf;
+    uint32_t best = 0xFFFFFFFFu;
+    int32_t bestj = INT_MAX;
+
+    // lane `r` (r < 64) enters its next tile: strip values in, the finished
+    // last row of the previous tile out, gamma(0, .) = 0 in.
+    auto enter_tile = [&](int32_t r, uint32_t(&up)[W]) {
+      if (lane == r) {
+#pragma unroll
+        for (int w = 0; w < W; w += 4) {
+          const uint4 nv = *(const uint4*)(my_stage + w);
+          *(uint4*)(my_stage + w) = make_uint4(up[w], up[w + 1], up[w + 2], up[w + 3]);
+          const uint4 zv = *(const uint4*)(zeros + w);
+          y[w] = nv.x;
+          y[w + 1] = nv.y;
+          y[w + 2] = nv.z;
+          y[w + 3] = nv.w;
+          up[w] = zv.x;
+          up[w + 1] = zv.y;
+          up[w + 2] = zv.z;
+          up[w + 3] = zv.w;
+        }
+      }
+    };
+    // one row step: lane l computes row (r - l) mod M of its tile.  `wrap`:
+    // lane 63's row is in the previous period (entry r + M).  `sw`: lane r
+    // switches tiles in this step; its neighbour r+1 still needs its last-row
+    // edge, so the DPP read comes before the switch overwrites `up`.
+    auto step = [&](int32_t r, uint32_t(&up)[W], uint32_t(&nw)[W], bool write_b, bool wrap,
+                    bool sw) {
+      const uint2 e = bxl[r];
+      const uint32_t left = from_left_lane(up[W - 1], e.y);
+      if (sw) enter_tile(r, up);
+      strip_row<F, W>(e.x, y, up, nw, dprev, left);
+      dprev = left;
+      if (write_b && lane == 63) bxl[wrap ? r + M : r].y = nw[W - 1];
+    };
+
+    for (int32_t p = 0;; ++p) {
+      // phase A: the 64 switch steps
+      const bool first = (p == 0);
+      for (int32_t r = 0; r < 64; r += 2) {
+        step(r, a, b, !first, true, true);
+        step(r + 1, b, a, !first || r + 1 == 63, r + 1 != 63, true);
+      }
+      // every lane has finished tile p-1: fold its last row, stage tile p+1
+      if (p >= 1) {
+        const int32_t jb = (p - 1) * T + lane * W;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          const uint32_t v = my_stage[w];
+          if (jb + w < N && v < best) {
+            best = v;
+            bestj = jb + w;
+          }
+        }
+      }
+      if (p + 1 < ntiles) {
+        uint32_t t1[W];
+        load_strip<W>(t1, args.ref + (int64_t)(p + 1) * T + lane * W);
+#pragma unroll
+        for (int w = 0; w < W; ++w) my_stage[w] = t1[w];
+      }
+      if (p == ntiles) break;
+      // phase B: plain steps, four per iteration
+      int32_t r = 64;
+      for (; r + 3 < M; r += 4) {
+        step(r, a, b, true, false, false);
+        step(r + 1, b, a, true, false, false);
+        step(r + 2, a, b, true, false, false);
+        step(r + 3, b, a, true, false, false);
+      }
+      for (; r + 1 < M; r += 2) {
+        step(r, a, b, true, false, false);
+        step(r + 1, b, a, true, false, false);
+      }
+      if (r < M) {
+        step(r, a, b, true, false, false);
+#pragma unroll
+        for (int w = 0; w < W; ++w) a[w] = b[w];
+      }
+    }
+
+    wave_argmin(best, bestj);
+    if (lane == 0) {
+      F::store_cost(args.cost, rd, best);
+      args.end[rd] = bestj;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Synchronised-tile kernel (any M >= 1)
+// ---------------------------------------------------------------------------
+
+template <class F, int W>
+struct PlainLds {
+  static size_t bytes(int max_m) {
+    size_t b = 4 * ((size_t)64 * W + (size_t)max_m) + sizeof(typename F::xlds) * (size_t)max_m;
+    return (b + 15) & ~(size_t)15;
+  }
+};
+
+template <class F, int W>
+__global__ __launch_bounds__(64) void k_align_plain(AlignArgs args) {
+  constexpr int T = 64 * W;
+  using X = typename F::xlds;
+  extern __shared__ __align__(16) uint32_t smem[];
+  const int lane = (int)threadIdx.x;
+  const int32_t item = (int32_t)blockIdx.x;
+  if (item >= args.nwork) return;
+  uint32_t* const slot = smem;  // last-row strips
+  uint32_t* const B = slot + 64 * W;
+  X* const xs = (X*)(B + args.max_m);
+  uint32_t* const my_slot = slot + lane * W;
+
+  const int32_t rd = args.order ? args.order[item] : item;
+  const int64_t q0 = args.offs ? args.offs[rd] : 0;
+  const int32_t M = args.offs ? (int32_t)(args.offs[rd + 1] - q0) : args.single_m;
+  const typename F::qin* __restrict__ qv = (const typename F::qin*)args.q + q0;
+  for (int k = lane; k < M; k += 64) {
+    xs[k] = F::to_lds(qv[k]);
+    B[k] = F::kInf;
+  }
+  __syncthreads();
+
+  const int64_t N = args.n;
+  const int32_t ntiles = (int32_t)((N + T - 1) / T);
+  uint32_t best = 0xFFFFFFFFu;
+  int32_t bestj = INT_MAX;
+  for (int32_t t = 0; t < ntiles; ++t) {
+    uint32_t y[W], a[W], b[W];
+    load_strip<W>(y, args.ref + (int64_t)t * T + lane * W);
+#pragma unroll
+    for (int w = 0; w < W; ++w) a[w] = b[w] = 0u;
+    uint32_t dprev = F::kInf;
+    auto step = [&](int32_t s, const uint32_t(&up)[W], uint32_t(&nw)[W]) {
+      const uint32_t left = from_left_lane(up[W - 1], B[s < M ? s : M - 1]);
+      const int32_t i = s - lane;
+      if ((uint32_t)i < (uint32_t)M) {
+        strip_row<F, W>((uint32_t)xs[i], y, up, nw, dprev, left);
+        dprev = left;
+        if (lane == 63) B[i] = nw[W - 1];
+        if (i == M - 1) {
+#pragma unroll
+          for (int w = 0; w < W; ++w) my_slot[w] = nw[w];
+        }
+      }
+    };
+    for (int32_t s = 0; s < M + 63; s += 2) {
+      step(s, a, b);
+      step(s + 1, b, a);
+    }
+    __syncthreads();
+    const int32_t jb = t * T + lane * W;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const uint32_t v = my_slot[w];
+      if (jb + w < N && v < best) {
+        best = v;
+        bestj = jb + w;
+      }
+    }
+    __syncthreads();
+  }
+  wave_argmin(best, bestj);
+  if (lane == 0) {
+    F::store_cost(args.cost, rd, best);
+    args.end[rd] = bestj;
+  }
+}
+
+__global__ void k_reset_counter(int32_t* c) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
+}
+
+template <class F, int W>
+hipError_t launch_skew_t(int blocks, const AlignArgs& a, hipStream_t st) {
+  const size_t lds = SkewLds<F, W>::bytes(a.max_m);
+  hipError_t e = hipFuncSetAttribute((const void*)k_align_skew<F, W>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, a.counter);
+  hipLaunchKernelGGL((k_align_skew<F, W>), dim3(blocks), dim3(64), lds, st, a);
+  return hipGetLastError();
+}
+
+template <class F, int W>
+hipError_t launch_plain_t(const AlignArgs& a, hipStream_t st) {
+  const size_t lds = PlainLds<F, W>::bytes(a.max_m);
+  hipError_t e = hipFuncSetAttribute((const void*)k_align_plain<F, W>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_align_plain<F, W>), dim3(a.nwork), dim3(64), lds, st, a);
+  return hipGetLastError();
+}
+
+template <class F>
+hipError_t launch_skew_f(int strip, int blocks, const AlignArgs& a, hipStream_t st) {
+  switch (strip) {
+    case 8: return launch_skew_t<F, 8>(blocks, a, st);
+    case 16: return launch_skew_t<F, 16>(blocks, a, st);
+    case 32: return launch_skew_t<F, 32>(blocks, a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <class F>
+hipError_t launch_plain_f(int strip, const AlignArgs& a, hipStream_t st) {
+  switch (strip) {
+    case 8: return launch_plain_t<F, 8>(a, st);
+    case 16: return launch_plain_t<F, 16>(a, st);
+    case 32: return launch_plain_t<F, 32>(a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <class F>
+size_t skew_bytes_f(int strip, int max_m) {
+  switch (strip) {
+    case 8: return SkewLds<F, 8>::bytes(max_m);
+    case 16: return SkewLds<F, 16>::bytes(max_m);
+    case 32: return SkewLds<F, 32>::bytes(max_m);
+  }
+  return 0;
+}
+
+template <class F>
+size_t plain_bytes_f(int strip, int max_m) {
+  switch (strip) {
+    case 8: return PlainLds<F, 8>::bytes(max_m);
+    case 16: return PlainLds<F, 16>::bytes(max_m);
+    case 32: return PlainLds<F, 32>::bytes(max_m);
+  }
+  return 0;
+}
+
+}  // namespace
+
+hipError_t launch_align_skew(int dtype, int strip, int blocks, const AlignArgs& a,
+                             hipStream_t st) {
+  return dtype == SDTW_I16 ? launch_skew_f<FmtI16>(strip, blocks, a, st)
+                           : launch_skew_f<FmtF32>(strip, blocks, a, st);
+}
+
+hipError_t launch_align_plain(int dtype, int strip, const AlignArgs& a, hipStream_t st) {
+  return dtype == SDTW_I16 ? launch_plain_f<FmtI16>(strip, a, st)
+                           : launch_plain_f<FmtF32>(strip, a, st);
+}
+
+size_t skew_lds_bytes(int dtype, int strip, int max_m) {
+  return dtype == SDTW_I16 ? skew_bytes_f<FmtI16>(strip, max_m)
+                           : skew_bytes_f<FmtF32>(strip, max_m);
+}
+
+size_t plain_lds_bytes(int dtype, int strip, int max_m) {
+  return dtype == SDTW_I16 ? plain_bytes_f<FmtI16>(strip, max_m)
+                           : plain_bytes_f<FmtF32>(strip, max_m);
+}
+
+}  // namespace sdtw

@@ -1,0 +1,386 @@
+// C ABI of the sDTW library: validation, object lifetimes, scheduling.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "common.h"
+
+struct sdtw_ref_s {
+  int device;
+  int dtype;
+  int64_t n;       // true length
+  int64_t n_pad;   // device layout length
+  uint32_t* data;  // u32 biased int16 or float bits
+  int open_streams;
+};
+
+struct sdtw_plan_s {
+  int device;
+  int dtype;
+  int32_t nq;
+  int32_t max_m;
+  int32_t nbig, nsmall;      // reads with M >= 64 / M < 64
+  int32_t max_m_big, max_m_small;
+  int64_t* offs_dev;         // [nq+1]
+  int32_t* order_dev;        // [nq]: long reads longest first, then short reads
+  int32_t* counter_dev;      // [1]
+  int strip;                 // columns per lane
+  int waves_per_cu;          // persistent grid density
+  int cus;                   // compute units of the device
+};
+
+namespace sdtw {
+
+static thread_local char g_err[512] = "";
+
+int set_error(int status, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return status;
+}
+
+int check_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return SDTW_OK;
+  if (e == hipErrorOutOfMemory)
+    return set_error(SDTW_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+  return set_error(SDTW_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int max_lds_bytes() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 65536;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return 65536;
+  return v;
+}
+
+static int current_device() {
+  int d = -1;
+  if (hipGetDevice(&d) != hipSuccess) return -1;
+  return d;
+}
+
+static int cu_count() {
+  int dev = current_device(), v = 0;
+  if (dev < 0 || hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return v;
+}
+
+static bool valid_strip(int s) { return s == 8 || s == 16 || s == 32; }
+
+}  // namespace sdtw
+
+using namespace sdtw;
+
+#define SDTW_REQUIRE(cond, ...) \
+  do {                          \
+    if (!(cond)) return set_error(SDTW_EINVAL, __VA_ARGS__); \
+  } while (0)
+
+extern "C" {
+
+const char* sdtw_last_error(void) { return g_err; }
+
+int sdtw_version(void) { return 1; }
+
+// ---------------------------------------------------------------------------
+// preparation
+// ---------------------------------------------------------------------------
+
+int sdtw_prepare_reference(const uint8_t* genome_dev, int64_t L, const float* table_dev, int k,
+                           double scale, float* z_dev, int16_t* codes_dev, int64_t* nsat_dev,
+                           void* stream) {
+  SDTW_REQUIRE(genome_dev && table_dev && z_dev, "sdtw_prepare_reference: null pointer");
+  SDTW_REQUIRE(k >= 1 && k <= 12, "sdtw_prepare_reference: k=%d outside [1, 12]", k);
+  SDTW_REQUIRE(L >= k, "sdtw_prepare_reference: genome length %lld < k=%d", (long long)L, k);
+  SDTW_REQUIRE(L - k + 1 <= (int64_t)INT32_MAX / 2,
+               "sdtw_prepare_reference: genome too long (%lld bases)", (long long)L);
+  SDTW_REQUIRE(isfinite(scale) && scale > 0.0, "sdtw_prepare_reference: scale must be > 0");
+  hipStream_t st = (hipStream_t)stream;
+  double* scratch = nullptr;
+  int rc = check_hip(hipMallocAsync((void**)&scratch, kRefPartials * sizeof(double), st),
+                     "sdtw_prepare_reference: scratch");
+  if (rc) return rc;
+  rc = check_hip(launch_prepare_reference(genome_dev, L, table_dev, k, scale, z_dev, codes_dev,
+                                          nsat_dev, scratch, st),
+                 "sdtw_prepare_reference: launch");
+  hipError_t e = hipFreeAsync(scratch, st);
+  if (rc) return rc;
+  return check_hip(e, "sdtw_prepare_reference: free");
+}
+
+int sdtw_prepare_queries(const float* raw_dev, const int64_t* offsets_dev, int32_t nq,
+                         double scale, float* z_dev, int16_t* codes_dev, int64_t* nsat_dev,
+                         void* stream) {
+  SDTW_REQUIRE(raw_dev && offsets_dev && z_dev, "sdtw_prepare_queries: null pointer");
+  SDTW_REQUIRE(nq >= 1, "sdtw_prepare_queries: nq=%d < 1", nq);
+  SDTW_REQUIRE(isfinite(scale) && scale > 0.0, "sdtw_prepare_queries: scale must be > 0");
+  return check_hip(launch_prepare_queries(raw_dev, offsets_dev, nq, scale, z_dev, codes_dev,
+                                          nsat_dev, (hipStream_t)stream),
+                   "sdtw_prepare_queries: launch");
+}
+
+// ---------------------------------------------------------------------------
+// reference
+// ---------------------------------------------------------------------------
+
+int sdtw_load_reference(const void* ref, int64_t n, int dtype, int ref_is_device, void* stream,
+                        sdtw_ref* out) {
+  SDTW_REQUIRE(ref && out, "sdtw_load_reference: null pointer");
+  SDTW_REQUIRE(dtype == SDTW_F32 || dtype == SDTW_I16, "sdtw_load_reference: bad dtype %d", dtype);
+  SDTW_REQUIRE(n >= 1 && n <= (int64_t)INT32_MAX - 2 * kPadUnit,
+               "sdtw_load_reference: length %lld outside [1, 2^31)", (long long)n);
+  hipStream_t st = (hipStream_t)stream;
+  const size_t esz = dtype == SDTW_I16 ? 2 : 4;
+  const int64_t n_pad = padded_length(n);
+  uint32_t* data = nullptr;
+  void* tmp = nullptr;
+  int32_t* nonfinite = nullptr;
+  int32_t host_nonfinite = 0;
+  int rc = check_hip(hipMalloc((void**)&data, (size_t)n_pad * 4), "sdtw_load_reference: alloc");
+  if (!rc) rc = check_hip(hipMalloc((void**)&nonfinite, sizeof(int32_t)), "sdtw_load_reference: alloc");
+  if (!rc) rc = check_hip(hipMemcpyAsync(nonfinite, &host_nonfinite, sizeof(int32_t),
+                                         hipMemcpyHostToDevice, st), "sdtw_load_reference: copy");
+  const void* src = ref;
+  if (!rc && !ref_is_device) {
+    rc = check_hip(hipMalloc(&tmp, (size_t)n * esz), "sdtw_load_reference: alloc");
+    if (!rc) rc = check_hip(hipMemcpyAsync(tmp, ref, (size_t)n * esz, hipMemcpyHostToDevice, st),
+                            "sdtw_load_reference: copy");
+    src = tmp;
+  }
+  if (!rc) rc = check_hip(launch_layout_reference(src, n, dtype, data, n_pad, nonfinite, st),
+                          "sdtw_load_reference: layout");
+  if (!rc) rc = check_hip(hipMemcpyAsync(&host_nonfinite, nonfinite, sizeof(int32_t),
+                                         hipMemcpyDeviceToHost, st), "sdtw_load_reference: copy");
+  if (!rc) rc = check_hip(hipStreamSynchronize(st), "sdtw_load_reference: sync");
+  if (tmp) (void)hipFree(tmp);
+  if (nonfinite) (void)hipFree(nonfinite);
+  if (!rc && host_nonfinite)
+    rc = set_error(SDTW_EINVAL, "sdtw_load_reference: %d non-finite values", host_nonfinite);
+  if (rc) {
+    if (data) (void)hipFree(data);
+    return rc;
+  }
+  sdtw_ref_s* r = new (std::nothrow) sdtw_ref_s;
+  if (!r) {
+    (void)hipFree(data);
+    return set_error(SDTW_ENOMEM, "sdtw_load_reference: host allocation");
+  }
+  r->device = current_device();
+  r->dtype = dtype;
+  r->n = n;
+  r->n_pad = n_pad;
+  r->data = data;
+  r->open_streams = 0;
+  *out = r;
+  return SDTW_OK;
+}
+
+int sdtw_reference_info(sdtw_ref ref, int64_t* n, int* dtype) {
+  SDTW_REQUIRE(ref, "sdtw_reference_info: null reference");
+  if (n) *n = ref->n;
+  if (dtype) *dtype = ref->dtype;
+  return SDTW_OK;
+}
+
+int sdtw_free_reference(sdtw_ref ref) {
+  SDTW_REQUIRE(ref, "sdtw_free_reference: null reference");
+  if (ref->open_streams > 0)
+    return set_error(SDTW_ESTATE, "sdtw_free_reference: %d streams still open", ref->open_streams);
+  int rc = check_hip(hipFree(ref->data), "sdtw_free_reference");
+  delete ref;
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
+// plans
+// ---------------------------------------------------------------------------
+
+static void choose_config(sdtw_plan_s* p) {
+  p->strip = 16;
+  // resident waves per CU: limited by LDS (the CU holds 160 KiB) and capped
+  // at 16 (four per SIMD), enough to hide LDS and DPP latency
+  const size_t per = skew_lds_bytes(p->dtype, p->strip, std::max(p->max_m_big, 64));
+  int w = (int)std::min<size_t>(16, (160 * 1024) / std::max<size_t>(per, 1));
+  p->waves_per_cu = std::max(w, 1);
+}
+
+int sdtw_plan_create(const int64_t* offsets_host, int32_t nq, int dtype, sdtw_plan* out) {
+  SDTW_REQUIRE(offsets_host && out, "sdtw_plan_create: null pointer");
+  SDTW_REQUIRE(nq >= 1, "sdtw_plan_create: nq=%d < 1", nq);
+  SDTW_REQUIRE(dtype == SDTW_F32 || dtype == SDTW_I16, "sdtw_plan_create: bad dtype %d", dtype);
+  SDTW_REQUIRE(offsets_host[0] >= 0, "sdtw_plan_create: negative offset");
+  std::vector<int32_t> big, small;
+  int32_t max_big = 0, max_small = 0;
+  for (int32_t r = 0; r < nq; ++r) {
+    const int64_t m = offsets_host[r + 1] - offsets_host[r];
+    SDTW_REQUIRE(m >= 1 && m <= SDTW_MAX_QUERY,
+                 "sdtw_plan_create: read %d has length %lld outside [1, %d]", r, (long long)m,
+                 SDTW_MAX_QUERY);
+    if (m >= 64) {
+      big.push_back(r);
+      max_big = std::max<int32_t>(max_big, (int32_t)m);
+    } else {
+      small.push_back(r);
+      max_small = std::max<int32_t>(max_small, (int32_t)m);
+    }
+  }
+  auto longer = [&](int32_t a, int32_t b) {
+    const int64_t ma = offsets_host[a + 1] - offsets_host[a];
+    const int64_t mb = offsets_host[b + 1] - offsets_host[b];
+    return ma != mb ? ma > mb : a < b;
+  };
+  std::sort(big.begin(), big.end(), longer);
+  std::sort(small.begin(), small.end(), longer);
+  std::vector<int32_t> order(big);
+  order.insert(order.end(), small.begin(), small.end());
+
+  sdtw_plan_s* p = new (std::nothrow) sdtw_plan_s();
+  if (!p) return set_error(SDTW_ENOMEM, "sdtw_plan_create: host allocation");
+  p->device = current_device();
+  p->dtype = dtype;
+  p->nq = nq;
+  p->nbig = (int32_t)big.size();
+  p->nsmall = (int32_t)small.size();
+  p->max_m_big = max_big;
+  p->max_m_small = max_small;
+  p->max_m = std::max(max_big, max_small);
+  p->cus = cu_count();
+  if (p->cus <= 0) p->cus = 256;
+  choose_config(p);
+  int rc = check_hip(hipMalloc((void**)&p->offs_dev, sizeof(int64_t) * (size_t)(nq + 1)),
+                     "sdtw_plan_create: alloc");
+  if (!rc) rc = check_hip(hipMalloc((void**)&p->order_dev, sizeof(int32_t) * (size_t)nq),
+                          "sdtw_plan_create: alloc");
+  if (!rc) rc = check_hip(hipMalloc((void**)&p->counter_dev, sizeof(int32_t)),
+                          "sdtw_plan_create: alloc");
+  if (!rc) rc = check_hip(hipMemcpy(p->offs_dev, offsets_host, sizeof(int64_t) * (size_t)(nq + 1),
+                                    hipMemcpyHostToDevice), "sdtw_plan_create: copy");
+  if (!rc) rc = check_hip(hipMemcpy(p->order_dev, order.data(), sizeof(int32_t) * (size_t)nq,
+                                    hipMemcpyHostToDevice), "sdtw_plan_create: copy");
+  if (rc) {
+    (void)hipFree(p->offs_dev);
+    (void)hipFree(p->order_dev);
+    (void)hipFree(p->counter_dev);
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return SDTW_OK;
+}
+
+int sdtw_plan_info(sdtw_plan plan, int32_t* nq, int* dtype, int32_t* max_m) {
+  SDTW_REQUIRE(plan, "sdtw_plan_info: null plan");
+  if (nq) *nq = plan->nq;
+  if (dtype) *dtype = plan->dtype;
+  if (max_m) *max_m = plan->max_m;
+  return SDTW_OK;
+}
+
+int sdtw_plan_set_config(sdtw_plan plan, int strip, int waves_per_cu) {
+  SDTW_REQUIRE(plan, "sdtw_plan_set_config: null plan");
+  SDTW_REQUIRE(strip == 0 || valid_strip(strip), "sdtw_plan_set_config: strip %d not in {8,16,32}",
+               strip);
+  SDTW_REQUIRE(waves_per_cu >= 0 && waves_per_cu <= 32,
+               "sdtw_plan_set_config: waves_per_cu %d outside [0, 32]", waves_per_cu);
+  if (strip) plan->strip = strip;
+  if (waves_per_cu) plan->waves_per_cu = waves_per_cu;
+  return SDTW_OK;
+}
+
+int sdtw_plan_get_config(sdtw_plan plan, int* strip, int* waves_per_cu) {
+  SDTW_REQUIRE(plan, "sdtw_plan_get_config: null plan");
+  if (strip) *strip = plan->strip;
+  if (waves_per_cu) *waves_per_cu = plan->waves_per_cu;
+  return SDTW_OK;
+}
+
+int sdtw_plan_destroy(sdtw_plan plan) {
+  SDTW_REQUIRE(plan, "sdtw_plan_destroy: null plan");
+  hipError_t e1 = hipFree(plan->offs_dev);
+  hipError_t e2 = hipFree(plan->order_dev);
+  hipError_t e3 = hipFree(plan->counter_dev);
+  delete plan;
+  if (e1 != hipSuccess) return check_hip(e1, "sdtw_plan_destroy");
+  if (e2 != hipSuccess) return check_hip(e2, "sdtw_plan_destroy");
+  return check_hip(e3, "sdtw_plan_destroy");
+}
+
+// ---------------------------------------------------------------------------
+// alignment
+// ---------------------------------------------------------------------------
+
+int sdtw_align_batch(sdtw_ref ref, sdtw_plan plan, const void* q_dev, void* cost_dev,
+                     int32_t* end_dev, void* stream) {
+  SDTW_REQUIRE(ref && plan, "sdtw_align_batch: null reference or plan");
+  SDTW_REQUIRE(q_dev && cost_dev && end_dev, "sdtw_align_batch: null device pointer");
+  SDTW_REQUIRE(ref->dtype == plan->dtype, "sdtw_align_batch: reference dtype %d != plan dtype %d",
+               ref->dtype, plan->dtype);
+  SDTW_REQUIRE(valid_strip(plan->strip), "sdtw_align_batch: bad strip");
+  const size_t lds_big = plan->nbig ? skew_lds_bytes(plan->dtype, plan->strip, plan->max_m_big) : 0;
+  const size_t lds_small =
+      plan->nsmall ? plain_lds_bytes(plan->dtype, plan->strip, plan->max_m_small) : 0;
+  const size_t lds_max = (size_t)max_lds_bytes();
+  SDTW_REQUIRE(lds_big <= lds_max && lds_small <= lds_max,
+               "sdtw_align_batch: %zu bytes of LDS needed, %zu available",
+               std::max(lds_big, lds_small), lds_max);
+  hipStream_t st = (hipStream_t)stream;
+  AlignArgs a{};
+  a.ref = ref->data;
+  a.n = ref->n;
+  a.q = q_dev;
+  a.offs = plan->offs_dev;
+  a.counter = plan->counter_dev;
+  a.cost = cost_dev;
+  a.end = end_dev;
+  if (plan->nbig) {
+    a.order = plan->order_dev;
+    a.nwork = plan->nbig;
+    a.max_m = plan->max_m_big;
+    const int blocks = std::min<int64_t>((int64_t)plan->cus * plan->waves_per_cu, plan->nbig);
+    int rc = check_hip(launch_align_skew(plan->dtype, plan->strip, blocks, a, st),
+                       "sdtw_align_batch: launch");
+    if (rc) return rc;
+  }
+  if (plan->nsmall) {
+    a.order = plan->order_dev + plan->nbig;
+    a.nwork = plan->nsmall;
+    a.max_m = plan->max_m_small;
+    int rc = check_hip(launch_align_plain(plan->dtype, plan->strip, a, st),
+                       "sdtw_align_batch: launch");
+    if (rc) return rc;
+  }
+  return SDTW_OK;
+}
+
+int sdtw_align_one(sdtw_ref ref, const void* q_dev, int32_t M, void* cost_dev, int32_t* end_dev,
+                   void* stream) {
+  SDTW_REQUIRE(ref, "sdtw_align_one: null reference");
+  SDTW_REQUIRE(q_dev && cost_dev && end_dev, "sdtw_align_one: null device pointer");
+  SDTW_REQUIRE(M >= 1 && M <= SDTW_MAX_QUERY, "sdtw_align_one: M=%d outside [1, %d]", M,
+               SDTW_MAX_QUERY);
+  AlignArgs a{};
+  a.ref = ref->data;
+  a.n = ref->n;
+  a.q = q_dev;
+  a.offs = nullptr;
+  a.order = nullptr;
+  a.nwork = 1;
+  a.max_m = M;
+  a.single_m = M;
+  a.cost = cost_dev;
+  a.end = end_dev;
+  return check_hip(launch_align_plain(ref->dtype, 16, a, (hipStream_t)stream),
+                   "sdtw_align_one: launch");
+}
+
+}  // extern "C"

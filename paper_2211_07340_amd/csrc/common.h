@@ -1,0 +1,62 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sdtw.h"
+
+namespace sdtw {
+
+// Status plumbing: every C entry point reports through set_error().
+int set_error(int status, const char* fmt, ...);
+int check_hip(hipError_t e, const char* what);
+
+// Width of the widest column strip a kernel uses (64 lanes x 32 columns); the
+// device copy of a reference is padded to a multiple of it plus one strip.
+constexpr int kLanes = 64;
+constexpr int kMaxStrip = 32;
+constexpr int64_t kPadUnit = int64_t(kLanes) * kMaxStrip;
+
+// Offset that maps int16 onto [0, 65535]; |x - y| is translation invariant.
+constexpr uint32_t kI16Bias = 32768u;
+
+inline int64_t padded_length(int64_t n) {
+  return ((n + kPadUnit - 1) / kPadUnit) * kPadUnit + kPadUnit;
+}
+
+// ---- launchers (prep.hip) ---------------------------------------------------
+hipError_t launch_prepare_reference(const uint8_t* g, int64_t L, const float* table,
+                                    int k, double scale, float* z, int16_t* codes,
+                                    int64_t* nsat, double* scratch, hipStream_t st);
+constexpr int kRefPartials = 512;  // doubles of scratch: partials + 2 stats
+hipError_t launch_prepare_queries(const float* raw, const int64_t* offs, int32_t nq,
+                                  double scale, float* z, int16_t* codes,
+                                  int64_t* nsat, hipStream_t st);
+hipError_t launch_layout_reference(const void* src, int64_t n, int dtype,
+                                   uint32_t* dst, int64_t n_pad, int32_t* nonfinite,
+                                   hipStream_t st);
+
+// ---- launchers (align.hip) --------------------------------------------------
+struct AlignArgs {
+  const uint32_t* ref;   // padded device layout (u32 biased int16, or f32 bits)
+  int64_t n;             // true reference length
+  const void* q;         // query values (int16 or float)
+  const int64_t* offs;   // CSR offsets [nq+1]
+  const int32_t* order;  // work list: read indices
+  int32_t nwork;         // entries in the work list
+  int32_t max_m;         // longest read in the work list (LDS sizing)
+  int32_t* counter;      // persistent work counter (device, reset by launcher)
+  void* cost;            // int32[nq] or float[nq]
+  int32_t* end;          // int32[nq]
+  int32_t single_m;      // used when offs == nullptr: one read of this length
+};
+// Continuous-skew persistent kernel; every read in the list must have M >= 64.
+hipError_t launch_align_skew(int dtype, int strip, int blocks, const AlignArgs& a,
+                             hipStream_t st);
+// Synchronised-tile single-wave kernel; any M >= 1; one block per work item.
+hipError_t launch_align_plain(int dtype, int strip, const AlignArgs& a, hipStream_t st);
+size_t skew_lds_bytes(int dtype, int strip, int max_m);
+size_t plain_lds_bytes(int dtype, int strip, int max_m);
+int max_lds_bytes();
+
+}  // namespace sdtw

@@ -1,0 +1,197 @@
+// Reference and query preparation (section 4.1; section 2.2 k-mer model).
+//
+// Reference: k-mer model lookup of both strands (one thread per output
+// sample), then a joint z-score whose mean and population sd are accumulated
+// in double by a fixed-partition, fixed-order reduction (deterministic from
+// run to run), then fixed-point codes.
+//
+// Queries: one thread per read walks its events in index order for the mean
+// and for the sum of squared deviations, so each read's statistics come from
+// exactly the same sequence of IEEE double operations as a plain sequential
+// loop (no contraction: the library is built with -ffp-contract=off).
+#include <math.h>
+
+#include "common.h"
+
+namespace sdtw {
+namespace {
+
+constexpr int kPrepThreads = 256;
+
+__device__ __forceinline__ int16_t to_code(float z, double scale, unsigned long long* nsat_local) {
+  double r = rint((double)z * scale);  // round half to even
+  if (r > 32767.0) { r = 32767.0; ++*nsat_local; }
+  if (r < -32768.0) { r = -32768.0; ++*nsat_local; }
+  return (int16_t)r;
+}
+
+// Expected current of k-mer p of the forward strand (p < nk) or of k-mer
+// p - nk of the reverse-complement strand read 5'->3'.
+__global__ void k_kmer(const uint8_t* __restrict__ g, int64_t L, int k,
+                       const float* __restrict__ table, float* __restrict__ sig) {
+  const int64_t nk = L - k + 1;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= 2 * nk) return;
+  uint32_t idx = 0;
+  if (p < nk) {
+    for (int m = 0; m < k; ++m) idx = idx * 4u + (g[p + m] & 3u);
+  } else {
+    const int64_t q = p - nk;  // position in revcomp(g)
+    for (int m = 0; m < k; ++m) idx = idx * 4u + (3u - (g[L - 1 - (q + m)] & 3u));
+  }
+  sig[p] = table[idx];
+}
+
+// mode 0: partial sums of x; mode 1: partial sums of (x - mean)^2.
+// Block b owns [b*chunk, min(n, (b+1)*chunk)); fixed order within the block.
+__global__ void k_partial(const float* __restrict__ x, int64_t n, int64_t chunk, int mode,
+                          const double* __restrict__ stats, double* __restrict__ partials) {
+  __shared__ double red[kPrepThreads];
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = min(n, lo + chunk);
+  const double mean = mode ? stats[0] : 0.0;
+  double acc = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kPrepThreads) {
+    double v = (double)x[i];
+    if (mode) {
+      double d = v - mean;
+      acc += d * d;
+    } else {
+      acc += v;
+    }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kPrepThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+// One thread: stats[0] = mean (mode 0) or stats[1] = population sd (mode 1).
+__global__ void k_finalize(const double* __restrict__ partials, int nb, int64_t n, int mode,
+                           double* __restrict__ stats, int64_t* __restrict__ nsat) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += partials[b];
+  if (mode == 0) {
+    stats[0] = s / (double)n;
+    if (nsat) *nsat = 0;
+  } else {
+    stats[1] = sqrt(s / (double)n);
+  }
+}
+
+// x and z may be the same array (normalised in place): each thread reads its
+// element before writing it, so neither pointer is declared restrict.
+__global__ void k_normalize(const float* x, int64_t n, const double* __restrict__ stats,
+                            double scale, float* z, int16_t* __restrict__ codes,
+                            int64_t* __restrict__ nsat) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long sat = 0;
+  if (i < n) {
+    const double mean = stats[0], sd = stats[1];
+    const float zi = sd > 0.0 ? (float)(((double)x[i] - mean) / sd) : 0.0f;
+    z[i] = zi;
+    if (codes) codes[i] = to_code(zi, scale, &sat);
+  }
+  if (nsat && sat) atomicAdd((unsigned long long*)nsat, sat);
+}
+
+__global__ void k_zero_i64(int64_t* p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
+// One thread per read: statistics in index order, as a sequential loop.
+__global__ void k_prep_queries(const float* __restrict__ raw, const int64_t* __restrict__ offs,
+                               int32_t nq, double scale, float* __restrict__ z,
+                               int16_t* __restrict__ codes, int64_t* __restrict__ nsat) {
+  const int32_t r = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (r >= nq) return;
+  const int64_t a = offs[r], b = offs[r + 1];
+  if (b <= a) return;
+  const double n = (double)(b - a);
+  double s = 0.0;
+  for (int64_t i = a; i < b; ++i) s += (double)raw[i];
+  const double mean = s / n;
+  double ss = 0.0;
+  for (int64_t i = a; i < b; ++i) {
+    double d = (double)raw[i] - mean;
+    ss += d * d;
+  }
+  const double sd = sqrt(ss / n);
+  unsigned long long sat = 0;
+  for (int64_t i = a; i < b; ++i) {
+    const float zi = sd > 0.0 ? (float)(((double)raw[i] - mean) / sd) : 0.0f;
+    z[i] = zi;
+    if (codes) codes[i] = to_code(zi, scale, &sat);
+  }
+  if (nsat && sat) atomicAdd((unsigned long long*)nsat, sat);
+}
+
+// Device layout of a reference: int16 -> u32 with +32768 bias, float -> bits;
+// zero padding up to n_pad.  Non-finite float values are counted.
+__global__ void k_layout(const void* __restrict__ src, int64_t n, int dtype,
+                         uint32_t* __restrict__ dst, int64_t n_pad, int32_t* __restrict__ nonfinite) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pad) return;
+  uint32_t v = 0;
+  if (i < n) {
+    if (dtype == SDTW_I16) {
+      v = (uint32_t)((int32_t)((const int16_t*)src)[i] + (int32_t)kI16Bias);
+    } else {
+      const float f = ((const float*)src)[i];
+      if (!isfinite(f)) atomicAdd(nonfinite, 1);
+      v = __float_as_uint(f);
+    }
+  }
+  dst[i] = v;
+}
+
+inline unsigned grid_for(int64_t n, int threads) {
+  return (unsigned)((n + threads - 1) / threads);
+}
+
+}  // namespace
+
+hipError_t launch_prepare_reference(const uint8_t* g, int64_t L, const float* table, int k,
+                                    double scale, float* z, int16_t* codes, int64_t* nsat,
+                                    double* scratch, hipStream_t st) {
+  const int64_t n = 2 * (L - k + 1);
+  // the raw signal is produced in z and normalised in place
+  hipLaunchKernelGGL(k_kmer, dim3(grid_for(n, kPrepThreads)), dim3(kPrepThreads), 0, st,
+                     g, L, k, table, z);
+  double* partials = scratch;
+  double* stats = scratch + (kRefPartials - 2);
+  int nb = (int)std::min<int64_t>(kRefPartials - 2, (n + kPrepThreads - 1) / kPrepThreads);
+  if (nb < 1) nb = 1;
+  const int64_t chunk = (n + nb - 1) / nb;
+  for (int mode = 0; mode < 2; ++mode) {
+    hipLaunchKernelGGL(k_partial, dim3(nb), dim3(kPrepThreads), 0, st, z, n, chunk, mode,
+                       stats, partials);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, partials, nb, n, mode, stats,
+                       mode == 0 ? nsat : nullptr);
+  }
+  hipLaunchKernelGGL(k_normalize, dim3(grid_for(n, kPrepThreads)), dim3(kPrepThreads), 0, st,
+                     z, n, stats, scale, z, codes, nsat);
+  return hipGetLastError();
+}
+
+hipError_t launch_prepare_queries(const float* raw, const int64_t* offs, int32_t nq,
+                                  double scale, float* z, int16_t* codes, int64_t* nsat,
+                                  hipStream_t st) {
+  if (nsat) hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, st, nsat);
+  hipLaunchKernelGGL(k_prep_queries, dim3(grid_for(nq, 64)), dim3(64), 0, st, raw, offs, nq,
+                     scale, z, codes, nsat);
+  return hipGetLastError();
+}
+
+hipError_t launch_layout_reference(const void* src, int64_t n, int dtype, uint32_t* dst,
+                                   int64_t n_pad, int32_t* nonfinite, hipStream_t st) {
+  hipLaunchKernelGGL(k_layout, dim3(grid_for(n_pad, kPrepThreads)), dim3(kPrepThreads), 0, st,
+                     src, n, dtype, dst, n_pad, nonfinite);
+  return hipGetLastError();
+}
+
+}  // namespace sdtw

@@ -1,0 +1,72 @@
+"""The C-ABI library loads, exports every symbol include/sdtw.h declares, and
+rejects bad arguments before touching the device (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sdtw.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sdtw_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2211_07340_amd as sd
+    if not os.path.exists(sd.library_path()):
+        import __graft_entry__
+        __graft_entry__.build()
+    return sd.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 14
+    raw = C.CDLL(os.path.join(ROOT, "paper_2211_07340_amd", "libsdtw.so"))
+    missing = [n for n in names if not hasattr(raw, n)]
+    assert not missing, missing
+
+
+def test_version_and_error_string(lib):
+    assert lib.sdtw_version() == 1
+    assert isinstance(lib.sdtw_last_error(), bytes)
+
+
+def _err(lib):
+    return lib.sdtw_last_error().decode()
+
+
+def test_plan_validation(lib):
+    h = C.c_void_p()
+    offs = np.array([0, 5, 5, 9], np.int64)  # read 1 is empty
+    rc = lib.sdtw_plan_create(offs.ctypes.data_as(C.c_void_p), 3, 1, C.byref(h))
+    assert rc == 1 and "read 1" in _err(lib)
+    offs = np.array([0, 5000], np.int64)  # longer than SDTW_MAX_QUERY
+    assert lib.sdtw_plan_create(offs.ctypes.data_as(C.c_void_p), 1, 1, C.byref(h)) == 1
+    assert lib.sdtw_plan_create(offs.ctypes.data_as(C.c_void_p), 0, 1, C.byref(h)) == 1
+    assert lib.sdtw_plan_create(offs.ctypes.data_as(C.c_void_p), 1, 7, C.byref(h)) == 1
+    assert lib.sdtw_plan_create(None, 1, 1, C.byref(h)) == 1
+    assert h.value is None
+
+
+def test_argument_validation(lib):
+    p = C.c_void_p(1)
+    assert lib.sdtw_align_batch(None, None, p, p, p, None) == 1
+    assert lib.sdtw_align_one(None, p, 5, p, p, None) == 1
+    assert lib.sdtw_load_reference(None, 10, 1, 0, None, C.byref(C.c_void_p())) == 1
+    assert lib.sdtw_load_reference(p, 0, 1, 0, None, C.byref(C.c_void_p())) == 1
+    assert lib.sdtw_load_reference(p, 10, 9, 0, None, C.byref(C.c_void_p())) == 1
+    assert lib.sdtw_prepare_reference(p, 3, p, 6, 64.0, p, p, p, None) == 1  # L < k
+    assert lib.sdtw_prepare_reference(p, 100, p, 6, -1.0, p, p, p, None) == 1
+    assert lib.sdtw_prepare_queries(p, p, 0, 64.0, p, p, p, None) == 1
+    assert lib.sdtw_plan_set_config(None, 16, 4) == 1
+    assert lib.sdtw_free_reference(None) == 1
+    assert lib.sdtw_plan_destroy(None) == 1
+    assert "null" in _err(lib)

@@ -1,0 +1,275 @@
+"""GPU parity: the HIP path against the CPU oracle, element by element.
+
+Bars: the int16 path is bit-exact against the exact integer oracle (cost and
+end); the float32 path is bit-exact against the float32-sequenced oracle and
+its cost lies within 1e-5 relative of the float64 oracle, whose last row must
+also accept the GPU's end (gamma64(M, end) <= cost64 * (1 + 1e-5)).
+Inputs are seeded and synthetic (synth) and prepared by the oracle, so the
+GPU and the oracle see identical arrays.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+sd = pytest.importorskip("paper_2211_07340_amd")
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sd.load_library()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def small_ref():
+    w = synth.workload(1, nq=64)
+    z, codes, nsat = oracle.prepare_reference(w.genome, w.table, w.k)
+    qz, qc, _ = oracle.prepare_queries(w.reads.values, w.reads.offsets)
+    return w, z, codes, qz, qc
+
+
+def gpu_batch(dev, ref_np, q_np, offs, dtype, strip=0, waves=0):
+    ref = sd.Reference(torch.from_numpy(np.ascontiguousarray(ref_np)).to(dev))
+    plan = sd.Plan(offs, dtype)
+    if strip or waves:
+        plan.set_config(strip, waves)
+    cost, end = sd.align_batch(ref, plan, torch.from_numpy(np.ascontiguousarray(q_np)).to(dev))
+    torch.cuda.synchronize()
+    out = cost.cpu().numpy(), end.cpu().numpy()
+    plan.close()
+    ref.close()
+    return out
+
+
+def check_i16(got, q, offs, ref, index=None):
+    want_c, want_e, _ = oracle.batch(oracle.I64, q, offs, ref, index=index)
+    gc, ge = got
+    if index is not None:
+        gc, ge = gc[index], ge[index]
+    bad = np.nonzero((gc.astype(np.int64) != want_c.astype(np.int64)) | (ge != want_e))[0]
+    assert bad.size == 0, f"{bad.size} mismatches, first {bad[:5]}: " \
+        f"gpu {gc[bad[:5]]},{ge[bad[:5]]} oracle {want_c[bad[:5]]},{want_e[bad[:5]]}"
+
+
+def check_f32(got, q, offs, ref, index=None, f64=True):
+    want_c, want_e, _ = oracle.batch(oracle.F32, q, offs, ref, index=index)
+    gc, ge = got
+    if index is not None:
+        gc, ge = gc[index], ge[index]
+    bad = np.nonzero((gc.astype(np.float64) != want_c) | (ge != want_e))[0]
+    assert bad.size == 0, f"{bad.size} mismatches, first {bad[:5]}: " \
+        f"gpu {gc[bad[:5]]},{ge[bad[:5]]} oracle {want_c[bad[:5]]},{want_e[bad[:5]]}"
+    if f64:
+        rows = range(offs.size - 1) if index is None else index
+        for t, r in enumerate(rows):
+            x = q[offs[r]:offs[r + 1]]
+            c64, e64, lr = oracle.sdtw_f64(x, ref, lastrow=True)
+            assert abs(float(gc[t]) - c64) <= 1e-5 * max(c64, 1e-30), (r, gc[t], c64)
+            assert lr[ge[t]] <= c64 * (1 + 1e-5) + 1e-30, (r, ge[t], e64)
+
+
+# ---------------------------------------------------------------------------
+
+
+def test_single_read_one_per_launch(dev, small_ref):
+    w, z, codes, qz, qc = small_ref
+    offs = w.reads.offsets
+    for r in (0, 1):
+        a, b = offs[r], offs[r + 1]
+        for dt, refv, qv in ((sd.I16, codes, qc), (sd.F32, z, qz)):
+            note(f"align_one read {r} dtype {dt} M={b - a} N={refv.size}")
+            ref = sd.Reference(torch.from_numpy(refv).to(dev))
+            cost, end = sd.align_one(ref, torch.from_numpy(qv[a:b].copy()).to(dev))
+            torch.cuda.synchronize()
+            if dt == sd.I16:
+                want = oracle.sdtw_i64(qv[a:b], refv)
+                assert (int(cost.item()), int(end.item())) == want
+            else:
+                want = oracle.sdtw_f32(qv[a:b], refv)
+                assert (np.float32(cost.item()), int(end.item())) == (want[0], want[1])
+            ref.close()
+
+
+def test_batch_64_reads_small_reference(dev, small_ref):
+    w, z, codes, qz, qc = small_ref
+    offs = w.reads.offsets
+    note("batch 64 x M=250 int16")
+    check_i16(gpu_batch(dev, codes, qc, offs, sd.I16), qc, offs, codes)
+    note("batch 64 x M=250 float32")
+    check_f32(gpu_batch(dev, z, qz, offs, sd.F32), qz, offs, z,
+              index=np.arange(0, 64, 8))
+
+
+@pytest.mark.parametrize("strip", [8, 16, 32])
+@pytest.mark.parametrize("waves", [1, 3, 16])
+def test_schedule_invariance(dev, small_ref, strip, waves):
+    w, z, codes, qz, qc = small_ref
+    offs = w.reads.offsets[:17]
+    note(f"schedule strip={strip} waves={waves}")
+    check_i16(gpu_batch(dev, codes, qc, offs, sd.I16, strip, waves), qc, offs, codes)
+    check_f32(gpu_batch(dev, z, qz, offs, sd.F32, strip, waves), qz, offs, z, f64=False)
+
+
+def _ragged_case(seed, Ms, N, lo=-3000, hi=3000):
+    rng = np.random.default_rng(seed)
+    ref = rng.integers(lo, hi, size=N).astype(np.int16)
+    qs = [rng.integers(lo, hi, size=m).astype(np.int16) for m in Ms]
+    vals, offs = synth.csr(qs)
+    return ref, vals.astype(np.int16), offs
+
+
+@pytest.mark.parametrize("N", [1, 7, 63, 64, 65, 511, 512, 513, 1023, 1024, 1025, 2047, 2048,
+                               2049, 5000])
+def test_edge_lengths_int16(dev, N):
+    Ms = [1, 2, 5, 33, 63, 64, 65, 66, 100, 127, 128, 129, 250, 700]
+    ref, q, offs = _ragged_case(N, Ms, N)
+    note(f"edge int16 N={N} Ms={Ms}")
+    for strip in (8, 16, 32):
+        check_i16(gpu_batch(dev, ref, q, offs, sd.I16, strip, 2), q, offs, ref)
+
+
+@pytest.mark.parametrize("N", [1, 65, 1025, 3001])
+def test_edge_lengths_float32(dev, N):
+    Ms = [1, 3, 63, 64, 65, 200, 1500]
+    rng = np.random.default_rng(N + 7)
+    ref = rng.normal(size=N).astype(np.float32)
+    qs = [rng.normal(size=m).astype(np.float32) for m in Ms]
+    q, offs = synth.csr(qs)
+    q = q.astype(np.float32)
+    note(f"edge float32 N={N}")
+    check_f32(gpu_batch(dev, ref, q, offs, sd.F32, 16, 2), q, offs, ref)
+
+
+def test_ties_constant_reference_and_extremes(dev):
+    # constant reference: every column ties, the first (end 0) must win
+    ref = np.full(3000, 17, np.int16)
+    qs = [np.full(m, v, np.int16) for m, v in ((70, 17), (300, -5), (64, 17), (10, 3))]
+    q, offs = synth.csr(qs)
+    q = q.astype(np.int16)
+    got = gpu_batch(dev, ref, q, offs, sd.I16)
+    assert got[1].tolist() == [0, 0, 0, 0]
+    assert got[0].tolist() == [0, 300 * 22, 0, 10 * 14]
+    check_i16(got, q, offs, ref)
+    # int16 extremes: |x - y| up to 65535 per cell, costs near 2^31 stay exact
+    rng = np.random.default_rng(99)
+    ref = rng.choice(np.array([-32768, 32767], np.int16), size=4000)
+    qs = [rng.choice(np.array([-32768, 32767], np.int16), size=m) for m in (64, 129, 2000, 4096)]
+    q, offs = synth.csr(qs)
+    q = q.astype(np.int16)
+    note("extremes int16")
+    check_i16(gpu_batch(dev, ref, q, offs, sd.I16), q, offs, ref)
+    qs = [np.full(m, -32768, np.int16) for m in (4096, 100)]
+    q, offs = synth.csr(qs)
+    q = q.astype(np.int16)
+    ref = np.full(50, 32767, np.int16)
+    got = gpu_batch(dev, ref, q, offs, sd.I16)
+    assert got[0].tolist() == [4096 * 65535, 100 * 65535]
+
+
+def test_query_longer_than_reference(dev):
+    ref, q, offs = _ragged_case(5, [400, 64, 90], 37)
+    check_i16(gpu_batch(dev, ref, q, offs, sd.I16), q, offs, ref)
+
+
+def test_exact_substring_zero_cost(dev, small_ref):
+    w, z, codes, qz, qc = small_ref
+    rng = np.random.default_rng(1)
+    starts = rng.integers(0, z.size - 300, size=8)
+    Ms = rng.integers(64, 300, size=8)
+    qs = [z[s:s + m].copy() for s, m in zip(starts, Ms)]
+    q, offs = synth.csr(qs)
+    q = q.astype(np.float32)
+    c, e = gpu_batch(dev, z, q, offs, sd.F32)
+    assert np.all(c == 0.0)
+    assert np.all(e <= starts + Ms - 1)
+    check_f32((c, e), q, offs, z, f64=False)
+
+
+def test_alone_equals_in_batch(dev, small_ref):
+    w, z, codes, qz, qc = small_ref
+    offs = w.reads.offsets[:9]
+    batch = gpu_batch(dev, codes, qc, offs, sd.I16)
+    ref = sd.Reference(torch.from_numpy(codes).to(dev))
+    for r in range(8):
+        cost, end = sd.align_one(ref, torch.from_numpy(qc[offs[r]:offs[r + 1]].copy()).to(dev))
+        torch.cuda.synchronize()
+        assert (int(cost.item()), int(end.item())) == (int(batch[0][r]), int(batch[1][r]))
+    ref.close()
+
+
+def test_uneven_batch_config2_shape(dev):
+    w = synth.workload(2, nq=24)
+    z, codes, _ = oracle.prepare_reference(w.genome, w.table, w.k)
+    qz, qc, _ = oracle.prepare_queries(w.reads.values, w.reads.offsets)
+    offs = w.reads.offsets
+    note(f"config-2 shape 24 reads M in [{w.reads.lengths.min()}, {w.reads.lengths.max()}]")
+    check_i16(gpu_batch(dev, codes, qc, offs, sd.I16), qc, offs, codes)
+    check_f32(gpu_batch(dev, z, qz, offs, sd.F32), qz, offs, z, index=np.arange(0, 24, 6))
+
+
+def test_full_config1_sampled(dev):
+    # the bench's launch configuration: all 4,096 reads in one persistent launch
+    w = synth.workload(1)
+    z, codes, _ = oracle.prepare_reference(w.genome, w.table, w.k)
+    qz, qc, _ = oracle.prepare_queries(w.reads.values, w.reads.offsets)
+    offs = w.reads.offsets
+    note("config-1 full batch int16 + float32, sampled oracle check")
+    gi = gpu_batch(dev, codes, qc, offs, sd.I16)
+    gf = gpu_batch(dev, z, qz, offs, sd.F32)
+    sample = np.random.default_rng(3).choice(4096, size=24, replace=False)
+    check_i16(gi, qc, offs, codes, index=sample)
+    check_f32(gf, qz, offs, z, index=sample[:6])
+    # on-target reads end where they were simulated from (the oracle puts every
+    # one of 600 such reads within 10 columns, 97.5% within 2)
+    on = w.reads.on_target
+    assert np.mean(np.abs(gi[1][on] - w.reads.end_true[on]) <= 10) > 0.999
+    assert np.mean(np.abs(gf[1][on] - w.reads.end_true[on]) <= 10) > 0.999
+
+
+def test_prepare_queries_matches_oracle(dev):
+    w = synth.workload(2, nq=300)
+    raw = torch.from_numpy(w.reads.values).to(dev)
+    offs = torch.from_numpy(w.reads.offsets).to(dev)
+    z, codes, nsat = sd.prepare_queries(raw, offs, 64.0)
+    torch.cuda.synchronize()
+    oz, oc, on = oracle.prepare_queries(w.reads.values, w.reads.offsets, 64.0)
+    assert np.array_equal(z.cpu().numpy().view(np.uint32), oz.view(np.uint32))
+    assert np.array_equal(codes.cpu().numpy(), oc)
+    assert int(nsat.item()) == on
+
+
+def test_prepare_reference_matches_oracle(dev):
+    w = synth.workload(0)
+    g = torch.from_numpy(w.genome).to(dev)
+    t = torch.from_numpy(w.table).to(dev)
+    z, codes, nsat = sd.prepare_reference(g, t, 6, 64.0)
+    torch.cuda.synchronize()
+    oz, oc, on = oracle.prepare_reference(w.genome, w.table, 6, 64.0)
+    gz = z.cpu().numpy()
+    # the joint statistics are reduced in a different order than the oracle's
+    # sequential loop: z may differ by one float32 ulp, codes only where that
+    # ulp crosses a rounding boundary
+    ulps = np.abs(gz.view(np.int32).astype(np.int64) - oz.view(np.int32).astype(np.int64))
+    assert ulps.max() <= 1 and np.mean(ulps > 0) < 1e-3
+    gc = codes.cpu().numpy()
+    diff = gc.astype(np.int32) != oc.astype(np.int32)
+    assert np.all(ulps[diff] > 0) and np.all(np.abs(gc.astype(np.int32) - oc)[diff] <= 1)
+    assert int(nsat.item()) == on
+    # the k-mer signal itself is exact: compare the pre-normalisation values
+    sig = oracle.kmer_signal(w.genome, w.table, 6)
+    assert np.allclose(gz, (sig - sig.astype(np.float64).mean()) / sig.astype(np.float64).std(),
+                       atol=1e-5)
