@@ -156,7 +156,7 @@ int sdtw_free_reference(sdtw_ref ref);
 /*
  * Validate and schedule a batch layout once; reuse it for every batch with
  * the same read lengths.  Reads are ordered longest first and pulled by a
- * persistent grid; reads shorter than 64 rows go to the one-wave kernel.
+ * persistent grid; reads shorter than 65 rows go to the one-wave kernel.
  *
  *   offsets_host  int64[nq+1] CSR offsets of the query values, read r is
  *                 q[offsets[r] .. offsets[r+1]); every read 1 <= M <=

@@ -25,7 +25,7 @@
 // reduction gives the first column attaining the minimum (the strict-less
 // last-row scan of Algorithms 1 and 2).
 //
-// k_align_skew (M >= 64): continuous skew.  Lanes never wait for each other
+// k_align_skew (M >= 65): continuous skew.  Lanes never wait for each other
 // at tile boundaries: lane l enters tile p at step p*M + l, so each period
 // of M steps starts with 64 "switch" steps in which exactly one lane swaps
 // its strip (masked LDS moves: new y from a staged copy of the tile, its
@@ -35,7 +35,7 @@
 //
 // k_align_plain (any M >= 1): synchronised tiles; every tile costs M + 63
 // steps with lanes idle during fill and drain.  Used for reads shorter than
-// 64 rows and as the one-read-per-launch baseline.
+// 65 rows and as the one-read-per-launch baseline.
 #include <limits.h>
 
 #include "common.h"
@@ -217,9 +217,14 @@ __global__ __launch_bounds__(64) void k_align_skew(AlignArgs args) {
     // lane 63's row is in the previous period (entry r + M).  `sw`: lane r
     // switches tiles in this step; its neighbour r+1 still needs its last-row
     // edge, so the DPP read comes before the switch overwrites `up`.
+    // The entry of step r + 1 is read during step r (before step r's own
+    // boundary write): lane 0's row r + 1 was written by lane 63 at least two
+    // steps earlier when M >= 65, which the launcher guarantees.
+    uint2 nxt;
     auto step = [&](int32_t r, uint32_t(&up)[W], uint32_t(&nw)[W], bool write_b, bool wrap,
                     bool sw) {
-      const uint2 e = bxl[r];
+      const uint2 e = nxt;
+      nxt = bxl[r + 1];
       const uint32_t left = from_left_lane(up[W - 1], e.y);
       if (sw) enter_tile(r, up);
       strip_row<F, W>(e.x, y, up, nw, dprev, left);
@@ -230,6 +235,7 @@ __global__ __launch_bounds__(64) void k_align_skew(AlignArgs args) {
     for (int32_t p = 0;; ++p) {
       // phase A: the 64 switch steps
       const bool first = (p == 0);
+      nxt = bxl[0];  // row 0 of the period (entry 63 + M is not maintained)
       for (int32_t r = 0; r < 64; r += 2) {
         step(r, a, b, !first, true, true);
         step(r + 1, b, a, !first || r + 1 == 63, r + 1 != 63, true);

@@ -25,7 +25,7 @@ struct sdtw_plan_s {
   int dtype;
   int32_t nq;
   int32_t max_m;
-  int32_t nbig, nsmall;      // reads with M >= 64 / M < 64
+  int32_t nbig, nsmall;      // reads with M >= kSkewMinM / shorter
   int32_t max_m_big, max_m_small;
   int64_t* offs_dev;         // [nq+1]
   int32_t* order_dev;        // [nq]: long reads longest first, then short reads
@@ -209,7 +209,7 @@ static void choose_config(sdtw_plan_s* p) {
   p->strip = 16;
   // resident waves per CU: limited by LDS (the CU holds 160 KiB) and capped
   // at 16 (four per SIMD), enough to hide LDS and DPP latency
-  const size_t per = skew_lds_bytes(p->dtype, p->strip, std::max(p->max_m_big, 64));
+  const size_t per = skew_lds_bytes(p->dtype, p->strip, std::max(p->max_m_big, kSkewMinM));
   int w = (int)std::min<size_t>(16, (160 * 1024) / std::max<size_t>(per, 1));
   p->waves_per_cu = std::max(w, 1);
 }
@@ -226,7 +226,7 @@ int sdtw_plan_create(const int64_t* offsets_host, int32_t nq, int dtype, sdtw_pl
     SDTW_REQUIRE(m >= 1 && m <= SDTW_MAX_QUERY,
                  "sdtw_plan_create: read %d has length %lld outside [1, %d]", r, (long long)m,
                  SDTW_MAX_QUERY);
-    if (m >= 64) {
+    if (m >= kSkewMinM) {
       big.push_back(r);
       max_big = std::max<int32_t>(max_big, (int32_t)m);
     } else {

@@ -20,6 +20,10 @@ constexpr int64_t kPadUnit = int64_t(kLanes) * kMaxStrip;
 // Offset that maps int16 onto [0, 65535]; |x - y| is translation invariant.
 constexpr uint32_t kI16Bias = 32768u;
 
+// Shortest read the continuous-skew kernel takes (its one-step-ahead LDS
+// prefetch needs lane 63's boundary write two steps before lane 0's read).
+constexpr int32_t kSkewMinM = 65;
+
 inline int64_t padded_length(int64_t n) {
   return ((n + kPadUnit - 1) / kPadUnit) * kPadUnit + kPadUnit;
 }
@@ -50,7 +54,7 @@ struct AlignArgs {
   int32_t* end;          // int32[nq]
   int32_t single_m;      // used when offs == nullptr: one read of this length
 };
-// Continuous-skew persistent kernel; every read in the list must have M >= 64.
+// Continuous-skew persistent kernel; every read in the list must have M >= 65.
 hipError_t launch_align_skew(int dtype, int strip, int blocks, const AlignArgs& a,
                              hipStream_t st);
 // Synchronised-tile single-wave kernel; any M >= 1; one block per work item.

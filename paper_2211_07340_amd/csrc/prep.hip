@@ -5,10 +5,11 @@
 // in double by a fixed-partition, fixed-order reduction (deterministic from
 // run to run), then fixed-point codes.
 //
-// Queries: one thread per read walks its events in index order for the mean
-// and for the sum of squared deviations, so each read's statistics come from
-// exactly the same sequence of IEEE double operations as a plain sequential
-// loop (no contraction: the library is built with -ffp-contract=off).
+// Queries: one wave per read; lane 0 walks the read's events in index order
+// for the mean and for the sum of squared deviations, so each read's
+// statistics come from exactly the same sequence of IEEE double operations as
+// a plain sequential loop (no contraction: the library is built with
+// -ffp-contract=off).
 #include <math.h>
 
 #include "common.h"
@@ -103,26 +104,51 @@ __global__ void k_zero_i64(int64_t* p) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
 }
 
-// One thread per read: statistics in index order, as a sequential loop.
-__global__ void k_prep_queries(const float* __restrict__ raw, const int64_t* __restrict__ offs,
-                               int32_t nq, double scale, float* __restrict__ z,
-                               int16_t* __restrict__ codes, int64_t* __restrict__ nsat) {
-  const int32_t r = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+// One wave per read.  Events are staged through LDS in coalesced chunks and
+// lane 0 accumulates the sum and then the sum of squared deviations in index
+// order, so the statistics come from the same sequence of double operations
+// as a plain sequential loop; all lanes then normalise and quantise.
+constexpr int kQChunk = 512;
+
+__device__ __forceinline__ double wave_seq_sum(const float* __restrict__ raw, int64_t a, int64_t b,
+                                               double mean, bool squares, float* buf) {
+  const int lane = (int)threadIdx.x;
+  double acc = 0.0;
+  for (int64_t base = a; base < b; base += kQChunk) {
+    const int n = (int)min<int64_t>(kQChunk, b - base);
+    for (int k = lane; k < n; k += 64) buf[k] = raw[base + k];
+    __syncthreads();
+    if (lane == 0) {
+      for (int k = 0; k < n; ++k) {
+        const double v = (double)buf[k];
+        if (squares) {
+          const double d = v - mean;
+          acc += d * d;
+        } else {
+          acc += v;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  return __shfl(acc, 0);
+}
+
+__global__ __launch_bounds__(64) void k_prep_queries(const float* __restrict__ raw,
+                                                     const int64_t* __restrict__ offs, int32_t nq,
+                                                     double scale, float* __restrict__ z,
+                                                     int16_t* __restrict__ codes,
+                                                     int64_t* __restrict__ nsat) {
+  __shared__ float buf[kQChunk];
+  const int32_t r = (int32_t)blockIdx.x;
   if (r >= nq) return;
   const int64_t a = offs[r], b = offs[r + 1];
   if (b <= a) return;
   const double n = (double)(b - a);
-  double s = 0.0;
-  for (int64_t i = a; i < b; ++i) s += (double)raw[i];
-  const double mean = s / n;
-  double ss = 0.0;
-  for (int64_t i = a; i < b; ++i) {
-    double d = (double)raw[i] - mean;
-    ss += d * d;
-  }
-  const double sd = sqrt(ss / n);
+  const double mean = wave_seq_sum(raw, a, b, 0.0, false, buf) / n;
+  const double sd = sqrt(wave_seq_sum(raw, a, b, mean, true, buf) / n);
   unsigned long long sat = 0;
-  for (int64_t i = a; i < b; ++i) {
+  for (int64_t i = a + threadIdx.x; i < b; i += 64) {
     const float zi = sd > 0.0 ? (float)(((double)raw[i] - mean) / sd) : 0.0f;
     z[i] = zi;
     if (codes) codes[i] = to_code(zi, scale, &sat);
@@ -182,8 +208,8 @@ hipError_t launch_prepare_queries(const float* raw, const int64_t* offs, int32_t
                                   double scale, float* z, int16_t* codes, int64_t* nsat,
                                   hipStream_t st) {
   if (nsat) hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, st, nsat);
-  hipLaunchKernelGGL(k_prep_queries, dim3(grid_for(nq, 64)), dim3(64), 0, st, raw, offs, nq,
-                     scale, z, codes, nsat);
+  hipLaunchKernelGGL(k_prep_queries, dim3(nq), dim3(64), 0, st, raw, offs, nq, scale, z, codes,
+                     nsat);
   return hipGetLastError();
 }
 

@@ -20,25 +20,28 @@ def skew_model(x, yref, W):
     L = 64
     T = L * W
     M, N = len(x), len(yref)
-    assert M >= 64
+    assert M >= 65
     ntiles = (N + T - 1) // T
     ref = np.zeros(ntiles * T + T, np.uint64)
     ref[:N] = yref.astype(np.int64) + 32768
     xb = x.astype(np.int64) + 32768
-    bxx = np.array([xb[(k - 63) % M] for k in range(M + 64)], np.uint64)
-    bxy = np.full(M + 64, INF, np.uint64)
+    bxx = np.array([xb[(k - 63) % M] for k in range(M + 65)], np.uint64)
+    bxy = np.full(M + 65, INF, np.uint64)
     stage = ref[0:T].reshape(L, W).copy()
     y = np.zeros((L, W), np.uint64)
     a = np.zeros((L, W), np.uint64)
     b = np.zeros((L, W), np.uint64)
-    st = {"dprev": np.full(L, INF, np.uint64)}
+    st = {"dprev": np.full(L, INF, np.uint64), "next": None}
     best = np.full(L, INF, np.uint64)
     bestj = np.full(L, 2 ** 31 - 1, np.int64)
     lanes = np.arange(L)
 
     def step(r, up, nw, write_b, wrap, sw):
-        k = 63 + r - lanes
-        ex, ey = bxx[k], bxy[k]
+        # this step's entries were read one step earlier (prefetch), before
+        # the previous step's boundary write became visible to this read
+        ex, ey = st["next"]
+        k = 63 + r + 1 - lanes
+        st["next"] = (bxx[k].copy(), bxy[k].copy())
         left = np.empty(L, np.uint64)
         left[1:] = up[:-1, W - 1]
         left[0] = ey[0]
@@ -60,6 +63,8 @@ def skew_model(x, yref, W):
 
     p = 0
     while True:
+        k0 = 63 - lanes  # fresh read at the start of every period
+        st["next"] = (bxx[k0].copy(), bxy[k0].copy())
         for r in range(0, 64, 2):
             step(r, a, b, p > 0, True, True)
             step(r + 1, b, a, p > 0 or r + 1 == 63, r + 1 != 63, True)
@@ -87,8 +92,8 @@ def skew_model(x, yref, W):
 
 
 @pytest.mark.parametrize("W,M,N,lo,hi", [
-    (4, 64, 1, -2, 2), (4, 64, 257, -2, 2), (4, 65, 255, -30000, 30000),
-    (8, 64, 513, -50, 50), (4, 131, 700, -3, 3), (8, 97, 1100, -30000, 30000),
+    (4, 65, 1, -2, 2), (4, 65, 257, -2, 2), (4, 65, 255, -30000, 30000),
+    (8, 66, 513, -50, 50), (4, 131, 700, -3, 3), (8, 97, 1100, -30000, 30000),
     (16, 70, 1025, -5, 5),
 ])
 def test_skew_schedule_matches_oracle(W, M, N, lo, hi):
