@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--config", type=int, default=1, choices=[1, 2, 3])
     ap.add_argument("--dtype", default="i16", choices=["i16", "f32"])
     ap.add_argument("--strip", type=int, default=0)
+    ap.add_argument("--chains", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
@@ -79,8 +80,8 @@ def main():
     raw = torch.from_numpy(reads.values).to(dev)
     offs_dev = torch.from_numpy(reads.offsets).to(dev)
     plan = sd.Plan(reads.offsets, dt)
-    if args.strip or args.waves:
-        plan.set_config(args.strip, args.waves)
+    if args.strip or args.chains or args.waves:
+        plan.set_config(args.strip, args.chains, args.waves)
     cost = torch.empty(nq, dtype=torch.int32 if dt == sd.I16 else torch.float32, device=dev)
     end = torch.empty(nq, dtype=torch.int32, device=dev)
     cells = float(reads.lengths.sum()) * N
@@ -112,7 +113,7 @@ def main():
     gcups = cells / (ms_step * 1e-3) / 1e9
     kern_tcups = cells / (kern_ms * 1e-3) / 1e12
     peak = valu_peak_tcups(args.dtype)
-    strip, waves = plan.config
+    strip, chains, waves = plan.config
 
     out = {
         "metric": "sDTW GCUPS at 1 GPU (% VALU peak)",
@@ -129,7 +130,7 @@ def main():
         "data": "synthetic (seeded genome, stand-in 6-mer pore model, simulated reads)",
         "config": {"workload": w.name, "reads": nq, "query_values": int(reads.values.size),
                    "reference_values": N, "cells_per_step": cells,
-                   "strip": strip, "waves_per_cu": waves},
+                   "strip": strip, "chains": chains, "waves_per_cu": waves},
         "reads_per_s": round(nq / (ms_step * 1e-3), 1),
         "pct_valu_peak": round(100 * gcups / (peak * 1e3), 2),
         "roofline": {"bound": "alu", "kernel": "sdtw_align_batch",
@@ -197,10 +198,16 @@ def cpu_baseline(w, reads, args):
     kind = oracle.I64 if args.dtype == "i16" else oracle.F32
     q = qc if args.dtype == "i16" else qz
     r = codes if args.dtype == "i16" else z
-    n = args.cpu_sample or max(8, min(reads.nq, 160 * cores))
+    if args.cpu_sample:
+        n = args.cpu_sample
+    else:  # about 10 s of work at ~0.25 GCUPS per core
+        per_read = reads.lengths.astype(np.float64) * r.size
+        n = int(np.searchsorted(np.cumsum(per_read), 2.5e9 * cores)) + 1
+        n = max(1, min(reads.nq, n))
     idx = np.arange(n)
+    threads = min(cores, n)
     t0 = time.perf_counter()
-    _, _, used = oracle.batch(kind, q, reads.offsets, r, index=idx, nthreads=cores)
+    _, _, used = oracle.batch(kind, q, reads.offsets, r, index=idx, nthreads=threads)
     t = time.perf_counter() - t0
     cells = float(reads.lengths[:n].sum()) * r.size
     return {"value": round(cells / t / 1e9, 3), "unit": "GCUPS", "cores": used,

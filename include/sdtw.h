@@ -156,7 +156,8 @@ int sdtw_free_reference(sdtw_ref ref);
 /*
  * Validate and schedule a batch layout once; reuse it for every batch with
  * the same read lengths.  Reads are ordered longest first and pulled by a
- * persistent grid; reads shorter than 65 rows go to the one-wave kernel.
+ * persistent grid (one launch per group of reads that share a kernel
+ * configuration); reads of 64 rows or fewer go to the one-wave kernel.
  *
  *   offsets_host  int64[nq+1] CSR offsets of the query values, read r is
  *                 q[offsets[r] .. offsets[r+1]); every read 1 <= M <=
@@ -172,13 +173,18 @@ int sdtw_plan_create(const int64_t* offsets_host, int32_t nq, int dtype,
 int sdtw_plan_info(sdtw_plan plan, int32_t* nq, int* dtype, int32_t* max_m);
 
 /*
- * Override the kernel configuration chosen for a plan (autotuning).
- *   strip  columns per lane: 8, 16 or 32 (0 = keep).
+ * Override the kernel configuration chosen for a plan (autotuning).  Results
+ * never depend on it.
+ *   strip   columns per lane: 8, 16 or 32 (0 = keep).
+ *   chains  independent dependency chains per lane for long reads: 1, 2 or
+ *           4 (0 = keep); strip / chains must be a multiple of 4.  Reads
+ *           with M >= 64 * chains + 1 use that many; shorter reads fall back
+ *           to fewer chains, and reads with M <= 64 to the one-wave kernel.
  *   waves_per_cu  resident waves per compute unit for the persistent grid,
- *                 1..32 (0 = keep).
+ *           1..32 (0 = keep).
  */
-int sdtw_plan_set_config(sdtw_plan plan, int strip, int waves_per_cu);
-int sdtw_plan_get_config(sdtw_plan plan, int* strip, int* waves_per_cu);
+int sdtw_plan_set_config(sdtw_plan plan, int strip, int chains, int waves_per_cu);
+int sdtw_plan_get_config(sdtw_plan plan, int* strip, int* chains, int* waves_per_cu);
 
 /* Release a plan (synchronise the streams that used it first). */
 int sdtw_plan_destroy(sdtw_plan plan);

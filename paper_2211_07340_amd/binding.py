@@ -49,8 +49,9 @@ def load_library():
         "sdtw_free_reference": ([p], C.c_int),
         "sdtw_plan_create": ([p, i32, C.c_int, C.POINTER(p)], C.c_int),
         "sdtw_plan_info": ([p, C.POINTER(i32), C.POINTER(C.c_int), C.POINTER(i32)], C.c_int),
-        "sdtw_plan_set_config": ([p, C.c_int, C.c_int], C.c_int),
-        "sdtw_plan_get_config": ([p, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
+        "sdtw_plan_set_config": ([p, C.c_int, C.c_int, C.c_int], C.c_int),
+        "sdtw_plan_get_config": ([p, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                  C.POINTER(C.c_int)], C.c_int),
         "sdtw_plan_destroy": ([p], C.c_int),
         "sdtw_align_batch": ([p, p, p, p, p, p], C.c_int),
         "sdtw_align_one": ([p, p, i32, p, p, p], C.c_int),
@@ -205,14 +206,16 @@ class Plan:
             raise SdtwError(5, "plan is closed")
         return self._h
 
-    def set_config(self, strip: int = 0, waves_per_cu: int = 0):
-        _check(load_library().sdtw_plan_set_config(self.handle, strip, waves_per_cu))
+    def set_config(self, strip: int = 0, chains: int = 0, waves_per_cu: int = 0):
+        _check(load_library().sdtw_plan_set_config(self.handle, strip, chains, waves_per_cu))
 
     @property
     def config(self):
-        s, w = C.c_int(), C.c_int()
-        _check(load_library().sdtw_plan_get_config(self.handle, C.byref(s), C.byref(w)))
-        return s.value, w.value
+        """(strip, chains, waves_per_cu)"""
+        s, k, w = C.c_int(), C.c_int(), C.c_int()
+        _check(load_library().sdtw_plan_get_config(self.handle, C.byref(s), C.byref(k),
+                                                   C.byref(w)))
+        return s.value, k.value, w.value
 
     def close(self):
         if self._h is not None:

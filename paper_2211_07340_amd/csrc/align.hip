@@ -38,6 +38,8 @@
 // 65 rows and as the one-read-per-launch baseline.
 #include <limits.h>
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace sdtw {
@@ -93,6 +95,77 @@ __device__ __forceinline__ uint32_t from_left_lane(uint32_t v, uint32_t lane0) {
   return (uint32_t)__builtin_amdgcn_update_dpp((int)lane0, (int)v, 0x138, 0xF, 0xF, false);
 }
 
+// Issue-order-pinned forms of the cell operations for the multi-chain
+// kernel.  The compiler's scheduler models these instructions as cheap and
+// emits each chain back to back; measured on gfx950 a dependent VALU
+// instruction issues about 10 cycles after its producer, so the K chains of
+// a lane are interleaved explicitly (volatile asm keeps its order).
+__device__ __forceinline__ uint32_t asm_min3(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t d;
+  asm volatile("v_min3_u32 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+  return d;
+}
+__device__ __forceinline__ uint32_t asm_sad(uint32_t x, uint32_t y, uint32_t m) {
+  uint32_t d;  // |x - y| + m on unsigned operands
+  asm volatile("v_sad_u32 %0, %1, %2, %3" : "=v"(d) : "v"(x), "v"(y), "v"(m));
+  return d;
+}
+__device__ __forceinline__ uint32_t asm_subf(uint32_t x, uint32_t y) {
+  uint32_t d;  // x - y in float32 (bit patterns in and out)
+  asm volatile("v_sub_f32 %0, %1, %2" : "=v"(d) : "v"(x), "v"(y));
+  return d;
+}
+__device__ __forceinline__ uint32_t asm_addabs(uint32_t d, uint32_t m) {
+  uint32_t r;  // |d| + m in float32
+  asm volatile("v_add_f32_e64 %0, |%1|, %2" : "=v"(r) : "v"(d), "v"(m));
+  return r;
+}
+// from_left_lane with its DPP in asm; the leading s_nop covers the two wait
+// states a DPP read needs after a VALU write of its source.
+__device__ __forceinline__ uint32_t asm_from_left_lane(uint32_t v, uint32_t lane0) {
+  uint32_t r = lane0;
+  asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 wave_shr:1 row_mask:0xf bank_mask:0xf"
+               : "+v"(r)
+               : "v"(v));
+  return r;
+}
+
+// One row step of K interleaved chains over a lane's strip: chain h owns
+// columns [h*H, (h+1)*H).  nw[c] = gamma(i_h, c) from up[c] = gamma(i_h - 1, c),
+// the diagonal dprev[h] and left[h] = gamma(i_h, first column - 1), where
+// i_h is chain h's row.  Instructions are issued column by column across the
+// chains so that consecutive instructions of one chain are K apart.
+template <class F, int K, int H, int W>
+__device__ __forceinline__ void chains_row(const uint32_t (&x)[K], const uint32_t (&y)[W],
+                                           const uint32_t (&up)[W], uint32_t (&nw)[W],
+                                           const uint32_t (&dprev)[K],
+                                           const uint32_t (&left)[K]) {
+#pragma unroll
+  for (int w = 0; w < H; ++w) {
+    uint32_t m[K];
+    if constexpr (std::is_same<F, FmtF32>::value) {
+      uint32_t d[K];
+#pragma unroll
+      for (int h = 0; h < K; ++h) d[h] = asm_subf(x[h], y[h * H + w]);
+#pragma unroll
+      for (int h = 0; h < K; ++h) {
+        const int c = h * H + w;
+        m[h] = asm_min3(up[c], w ? up[c - 1] : dprev[h], w ? nw[c - 1] : left[h]);
+      }
+#pragma unroll
+      for (int h = 0; h < K; ++h) nw[h * H + w] = asm_addabs(d[h], m[h]);
+    } else {
+#pragma unroll
+      for (int h = 0; h < K; ++h) {
+        const int c = h * H + w;
+        m[h] = asm_min3(up[c], w ? up[c - 1] : dprev[h], w ? nw[c - 1] : left[h]);
+      }
+#pragma unroll
+      for (int h = 0; h < K; ++h) nw[h * H + w] = asm_sad(x[h], y[h * H + w], m[h]);
+    }
+  }
+}
+
 __device__ __forceinline__ void wave_argmin(uint32_t& best, int32_t& bestj) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
@@ -102,6 +175,15 @@ __device__ __forceinline__ void wave_argmin(uint32_t& best, int32_t& bestj) {
       best = ob;
       bestj = oj;
     }
+  }
+}
+
+// f(integral_constant<int, I>) for I in [B, E), unrolled at compile time
+template <int B, int E, class Fn>
+__device__ __forceinline__ void static_for(Fn&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
   }
 }
 
@@ -121,37 +203,49 @@ __device__ __forceinline__ void load_strip(uint32_t (&dst)[W], const uint32_t* _
 // Continuous-skew kernel
 // ---------------------------------------------------------------------------
 
-template <class F, int W>
+template <class F, int W, int K>
 struct SkewLds {
   static constexpr int kStage = 64 * W;  // per-lane strips: next tile / last rows
   static constexpr int kZeros = W;
-  // query/boundary pairs: max_m + 64 entries of 8 bytes
+  // query/boundary pairs: max_m + 64K entries of 8 bytes
   static size_t bytes(int max_m) {
-    size_t b = 4 * ((size_t)kStage + kZeros) + 8 * ((size_t)max_m + 64);
+    size_t b = 4 * ((size_t)kStage + kZeros) + 8 * ((size_t)max_m + 64 * K);
     return (b + 15) & ~(size_t)15;
   }
 };
 
-// LDS layout of the query and the left-boundary column (one 8-byte entry
-// per k in [0, M + 64)):
-//   bx[k].x = query row (k - 63) mod M      (biased int16 or float bits)
-//   bx[k].y = boundary gamma(row k - 63, last column of the previous tile)
-//             for k in [63, M + 63)
-// Lane l reads its row r of the current period at entry 63 + r - l, so one
-// per-lane address serves all three accesses of a step: every lane's query
-// value, lane 0's boundary value (entry 63 + r holds row r), and lane 63's
-// boundary write of its row r - 63 (entry r, its own entry).  Rows M-63..M-1
-// of lane 63 (written in the first 63 steps of a period) land at r + M.
-template <class F, int W>
+// K chains per lane.  Lane l's strip of W columns is cut into K sub-strips of
+// H = W/K columns; sub-strip h is "sub-lane" s = K*l + h and works on row
+// (t - s) mod M of its tile at step t.  Within a step the K sub-strips of a
+// lane are independent dependency chains (each needs the edge its left
+// neighbour produced one step earlier), which the hardware can overlap:
+// chain 0 takes lane l-1's last-column edge by DPP, chain h > 0 takes the
+// lane's own chain h-1 edge, still in its row buffer.
+//
+// LDS layout of the query and the left-boundary column, one 8-byte entry per
+// k in [0, M + 64K):
+//   bx[k].x = query row (k - (64K - 1)) mod M   (biased int16 or float bits)
+//   bx[k].y = boundary gamma(row k - (64K - 1), last column of the previous
+//             tile) for k in [64K - 1, M + 64K - 1)
+// Chain h of lane l reads its row r of the current period at entry
+// K(63 - l) + r + (K - 1 - h); so lane 0's chain 0 finds boundary row r at
+// entry 64K - 1 + r, and the last sub-lane (lane 63, chain K-1) writes its
+// boundary row r - (64K - 1) at entry r, its own entry (at r + M while that
+// row is in the previous period).
+template <class F, int W, int K>
 __global__ __launch_bounds__(64) void k_align_skew(AlignArgs args) {
   constexpr int T = 64 * W;
+  constexpr int H = W / K;
+  constexpr int S = 64 * K;                   // sub-lanes = switch steps per period
+  constexpr int U = K > 2 ? K : 2;            // phase-A unroll: chain index compile-time
+  static_assert(W % K == 0 && H % 4 == 0, "sub-strips are whole uint4 groups");
   extern __shared__ __align__(16) uint32_t smem[];
   const int lane = (int)threadIdx.x;
   uint32_t* const stage = smem;
-  uint32_t* const zeros = stage + SkewLds<F, W>::kStage;
-  uint2* const bx = (uint2*)(zeros + SkewLds<F, W>::kZeros);
+  uint32_t* const zeros = stage + SkewLds<F, W, K>::kStage;
+  uint2* const bx = (uint2*)(zeros + SkewLds<F, W, K>::kZeros);
   uint32_t* const my_stage = stage + lane * W;
-  uint2* const bxl = bx + 63 - lane;
+  uint2* const bxl = bx + K * (63 - lane);
 
   if (lane < W) zeros[lane] = 0u;
   const int32_t N = (int32_t)args.n;
@@ -173,8 +267,8 @@ __global__ __launch_bounds__(64) void k_align_skew(AlignArgs args) {
     const typename F::qin* __restrict__ qv = (const typename F::qin*)args.q + q0;
 
     __syncthreads();  // previous read's LDS use is complete
-    for (int k = lane; k < M + 64; k += 64) {
-      int s = k - 63;
+    for (int k = lane; k < M + S; k += 64) {
+      int s = k - (S - 1);
       s = s < 0 ? s + M : (s >= M ? s - M : s);
       bx[k] = make_uint2((uint32_t)F::to_lds(qv[s]), F::kInf);  // gamma(i, 0) = +inf
     }
@@ -186,59 +280,78 @@ __global__ __launch_bounds__(64) void k_align_skew(AlignArgs args) {
     }
     __syncthreads();
 
-    uint32_t y[W], a[W], b[W];
+    uint32_t y[W], a[W], b[W], dprev[K];
 #pragma unroll
     for (int w = 0; w < W; ++w) y[w] = a[w] = b[w] = 0u;
-    uint32_t dprev = F::kInf;
+#pragma unroll
+    for (int h = 0; h < K; ++h) dprev[h] = F::kInf;
     uint32_t best = 0xFFFFFFFFu;
     int32_t bestj = INT_MAX;
 
-    // lane `r` (r < 64) enters its next tile: strip values in, the finished
-    // last row of the previous tile out, gamma(0, .) = 0 in.
-    auto enter_tile = [&](int32_t r, uint32_t(&up)[W]) {
-      if (lane == r) {
+    // The entries of step r + 1 are read during step r (before step r's own
+    // boundary write): lane 0's row r + 1 was written by the last sub-lane
+    // at least two steps earlier when M >= 64K + 1, which the launcher
+    // guarantees.
+    uint2 nxt[K];
+    auto load_entries = [&](int32_t r, uint2(&e)[K]) {
 #pragma unroll
-        for (int w = 0; w < W; w += 4) {
-          const uint4 nv = *(const uint4*)(my_stage + w);
-          *(uint4*)(my_stage + w) = make_uint4(up[w], up[w + 1], up[w + 2], up[w + 3]);
-          const uint4 zv = *(const uint4*)(zeros + w);
-          y[w] = nv.x;
-          y[w + 1] = nv.y;
-          y[w + 2] = nv.z;
-          y[w + 3] = nv.w;
-          up[w] = zv.x;
-          up[w + 1] = zv.y;
-          up[w + 2] = zv.z;
-          up[w + 3] = zv.w;
+      for (int h = 0; h < K; ++h) e[h] = bxl[r + (K - 1 - h)];
+    };
+    // One row step.  CH >= 0: sub-lane r (lane r / K, chain CH == r % K)
+    // enters its next tile in this step; the edges its right neighbours need
+    // are read before the switch overwrites `up`.
+    auto step = [&](auto ch, int32_t r, uint32_t(&up)[W], uint32_t(&nw)[W], bool write_b,
+                    bool wrap) {
+      constexpr int CH = decltype(ch)::value;
+      uint2 e[K];
+#pragma unroll
+      for (int h = 0; h < K; ++h) e[h] = nxt[h];
+      load_entries(r + 1, nxt);
+      uint32_t left[K];
+      left[0] = asm_from_left_lane(up[W - 1], e[0].y);
+#pragma unroll
+      for (int h = 1; h < K; ++h) left[h] = up[h * H - 1];
+      if constexpr (CH >= 0) {
+        if (lane == r / K) {
+#pragma unroll
+          for (int w = CH * H; w < (CH + 1) * H; w += 4) {
+            const uint4 nv = *(const uint4*)(my_stage + w);
+            *(uint4*)(my_stage + w) = make_uint4(up[w], up[w + 1], up[w + 2], up[w + 3]);
+            const uint4 zv = *(const uint4*)(zeros + w);
+            y[w] = nv.x;
+            y[w + 1] = nv.y;
+            y[w + 2] = nv.z;
+            y[w + 3] = nv.w;
+            up[w] = zv.x;
+            up[w + 1] = zv.y;
+            up[w + 2] = zv.z;
+            up[w + 3] = zv.w;
+          }
         }
       }
-    };
-    // one row step: lane l computes row (r - l) mod M of its tile.  `wrap`:
-    // lane 63's row is in the previous period (entry r + M).  `sw`: lane r
-    // switches tiles in this step; its neighbour r+1 still needs its last-row
-    // edge, so the DPP read comes before the switch overwrites `up`.
-    // The entry of step r + 1 is read during step r (before step r's own
-    // boundary write): lane 0's row r + 1 was written by lane 63 at least two
-    // steps earlier when M >= 65, which the launcher guarantees.
-    uint2 nxt;
-    auto step = [&](int32_t r, uint32_t(&up)[W], uint32_t(&nw)[W], bool write_b, bool wrap,
-                    bool sw) {
-      const uint2 e = nxt;
-      nxt = bxl[r + 1];
-      const uint32_t left = from_left_lane(up[W - 1], e.y);
-      if (sw) enter_tile(r, up);
-      strip_row<F, W>(e.x, y, up, nw, dprev, left);
-      dprev = left;
+      uint32_t xs[K];
+#pragma unroll
+      for (int h = 0; h < K; ++h) xs[h] = e[h].x;
+      chains_row<F, K, H, W>(xs, y, up, nw, dprev, left);
+#pragma unroll
+      for (int h = 0; h < K; ++h) dprev[h] = left[h];
       if (write_b && lane == 63) bxl[wrap ? r + M : r].y = nw[W - 1];
     };
+    using NoSwitch = std::integral_constant<int, -1>;
 
     for (int32_t p = 0;; ++p) {
-      // phase A: the 64 switch steps
+      // phase A: the 64K switch steps
       const bool first = (p == 0);
-      nxt = bxl[0];  // row 0 of the period (entry 63 + M is not maintained)
-      for (int32_t r = 0; r < 64; r += 2) {
-        step(r, a, b, !first, true, true);
-        step(r + 1, b, a, !first || r + 1 == 63, r + 1 != 63, true);
+      load_entries(0, nxt);  // row 0 of the period (entry 64K - 1 + M is not kept)
+      for (int32_t r = 0; r < S; r += U) {
+        // chain index of step r + u is (r + u) % K == u % K since U % K == 0
+        static_for<0, U / 2>([&](auto uu) {
+          constexpr int u = 2 * decltype(uu)::value;
+          step(std::integral_constant<int, u % K>{}, r + u, a, b, !first || r + u == S - 1,
+               r + u != S - 1);
+          step(std::integral_constant<int, (u + 1) % K>{}, r + u + 1, b, a,
+               !first || r + u + 1 == S - 1, r + u + 1 != S - 1);
+        });
       }
       // every lane has finished tile p-1: fold its last row, stage tile p+1
       if (p >= 1) {
@@ -260,19 +373,19 @@ __global__ __launch_bounds__(64) void k_align_skew(AlignArgs args) {
       }
       if (p == ntiles) break;
       // phase B: plain steps, four per iteration
-      int32_t r = 64;
+      int32_t r = S;
       for (; r + 3 < M; r += 4) {
-        step(r, a, b, true, false, false);
-        step(r + 1, b, a, true, false, false);
-        step(r + 2, a, b, true, false, false);
-        step(r + 3, b, a, true, false, false);
+        step(NoSwitch{}, r, a, b, true, false);
+        step(NoSwitch{}, r + 1, b, a, true, false);
+        step(NoSwitch{}, r + 2, a, b, true, false);
+        step(NoSwitch{}, r + 3, b, a, true, false);
       }
       for (; r + 1 < M; r += 2) {
-        step(r, a, b, true, false, false);
-        step(r + 1, b, a, true, false, false);
+        step(NoSwitch{}, r, a, b, true, false);
+        step(NoSwitch{}, r + 1, b, a, true, false);
       }
       if (r < M) {
-        step(r, a, b, true, false, false);
+        step(NoSwitch{}, r, a, b, true, false);
 #pragma unroll
         for (int w = 0; w < W; ++w) a[w] = b[w];
       }
@@ -371,14 +484,14 @@ __global__ void k_reset_counter(int32_t* c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
 }
 
-template <class F, int W>
+template <class F, int W, int K>
 hipError_t launch_skew_t(int blocks, const AlignArgs& a, hipStream_t st) {
-  const size_t lds = SkewLds<F, W>::bytes(a.max_m);
-  hipError_t e = hipFuncSetAttribute((const void*)k_align_skew<F, W>,
+  const size_t lds = SkewLds<F, W, K>::bytes(a.max_m);
+  hipError_t e = hipFuncSetAttribute((const void*)k_align_skew<F, W, K>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, a.counter);
-  hipLaunchKernelGGL((k_align_skew<F, W>), dim3(blocks), dim3(64), lds, st, a);
+  hipLaunchKernelGGL((k_align_skew<F, W, K>), dim3(blocks), dim3(64), lds, st, a);
   return hipGetLastError();
 }
 
@@ -393,11 +506,16 @@ hipError_t launch_plain_t(const AlignArgs& a, hipStream_t st) {
 }
 
 template <class F>
-hipError_t launch_skew_f(int strip, int blocks, const AlignArgs& a, hipStream_t st) {
-  switch (strip) {
-    case 8: return launch_skew_t<F, 8>(blocks, a, st);
-    case 16: return launch_skew_t<F, 16>(blocks, a, st);
-    case 32: return launch_skew_t<F, 32>(blocks, a, st);
+hipError_t launch_skew_f(int strip, int chains, int blocks, const AlignArgs& a, hipStream_t st) {
+  switch (strip * 8 + chains) {
+    case 8 * 8 + 1: return launch_skew_t<F, 8, 1>(blocks, a, st);
+    case 8 * 8 + 2: return launch_skew_t<F, 8, 2>(blocks, a, st);
+    case 16 * 8 + 1: return launch_skew_t<F, 16, 1>(blocks, a, st);
+    case 16 * 8 + 2: return launch_skew_t<F, 16, 2>(blocks, a, st);
+    case 16 * 8 + 4: return launch_skew_t<F, 16, 4>(blocks, a, st);
+    case 32 * 8 + 1: return launch_skew_t<F, 32, 1>(blocks, a, st);
+    case 32 * 8 + 2: return launch_skew_t<F, 32, 2>(blocks, a, st);
+    case 32 * 8 + 4: return launch_skew_t<F, 32, 4>(blocks, a, st);
   }
   return hipErrorInvalidValue;
 }
@@ -413,13 +531,11 @@ hipError_t launch_plain_f(int strip, const AlignArgs& a, hipStream_t st) {
 }
 
 template <class F>
-size_t skew_bytes_f(int strip, int max_m) {
-  switch (strip) {
-    case 8: return SkewLds<F, 8>::bytes(max_m);
-    case 16: return SkewLds<F, 16>::bytes(max_m);
-    case 32: return SkewLds<F, 32>::bytes(max_m);
-  }
-  return 0;
+size_t skew_bytes_f(int strip, int chains, int max_m) {
+  if (!valid_strip_chains(strip, chains)) return 0;
+  // the layout depends on (W, K) only through 4(64W + W) + 8(M + 64K)
+  return (4 * ((size_t)64 * strip + strip) + 8 * ((size_t)max_m + 64 * chains) + 15) &
+         ~(size_t)15;
 }
 
 template <class F>
@@ -434,10 +550,10 @@ size_t plain_bytes_f(int strip, int max_m) {
 
 }  // namespace
 
-hipError_t launch_align_skew(int dtype, int strip, int blocks, const AlignArgs& a,
+hipError_t launch_align_skew(int dtype, int strip, int chains, int blocks, const AlignArgs& a,
                              hipStream_t st) {
-  return dtype == SDTW_I16 ? launch_skew_f<FmtI16>(strip, blocks, a, st)
-                           : launch_skew_f<FmtF32>(strip, blocks, a, st);
+  return dtype == SDTW_I16 ? launch_skew_f<FmtI16>(strip, chains, blocks, a, st)
+                           : launch_skew_f<FmtF32>(strip, chains, blocks, a, st);
 }
 
 hipError_t launch_align_plain(int dtype, int strip, const AlignArgs& a, hipStream_t st) {
@@ -445,9 +561,9 @@ hipError_t launch_align_plain(int dtype, int strip, const AlignArgs& a, hipStrea
                            : launch_plain_f<FmtF32>(strip, a, st);
 }
 
-size_t skew_lds_bytes(int dtype, int strip, int max_m) {
-  return dtype == SDTW_I16 ? skew_bytes_f<FmtI16>(strip, max_m)
-                           : skew_bytes_f<FmtF32>(strip, max_m);
+size_t skew_lds_bytes(int dtype, int strip, int chains, int max_m) {
+  return dtype == SDTW_I16 ? skew_bytes_f<FmtI16>(strip, chains, max_m)
+                           : skew_bytes_f<FmtF32>(strip, chains, max_m);
 }
 
 size_t plain_lds_bytes(int dtype, int strip, int max_m) {

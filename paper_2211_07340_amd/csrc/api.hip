@@ -25,14 +25,14 @@ struct sdtw_plan_s {
   int dtype;
   int32_t nq;
   int32_t max_m;
-  int32_t nbig, nsmall;      // reads with M >= kSkewMinM / shorter
-  int32_t max_m_big, max_m_small;
-  int64_t* offs_dev;         // [nq+1]
-  int32_t* order_dev;        // [nq]: long reads longest first, then short reads
-  int32_t* counter_dev;      // [1]
-  int strip;                 // columns per lane
-  int waves_per_cu;          // persistent grid density
-  int cus;                   // compute units of the device
+  std::vector<int32_t> sorted_m;  // read lengths, longest first (order_dev's order)
+  int64_t* offs_dev;              // [nq+1]
+  int32_t* order_dev;             // [nq]: read indices, longest first
+  int32_t* counter_dev;           // [1]
+  int strip;                      // columns per lane
+  int chains;                     // most chains per lane (K) the long reads use
+  int waves_per_cu;               // persistent grid density
+  int cus;                        // compute units of the device
 };
 
 namespace sdtw {
@@ -205,11 +205,42 @@ int sdtw_free_reference(sdtw_ref ref) {
 // plans
 // ---------------------------------------------------------------------------
 
+// One launch of the batch: reads order[first, first + count), all with
+// lengths in [min_m, max_m], run by the skew kernel with `chains` chains per
+// lane (chains == 0: the synchronised single-wave kernel).
+struct LaunchGroup {
+  int32_t first, count, max_m, chains;
+};
+
+static std::vector<LaunchGroup> launch_groups(const sdtw_plan_s* p) {
+  std::vector<LaunchGroup> g;
+  int32_t pos = 0;
+  const int32_t n = p->nq;
+  for (int k = p->chains; k >= 1; k /= 2) {
+    if (!valid_strip_chains(p->strip, k)) continue;
+    const int32_t lo = skew_min_m(k);
+    const int32_t start = pos;
+    while (pos < n && p->sorted_m[pos] >= lo) ++pos;
+    if (pos > start) g.push_back({start, pos - start, p->sorted_m[start], k});
+  }
+  if (pos < n) g.push_back({pos, n - pos, p->sorted_m[pos], 0});
+  return g;
+}
+
 static void choose_config(sdtw_plan_s* p) {
   p->strip = 16;
+  // Chains per lane follow occupancy.  Each lane's row is a serial chain of
+  // dependent instructions (about 10 cycles apart on gfx950); four or more
+  // waves per SIMD hide that and the kernel is issue-bound, so one chain
+  // suffices.  With fewer reads two chains per lane supply independent work
+  // (measured: 1,024 reads x 10 M columns run 12% faster with 2 than with 1;
+  // 4 chains lose to the 256 tile-switch steps they need per period).
+  const int64_t simds = (int64_t)p->cus * 4;
+  p->chains = p->nq >= 4 * simds ? 1 : 2;
   // resident waves per CU: limited by LDS (the CU holds 160 KiB) and capped
-  // at 16 (four per SIMD), enough to hide LDS and DPP latency
-  const size_t per = skew_lds_bytes(p->dtype, p->strip, std::max(p->max_m_big, kSkewMinM));
+  // at 16 (four per SIMD)
+  const size_t per = skew_lds_bytes(p->dtype, p->strip, p->chains,
+                                    std::max(p->max_m, skew_min_m(p->chains)));
   int w = (int)std::min<size_t>(16, (160 * 1024) / std::max<size_t>(per, 1));
   p->waves_per_cu = std::max(w, 1);
 }
@@ -219,41 +250,29 @@ int sdtw_plan_create(const int64_t* offsets_host, int32_t nq, int dtype, sdtw_pl
   SDTW_REQUIRE(nq >= 1, "sdtw_plan_create: nq=%d < 1", nq);
   SDTW_REQUIRE(dtype == SDTW_F32 || dtype == SDTW_I16, "sdtw_plan_create: bad dtype %d", dtype);
   SDTW_REQUIRE(offsets_host[0] >= 0, "sdtw_plan_create: negative offset");
-  std::vector<int32_t> big, small;
-  int32_t max_big = 0, max_small = 0;
+  std::vector<int32_t> order((size_t)nq);
+  int32_t max_m = 0;
   for (int32_t r = 0; r < nq; ++r) {
     const int64_t m = offsets_host[r + 1] - offsets_host[r];
     SDTW_REQUIRE(m >= 1 && m <= SDTW_MAX_QUERY,
                  "sdtw_plan_create: read %d has length %lld outside [1, %d]", r, (long long)m,
                  SDTW_MAX_QUERY);
-    if (m >= kSkewMinM) {
-      big.push_back(r);
-      max_big = std::max<int32_t>(max_big, (int32_t)m);
-    } else {
-      small.push_back(r);
-      max_small = std::max<int32_t>(max_small, (int32_t)m);
-    }
+    order[(size_t)r] = r;
+    max_m = std::max<int32_t>(max_m, (int32_t)m);
   }
-  auto longer = [&](int32_t a, int32_t b) {
-    const int64_t ma = offsets_host[a + 1] - offsets_host[a];
-    const int64_t mb = offsets_host[b + 1] - offsets_host[b];
-    return ma != mb ? ma > mb : a < b;
-  };
-  std::sort(big.begin(), big.end(), longer);
-  std::sort(small.begin(), small.end(), longer);
-  std::vector<int32_t> order(big);
-  order.insert(order.end(), small.begin(), small.end());
+  auto len = [&](int32_t r) { return offsets_host[r + 1] - offsets_host[r]; };
+  std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return len(a) != len(b) ? len(a) > len(b) : a < b;
+  });
 
   sdtw_plan_s* p = new (std::nothrow) sdtw_plan_s();
   if (!p) return set_error(SDTW_ENOMEM, "sdtw_plan_create: host allocation");
   p->device = current_device();
   p->dtype = dtype;
   p->nq = nq;
-  p->nbig = (int32_t)big.size();
-  p->nsmall = (int32_t)small.size();
-  p->max_m_big = max_big;
-  p->max_m_small = max_small;
-  p->max_m = std::max(max_big, max_small);
+  p->max_m = max_m;
+  p->sorted_m.resize((size_t)nq);
+  for (int32_t i = 0; i < nq; ++i) p->sorted_m[(size_t)i] = (int32_t)len(order[(size_t)i]);
   p->cus = cu_count();
   if (p->cus <= 0) p->cus = 256;
   choose_config(p);
@@ -286,20 +305,29 @@ int sdtw_plan_info(sdtw_plan plan, int32_t* nq, int* dtype, int32_t* max_m) {
   return SDTW_OK;
 }
 
-int sdtw_plan_set_config(sdtw_plan plan, int strip, int waves_per_cu) {
+int sdtw_plan_set_config(sdtw_plan plan, int strip, int chains, int waves_per_cu) {
   SDTW_REQUIRE(plan, "sdtw_plan_set_config: null plan");
   SDTW_REQUIRE(strip == 0 || valid_strip(strip), "sdtw_plan_set_config: strip %d not in {8,16,32}",
                strip);
+  SDTW_REQUIRE(chains == 0 || chains == 1 || chains == 2 || chains == 4,
+               "sdtw_plan_set_config: chains %d not in {1,2,4}", chains);
   SDTW_REQUIRE(waves_per_cu >= 0 && waves_per_cu <= 32,
                "sdtw_plan_set_config: waves_per_cu %d outside [0, 32]", waves_per_cu);
-  if (strip) plan->strip = strip;
+  const int s2 = strip ? strip : plan->strip;
+  const int k2 = chains ? chains : plan->chains;
+  SDTW_REQUIRE(valid_strip_chains(s2, k2),
+               "sdtw_plan_set_config: strip %d with %d chains (strip/chains must be a multiple "
+               "of 4)", s2, k2);
+  plan->strip = s2;
+  plan->chains = k2;
   if (waves_per_cu) plan->waves_per_cu = waves_per_cu;
   return SDTW_OK;
 }
 
-int sdtw_plan_get_config(sdtw_plan plan, int* strip, int* waves_per_cu) {
+int sdtw_plan_get_config(sdtw_plan plan, int* strip, int* chains, int* waves_per_cu) {
   SDTW_REQUIRE(plan, "sdtw_plan_get_config: null plan");
   if (strip) *strip = plan->strip;
+  if (chains) *chains = plan->chains;
   if (waves_per_cu) *waves_per_cu = plan->waves_per_cu;
   return SDTW_OK;
 }
@@ -326,13 +354,14 @@ int sdtw_align_batch(sdtw_ref ref, sdtw_plan plan, const void* q_dev, void* cost
   SDTW_REQUIRE(ref->dtype == plan->dtype, "sdtw_align_batch: reference dtype %d != plan dtype %d",
                ref->dtype, plan->dtype);
   SDTW_REQUIRE(valid_strip(plan->strip), "sdtw_align_batch: bad strip");
-  const size_t lds_big = plan->nbig ? skew_lds_bytes(plan->dtype, plan->strip, plan->max_m_big) : 0;
-  const size_t lds_small =
-      plan->nsmall ? plain_lds_bytes(plan->dtype, plan->strip, plan->max_m_small) : 0;
+  const std::vector<LaunchGroup> groups = launch_groups(plan);
   const size_t lds_max = (size_t)max_lds_bytes();
-  SDTW_REQUIRE(lds_big <= lds_max && lds_small <= lds_max,
-               "sdtw_align_batch: %zu bytes of LDS needed, %zu available",
-               std::max(lds_big, lds_small), lds_max);
+  for (const LaunchGroup& g : groups) {
+    const size_t lds = g.chains ? skew_lds_bytes(plan->dtype, plan->strip, g.chains, g.max_m)
+                                : plain_lds_bytes(plan->dtype, plan->strip, g.max_m);
+    SDTW_REQUIRE(lds <= lds_max, "sdtw_align_batch: %zu bytes of LDS needed, %zu available", lds,
+                 lds_max);
+  }
   hipStream_t st = (hipStream_t)stream;
   AlignArgs a{};
   a.ref = ref->data;
@@ -342,21 +371,19 @@ int sdtw_align_batch(sdtw_ref ref, sdtw_plan plan, const void* q_dev, void* cost
   a.counter = plan->counter_dev;
   a.cost = cost_dev;
   a.end = end_dev;
-  if (plan->nbig) {
-    a.order = plan->order_dev;
-    a.nwork = plan->nbig;
-    a.max_m = plan->max_m_big;
-    const int blocks = std::min<int64_t>((int64_t)plan->cus * plan->waves_per_cu, plan->nbig);
-    int rc = check_hip(launch_align_skew(plan->dtype, plan->strip, blocks, a, st),
-                       "sdtw_align_batch: launch");
-    if (rc) return rc;
-  }
-  if (plan->nsmall) {
-    a.order = plan->order_dev + plan->nbig;
-    a.nwork = plan->nsmall;
-    a.max_m = plan->max_m_small;
-    int rc = check_hip(launch_align_plain(plan->dtype, plan->strip, a, st),
-                       "sdtw_align_batch: launch");
+  for (const LaunchGroup& g : groups) {
+    a.order = plan->order_dev + g.first;
+    a.nwork = g.count;
+    a.max_m = g.max_m;
+    int rc;
+    if (g.chains) {
+      const int blocks = (int)std::min<int64_t>((int64_t)plan->cus * plan->waves_per_cu, g.count);
+      rc = check_hip(launch_align_skew(plan->dtype, plan->strip, g.chains, blocks, a, st),
+                     "sdtw_align_batch: launch");
+    } else {
+      rc = check_hip(launch_align_plain(plan->dtype, plan->strip, a, st),
+                     "sdtw_align_batch: launch");
+    }
     if (rc) return rc;
   }
   return SDTW_OK;

@@ -20,9 +20,18 @@ constexpr int64_t kPadUnit = int64_t(kLanes) * kMaxStrip;
 // Offset that maps int16 onto [0, 65535]; |x - y| is translation invariant.
 constexpr uint32_t kI16Bias = 32768u;
 
-// Shortest read the continuous-skew kernel takes (its one-step-ahead LDS
-// prefetch needs lane 63's boundary write two steps before lane 0's read).
-constexpr int32_t kSkewMinM = 65;
+// Shortest read the continuous-skew kernel takes with K chains per lane: its
+// one-step-ahead LDS prefetch needs the last sub-lane's boundary write two
+// steps before lane 0's read, i.e. M >= 64K + 1.
+inline int32_t skew_min_m(int chains) { return 64 * chains + 1; }
+
+// Strip widths and chains-per-lane the skew kernel is built for: W in
+// {8, 16, 32}, K in {1, 2, 4}, W / K a multiple of 4.
+inline bool valid_strip_chains(int strip, int chains) {
+  if (strip != 8 && strip != 16 && strip != 32) return false;
+  if (chains != 1 && chains != 2 && chains != 4) return false;
+  return (strip / chains) % 4 == 0;
+}
 
 inline int64_t padded_length(int64_t n) {
   return ((n + kPadUnit - 1) / kPadUnit) * kPadUnit + kPadUnit;
@@ -54,12 +63,13 @@ struct AlignArgs {
   int32_t* end;          // int32[nq]
   int32_t single_m;      // used when offs == nullptr: one read of this length
 };
-// Continuous-skew persistent kernel; every read in the list must have M >= 65.
-hipError_t launch_align_skew(int dtype, int strip, int blocks, const AlignArgs& a,
+// Continuous-skew persistent kernel with `chains` chains per lane; every read
+// in the list must have M >= skew_min_m(chains).
+hipError_t launch_align_skew(int dtype, int strip, int chains, int blocks, const AlignArgs& a,
                              hipStream_t st);
 // Synchronised-tile single-wave kernel; any M >= 1; one block per work item.
 hipError_t launch_align_plain(int dtype, int strip, const AlignArgs& a, hipStream_t st);
-size_t skew_lds_bytes(int dtype, int strip, int max_m);
+size_t skew_lds_bytes(int dtype, int strip, int chains, int max_m);
 size_t plain_lds_bytes(int dtype, int strip, int max_m);
 int max_lds_bytes();
 

@@ -42,11 +42,11 @@ def small_ref():
     return w, z, codes, qz, qc
 
 
-def gpu_batch(dev, ref_np, q_np, offs, dtype, strip=0, waves=0):
+def gpu_batch(dev, ref_np, q_np, offs, dtype, strip=0, waves=0, chains=0):
     ref = sd.Reference(torch.from_numpy(np.ascontiguousarray(ref_np)).to(dev))
     plan = sd.Plan(offs, dtype)
-    if strip or waves:
-        plan.set_config(strip, waves)
+    if strip or waves or chains:
+        plan.set_config(strip, chains, waves)
     cost, end = sd.align_batch(ref, plan, torch.from_numpy(np.ascontiguousarray(q_np)).to(dev))
     torch.cuda.synchronize()
     out = cost.cpu().numpy(), end.cpu().numpy()
@@ -114,14 +114,15 @@ def test_batch_64_reads_small_reference(dev, small_ref):
               index=np.arange(0, 64, 8))
 
 
-@pytest.mark.parametrize("strip", [8, 16, 32])
+@pytest.mark.parametrize("strip,chains", [(8, 1), (8, 2), (16, 1), (16, 2), (16, 4), (32, 1),
+                                          (32, 2), (32, 4)])
 @pytest.mark.parametrize("waves", [1, 3, 16])
-def test_schedule_invariance(dev, small_ref, strip, waves):
+def test_schedule_invariance(dev, small_ref, strip, chains, waves):
     w, z, codes, qz, qc = small_ref
     offs = w.reads.offsets[:17]
-    note(f"schedule strip={strip} waves={waves}")
-    check_i16(gpu_batch(dev, codes, qc, offs, sd.I16, strip, waves), qc, offs, codes)
-    check_f32(gpu_batch(dev, z, qz, offs, sd.F32, strip, waves), qz, offs, z, f64=False)
+    note(f"schedule strip={strip} chains={chains} waves={waves}")
+    check_i16(gpu_batch(dev, codes, qc, offs, sd.I16, strip, waves, chains), qc, offs, codes)
+    check_f32(gpu_batch(dev, z, qz, offs, sd.F32, strip, waves, chains), qz, offs, z, f64=False)
 
 
 def _ragged_case(seed, Ms, N, lo=-3000, hi=3000):
@@ -135,16 +136,16 @@ def _ragged_case(seed, Ms, N, lo=-3000, hi=3000):
 @pytest.mark.parametrize("N", [1, 7, 63, 64, 65, 511, 512, 513, 1023, 1024, 1025, 2047, 2048,
                                2049, 5000])
 def test_edge_lengths_int16(dev, N):
-    Ms = [1, 2, 5, 33, 63, 64, 65, 66, 100, 127, 128, 129, 250, 700]
+    Ms = [1, 2, 5, 33, 63, 64, 65, 66, 100, 127, 128, 129, 130, 250, 256, 257, 258, 700]
     ref, q, offs = _ragged_case(N, Ms, N)
     note(f"edge int16 N={N} Ms={Ms}")
-    for strip in (8, 16, 32):
-        check_i16(gpu_batch(dev, ref, q, offs, sd.I16, strip, 2), q, offs, ref)
+    for strip, chains in ((8, 2), (16, 1), (16, 2), (16, 4), (32, 2), (32, 4)):
+        check_i16(gpu_batch(dev, ref, q, offs, sd.I16, strip, 2, chains), q, offs, ref)
 
 
 @pytest.mark.parametrize("N", [1, 65, 1025, 3001])
 def test_edge_lengths_float32(dev, N):
-    Ms = [1, 3, 63, 64, 65, 200, 1500]
+    Ms = [1, 3, 63, 64, 65, 129, 200, 257, 1500]
     rng = np.random.default_rng(N + 7)
     ref = rng.normal(size=N).astype(np.float32)
     qs = [rng.normal(size=m).astype(np.float32) for m in Ms]
