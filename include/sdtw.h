@@ -125,6 +125,18 @@ int sdtw_prepare_queries(const float* raw_dev, const int64_t* offsets_dev,
                          int32_t nq, double scale, float* z_dev,
                          int16_t* codes_dev, int64_t* nsat_dev, void* stream);
 
+/*
+ * sdtw_prepare_queries with explicit statistics, for reads that arrive in
+ * chunks: every chunk of a read must be scaled like its first one so that
+ * extending a resident row equals aligning the concatenated read.
+ *   stats_in_dev   double[2 nq] (mean, sd) per read to apply, or NULL to
+ *                  use each read's own statistics as sdtw_prepare_queries.
+ *   stats_out_dev  double[2 nq] receiving the (mean, sd) applied, or NULL.
+ */
+int sdtw_prepare_queries_ex(const float* raw_dev, const int64_t* offsets_dev, int32_t nq,
+                            double scale, const double* stats_in_dev, double* stats_out_dev,
+                            float* z_dev, int16_t* codes_dev, int64_t* nsat_dev, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Reference handle                                                          */
 /* ------------------------------------------------------------------------ */
@@ -211,6 +223,66 @@ int sdtw_align_batch(sdtw_ref ref, sdtw_plan plan, const void* q_dev,
  */
 int sdtw_align_one(sdtw_ref ref, const void* q_dev, int32_t M, void* cost_dev,
                    int32_t* end_dev, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Streaming extension (Read Until: section 2.2 rejection before most of a   */
+/* read is sequenced; section 4.1 reads arrive as the sequencer produces     */
+/* them)                                                                     */
+/* ------------------------------------------------------------------------ */
+/*
+ * A stream holds one read's resident DP row gamma(m, 0..N-1) for the m query
+ * rows folded in so far (row i depends only on X[1..i], section 2.3 Eq. 1),
+ * so extending it by a chunk of k new events computes rows m+1..m+k only,
+ * with results identical to aligning the concatenated m+k events from
+ * scratch.  Normalisation is the caller's: a read's chunks must be scaled
+ * with statistics fixed by its first chunk (see sdtw_prepare_queries_ex).
+ *
+ * Rows come from a per-device pool with a byte budget; a row is N padded x
+ * 4 bytes.  Closed rows are cached for reuse and released when a row of
+ * another size needs their room.
+ */
+
+/* Byte budget of resident rows on the current device (default 16 GiB). */
+int sdtw_set_row_budget(int64_t bytes);
+int sdtw_row_budget_info(int64_t* budget, int64_t* in_use, int64_t* cached);
+
+/*
+ * Open a stream on `ref` (its dtype applies).  SDTW_EBUDGET when the row
+ * would exceed the budget (nothing allocated; retry after closing others),
+ * SDTW_ENOMEM when the device allocation fails.  The reference cannot be
+ * freed while streams are open on it.
+ */
+int sdtw_stream_open(sdtw_ref ref, sdtw_stream* out);
+
+/* Rows folded in so far and the reference length. */
+int sdtw_stream_info(sdtw_stream s, int32_t* rows, int64_t* n);
+
+/*
+ * Close a stream and return its row to the pool.  Waits for enqueued work
+ * that uses the row.  The handle is invalid afterwards.
+ */
+int sdtw_stream_close(sdtw_stream s);
+
+/*
+ * Copy the resident row (N values: int32 costs for SDTW_I16, float32 for
+ * SDTW_F32) to device memory `dst_dev`, asynchronously on `stream`.
+ * SDTW_ESTATE when the stream has no rows yet.
+ */
+int sdtw_stream_copy_row(sdtw_stream s, void* dst_dev, void* stream);
+
+/*
+ * Extend `ns` distinct streams by one chunk each in one launch (continuous
+ * batching).  Chunk i is chunk_dev[offsets[i] .. offsets[i+1]) (int16 or
+ * float32 values of the reference's dtype), 1 <= length <= SDTW_MAX_QUERY;
+ * a stream's total rows stay <= 32,767 on the int16 path.  All streams
+ * must share one reference.  Outputs, per stream in call order: the cost
+ * and 0-based end of the new last row (as sdtw_align_batch).  A stream's
+ * row count advances when the call returns; calls on the same streams must
+ * be issued in order on one HIP stream (or ordered by the caller).
+ */
+int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk_dev,
+                       const int64_t* chunk_offsets_host, void* cost_dev, int32_t* end_dev,
+                       void* stream);
 
 #ifdef __cplusplus
 }

@@ -10,7 +10,8 @@ What it computes (each function cites the passage it follows):
 * ``kmer_signal``   -- k-mer model conversion of a genome into the expected
   current for the forward and reverse-complement strands (section 2.2, k-mer
   model lookup over a sliding window; section 4.1, both strands).
-* ``znorm``         -- z-score normalisation, statistics in double (section 4.1).
+* ``znorm``         -- z-score normalisation, statistics in double (section 4.1);
+  ``zstats`` / ``zapply`` split it for reads that arrive in chunks.
 * ``quantize``      -- fixed-point scaling to int16 (section 4.1; section 4.3,
   fixed-point data representation).
 * ``sdtw_i64``, ``sdtw_f32``, ``sdtw_f64`` -- sDTW cost and end position
@@ -63,6 +64,10 @@ def _load():
     lib.oracle_kmer_signal.restype = i64
     lib.oracle_znorm.argtypes = [p, i64, p]
     lib.oracle_znorm.restype = None
+    lib.oracle_zstats.argtypes = [p, i64, p]
+    lib.oracle_zstats.restype = None
+    lib.oracle_zapply.argtypes = [p, i64, C.c_double, C.c_double, p]
+    lib.oracle_zapply.restype = None
     lib.oracle_quantize.argtypes = [p, i64, C.c_double, p]
     lib.oracle_quantize.restype = i64
     for name in ("oracle_sdtw_i64", "oracle_sdtw_f32", "oracle_sdtw_f64"):
@@ -100,6 +105,23 @@ def znorm(v: np.ndarray) -> np.ndarray:
     out = np.empty_like(a)
     if a.size:
         _load().oracle_znorm(_ptr(a), a.size, _ptr(out))
+    return out
+
+
+def zstats(v: np.ndarray):
+    """(mean, population sd) of v, accumulated in double in index order."""
+    a = np.ascontiguousarray(v, dtype=np.float32)
+    out = np.zeros(2, np.float64)
+    _load().oracle_zstats(_ptr(a), a.size, _ptr(out))
+    return float(out[0]), float(out[1])
+
+
+def zapply(v: np.ndarray, mean: float, sd: float) -> np.ndarray:
+    """(v - mean) / sd in double, rounded to float32 (zeros when sd == 0)."""
+    a = np.ascontiguousarray(v, dtype=np.float32)
+    out = np.empty_like(a)
+    if a.size:
+        _load().oracle_zapply(_ptr(a), a.size, float(mean), float(sd), _ptr(out))
     return out
 
 

@@ -89,6 +89,30 @@ void oracle_znorm(const float* v, int64_t n, float* out) {
 }
 
 /*
+ * The same z-score split in two: the statistics of v (mean and population
+ * sd, accumulated in double in index order), and their application to any
+ * values (used for a read that arrives in chunks: every chunk is scaled with
+ * the statistics of the read's first chunk).
+ */
+void oracle_zstats(const float* v, int64_t n, double* mean_sd) {
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) s += (double)v[i];
+  double mean = s / (double)n;
+  double ss = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    double d = (double)v[i] - mean;
+    ss += d * d;
+  }
+  mean_sd[0] = mean;
+  mean_sd[1] = sqrt(ss / (double)n);
+}
+
+void oracle_zapply(const float* v, int64_t n, double mean, double sd, float* out) {
+  for (int64_t i = 0; i < n; ++i)
+    out[i] = (sd > 0.0) ? (float)(((double)v[i] - mean) / sd) : 0.0f;
+}
+
+/*
  * Fixed-point scaling (section 4.1, section 4.3 "fixed-point data
  * representation"): code = saturate_int16(round_half_even(z * scale)), the
  * product taken in double.  Returns the number of saturated values.

@@ -5,10 +5,12 @@ Python binding of the C ABI in ``include/sdtw.h`` (``libsdtw.so``, built by
 This module only marshals arguments: every step runs in the HIP library.
 Device memory and streams come from PyTorch (``torch.cuda``).
 """
-from .binding import (F32, I16, Plan, Reference, SdtwError, align_batch, align_one,
-                      library_path, load_library, prepare_queries, prepare_reference,
+from .binding import (F32, I16, Plan, Reference, SdtwError, Stream, align_batch, align_one,
+                      library_path, load_library, prepare_queries, prepare_queries_ex,
+                      prepare_reference, row_budget_info, set_row_budget, stream_extend,
                       version)
 
-__all__ = ["F32", "I16", "Plan", "Reference", "SdtwError", "align_batch", "align_one",
-           "library_path", "load_library", "prepare_queries", "prepare_reference",
-           "version"]
+__all__ = ["F32", "I16", "Plan", "Reference", "SdtwError", "Stream", "align_batch",
+           "align_one", "library_path", "load_library", "prepare_queries",
+           "prepare_queries_ex", "prepare_reference", "row_budget_info", "set_row_budget",
+           "stream_extend", "version"]

@@ -55,6 +55,14 @@ def load_library():
         "sdtw_plan_destroy": ([p], C.c_int),
         "sdtw_align_batch": ([p, p, p, p, p, p], C.c_int),
         "sdtw_align_one": ([p, p, i32, p, p, p], C.c_int),
+        "sdtw_prepare_queries_ex": ([p, p, i32, dbl, p, p, p, p, p, p], C.c_int),
+        "sdtw_set_row_budget": ([i64], C.c_int),
+        "sdtw_row_budget_info": ([C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)], C.c_int),
+        "sdtw_stream_open": ([p, C.POINTER(p)], C.c_int),
+        "sdtw_stream_info": ([p, C.POINTER(i32), C.POINTER(i64)], C.c_int),
+        "sdtw_stream_close": ([p], C.c_int),
+        "sdtw_stream_copy_row": ([p, p, p], C.c_int),
+        "sdtw_stream_extend": ([p, i32, p, p, p, p, p], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -142,6 +150,25 @@ def prepare_queries(raw, offsets, scale: float = 64.0, stream=None):
                                     _dev(offsets, torch.int64, "offsets"), nq, float(scale),
                                     _dev(z), _dev(codes), _dev(nsat), _stream(stream)))
     return z, codes, nsat
+
+
+def prepare_queries_ex(raw, offsets, scale: float = 64.0, stats_in=None, stream=None):
+    """sdtw_prepare_queries_ex: as prepare_queries, with fixed per-read
+    statistics (float64 device tensor [nq, 2] of (mean, sd)) if given.
+    Returns (z, codes, nsat, stats) where stats are the (mean, sd) applied."""
+    torch = _torch()
+    lib = load_library()
+    nq = offsets.numel() - 1
+    z = torch.empty_like(raw)
+    codes = torch.empty(raw.numel(), dtype=torch.int16, device=raw.device)
+    nsat = torch.empty(1, dtype=torch.int64, device=raw.device)
+    stats = torch.empty((nq, 2), dtype=torch.float64, device=raw.device)
+    sin = None if stats_in is None else _dev(stats_in, torch.float64, "stats_in")
+    _check(lib.sdtw_prepare_queries_ex(_dev(raw, torch.float32, "raw"),
+                                       _dev(offsets, torch.int64, "offsets"), nq, float(scale),
+                                       sin, _dev(stats), _dev(z), _dev(codes), _dev(nsat),
+                                       _stream(stream)))
+    return z, codes, nsat, stats
 
 
 # ---------------------------------------------------------------------------
@@ -257,4 +284,83 @@ def align_one(ref: Reference, q, cost=None, end=None, stream=None):
     cost, end = _outputs(1, ref.dtype, q.device, cost, end)
     _check(load_library().sdtw_align_one(ref.handle, _dev(q, qdt, "q"), q.numel(), _dev(cost),
                                          _dev(end, torch.int32, "end"), _stream(stream)))
+    return cost, end
+
+
+# ---------------------------------------------------------------------------
+# streaming extension
+# ---------------------------------------------------------------------------
+
+def set_row_budget(nbytes: int):
+    """Byte budget of resident rows on the current device."""
+    _check(load_library().sdtw_set_row_budget(int(nbytes)))
+
+
+def row_budget_info():
+    """(budget, in_use, cached) bytes on the current device."""
+    b, u, c = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(load_library().sdtw_row_budget_info(C.byref(b), C.byref(u), C.byref(c)))
+    return b.value, u.value, c.value
+
+
+class Stream:
+    """One read extended chunk by chunk over a resident DP row."""
+
+    def __init__(self, ref: Reference):
+        h = C.c_void_p()
+        _check(load_library().sdtw_stream_open(ref.handle, C.byref(h)))
+        self._h = h
+        self.ref = ref
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise SdtwError(5, "stream is closed")
+        return self._h
+
+    @property
+    def rows(self) -> int:
+        r, n = C.c_int32(), C.c_int64()
+        _check(load_library().sdtw_stream_info(self.handle, C.byref(r), C.byref(n)))
+        return r.value
+
+    def copy_row(self, out=None, stream=None):
+        """The resident row gamma(rows, .) as an int32 / float32 device tensor."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.ref.n, dtype=torch.int32 if self.ref.dtype == I16
+                              else torch.float32, device="cuda")
+        _check(load_library().sdtw_stream_copy_row(self.handle, _dev(out), _stream(stream)))
+        return out
+
+    def close(self):
+        if self._h is not None:
+            _check(load_library().sdtw_stream_close(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def stream_extend(streams, chunks, offsets, cost=None, end=None, stream=None):
+    """sdtw_stream_extend: extend each stream by its chunk (CSR ``chunks`` on
+    the device, host ``offsets``); returns (cost, end) device tensors."""
+    torch = _torch()
+    lib = load_library()
+    ns = len(streams)
+    if ns == 0:
+        raise ValueError("no streams")
+    offs = _offsets_host(offsets)
+    if offs.size != ns + 1:
+        raise ValueError("offsets must have len(streams) + 1 entries")
+    dt = streams[0].ref.dtype
+    qdt = torch.int16 if dt == I16 else torch.float32
+    cost, end = _outputs(ns, dt, chunks.device, cost, end)
+    handles = (C.c_void_p * ns)(*[s.handle for s in streams])
+    _check(lib.sdtw_stream_extend(handles, ns, _dev(chunks, qdt, "chunks"),
+                                  offs.ctypes.data_as(C.c_void_p), _dev(cost),
+                                  _dev(end, torch.int32, "end"), _stream(stream)))
     return cost, end

@@ -203,13 +203,15 @@ __device__ __forceinline__ void load_strip(uint32_t (&dst)[W], const uint32_t* _
 // Continuous-skew kernel
 // ---------------------------------------------------------------------------
 
-template <class F, int W, int K>
+template <class F, int W, int K, bool STREAM>
 struct SkewLds {
-  static constexpr int kStage = 64 * W;  // per-lane strips: next tile / last rows
-  static constexpr int kZeros = W;
-  // query/boundary pairs: max_m + 64K entries of 8 bytes
+  static constexpr int kStage = 64 * W;             // next tile's strips / finished last rows
+  static constexpr int kAcc = STREAM ? 64 * W : 0;  // next tile's resident-row strips
+  static constexpr int kLeft = STREAM ? 64 : 0;     // resident value left of each strip
+  static constexpr int kZeros = STREAM ? 0 : W;     // gamma(0, .) = 0 for fresh reads
+  // + query/boundary pairs: max_m + 64K entries of 8 bytes
   static size_t bytes(int max_m) {
-    size_t b = 4 * ((size_t)kStage + kZeros) + 8 * ((size_t)max_m + 64 * K);
+    size_t b = 4 * ((size_t)kStage + kAcc + kLeft + kZeros) + 8 * ((size_t)max_m + 64 * K);
     return (b + 15) & ~(size_t)15;
   }
 };
@@ -232,8 +234,17 @@ struct SkewLds {
 // entry 64K - 1 + r, and the last sub-lane (lane 63, chain K-1) writes its
 // boundary row r - (64K - 1) at entry r, its own entry (at r + M while that
 // row is in the previous period).
-template <class F, int W, int K>
+//
+// STREAM: each work item extends a resident row acc = gamma(m_old, .) by the
+// M rows of one chunk (rows m_old+1 .. m_old+M of the read): when a sub-lane
+// enters a tile its previous row is acc's strip (instead of zeros) and its
+// diagonal is acc one column to the left (+inf left of column 0); the
+// finished last row of every tile is written back to acc.  A tile's acc is
+// staged one period before that tile's write-back, so reads see the row as
+// it was before this extension.
+template <class F, int W, int K, bool STREAM>
 __global__ __launch_bounds__(64) void k_align_skew(AlignArgs args) {
+  using Lay = SkewLds<F, W, K, STREAM>;
   constexpr int T = 64 * W;
   constexpr int H = W / K;
   constexpr int S = 64 * K;                   // sub-lanes = switch steps per period
@@ -242,12 +253,17 @@ __global__ __launch_bounds__(64) void k_align_skew(AlignArgs args) {
   extern __shared__ __align__(16) uint32_t smem[];
   const int lane = (int)threadIdx.x;
   uint32_t* const stage = smem;
-  uint32_t* const zeros = stage + SkewLds<F, W, K>::kStage;
-  uint2* const bx = (uint2*)(zeros + SkewLds<F, W, K>::kZeros);
+  uint32_t* const accst = stage + Lay::kStage;
+  uint32_t* const accleft = accst + Lay::kAcc;
+  uint32_t* const zeros = accleft + Lay::kLeft;
+  uint2* const bx = (uint2*)(zeros + Lay::kZeros);
   uint32_t* const my_stage = stage + lane * W;
+  uint32_t* const my_acc = accst + lane * W;
   uint2* const bxl = bx + K * (63 - lane);
 
-  if (lane < W) zeros[lane] = 0u;
+  if constexpr (!STREAM) {
+    if (lane < W) zeros[lane] = 0u;
+  }
   const int32_t N = (int32_t)args.n;
   const int32_t ntiles = (N + T - 1) / T;
 
@@ -260,11 +276,42 @@ __global__ __launch_bounds__(64) void k_align_skew(AlignArgs args) {
     int32_t item = atomicAdd(args.counter, lane == 0 ? 1 : 0);
     item = __builtin_amdgcn_readfirstlane(item);
     if (item >= args.nwork) break;
-    const int32_t rd = __builtin_amdgcn_readfirstlane(args.order ? args.order[item] : item);
-    const int64_t q0 = args.offs ? args.offs[rd] : 0;
-    const int32_t M = __builtin_amdgcn_readfirstlane(
-        args.offs ? (int32_t)(args.offs[rd + 1] - q0) : args.single_m);
+    int32_t rd, M, m_old = 0;
+    int64_t q0;
+    uint32_t* acc = nullptr;
+    if constexpr (STREAM) {
+      const StreamItem it = args.items[item];
+      q0 = it.q0;
+      M = __builtin_amdgcn_readfirstlane(it.m);
+      m_old = __builtin_amdgcn_readfirstlane(it.m_old);
+      rd = __builtin_amdgcn_readfirstlane(it.out);
+      acc = it.acc;
+    } else {
+      rd = __builtin_amdgcn_readfirstlane(args.order ? args.order[item] : item);
+      q0 = args.offs ? args.offs[rd] : 0;
+      M = __builtin_amdgcn_readfirstlane(args.offs ? (int32_t)(args.offs[rd + 1] - q0)
+                                                   : args.single_m);
+    }
     const typename F::qin* __restrict__ qv = (const typename F::qin*)args.q + q0;
+    // resident row of tile t into this lane's LDS strip (and the value left
+    // of the strip); a fresh read (m_old == 0) stages gamma(0, .) = 0
+    auto stage_acc = [&](int32_t t) {
+      if constexpr (STREAM) {
+        const int64_t c0 = (int64_t)t * T + lane * W;
+        uint32_t v[W];
+        uint32_t left = F::kInf;
+        if (m_old > 0) {
+          load_strip<W>(v, acc + c0);
+          if (c0 > 0) left = acc[c0 - 1];
+        } else {
+#pragma unroll
+          for (int w = 0; w < W; ++w) v[w] = 0u;
+        }
+#pragma unroll
+        for (int w = 0; w < W; ++w) my_acc[w] = v[w];
+        accleft[lane] = left;
+      }
+    };
 
     __syncthreads();  // previous read's LDS use is complete
     for (int k = lane; k < M + S; k += 64) {
@@ -278,6 +325,7 @@ __global__ __launch_bounds__(64) void k_align_skew(AlignArgs args) {
 #pragma unroll
       for (int w = 0; w < W; ++w) my_stage[w] = t0[w];
     }
+    stage_acc(0);
     __syncthreads();
 
     uint32_t y[W], a[W], b[W], dprev[K];
@@ -313,11 +361,12 @@ __global__ __launch_bounds__(64) void k_align_skew(AlignArgs args) {
       for (int h = 1; h < K; ++h) left[h] = up[h * H - 1];
       if constexpr (CH >= 0) {
         if (lane == r / K) {
+          const uint32_t* const src = STREAM ? my_acc : zeros;
 #pragma unroll
           for (int w = CH * H; w < (CH + 1) * H; w += 4) {
             const uint4 nv = *(const uint4*)(my_stage + w);
             *(uint4*)(my_stage + w) = make_uint4(up[w], up[w + 1], up[w + 2], up[w + 3]);
-            const uint4 zv = *(const uint4*)(zeros + w);
+            const uint4 zv = *(const uint4*)(src + (STREAM ? w : w - CH * H));
             y[w] = nv.x;
             y[w + 1] = nv.y;
             y[w + 2] = nv.z;
@@ -327,6 +376,7 @@ __global__ __launch_bounds__(64) void k_align_skew(AlignArgs args) {
             up[w + 2] = zv.z;
             up[w + 3] = zv.w;
           }
+          if constexpr (STREAM) dprev[CH] = CH == 0 ? accleft[lane] : my_acc[CH * H - 1];
         }
       }
       uint32_t xs[K];
@@ -353,16 +403,23 @@ __global__ __launch_bounds__(64) void k_align_skew(AlignArgs args) {
                !first || r + u + 1 == S - 1, r + u + 1 != S - 1);
         });
       }
-      // every lane has finished tile p-1: fold its last row, stage tile p+1
+      // every lane has finished tile p-1: fold its last row (and write it
+      // back as the new resident row), stage tile p+1
       if (p >= 1) {
         const int32_t jb = (p - 1) * T + lane * W;
+        uint32_t lr[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-          const uint32_t v = my_stage[w];
-          if (jb + w < N && v < best) {
-            best = v;
+          lr[w] = my_stage[w];
+          if (jb + w < N && lr[w] < best) {
+            best = lr[w];
             bestj = jb + w;
           }
+        }
+        if constexpr (STREAM) {
+#pragma unroll
+          for (int w = 0; w < W; w += 4)
+            *(uint4*)(acc + jb + w) = make_uint4(lr[w], lr[w + 1], lr[w + 2], lr[w + 3]);
         }
       }
       if (p + 1 < ntiles) {
@@ -370,6 +427,7 @@ __global__ __launch_bounds__(64) void k_align_skew(AlignArgs args) {
         load_strip<W>(t1, args.ref + (int64_t)(p + 1) * T + lane * W);
 #pragma unroll
         for (int w = 0; w < W; ++w) my_stage[w] = t1[w];
+        stage_acc(p + 1);
       }
       if (p == ntiles) break;
       // phase B: plain steps, four per iteration
@@ -411,7 +469,11 @@ struct PlainLds {
   }
 };
 
-template <class F, int W>
+// STREAM: as k_align_skew's streaming mode, per tile: the previous row is
+// the resident row's strip and the diagonal the resident value to its left;
+// the finished last row of tile t-1 is written back after tile t's resident
+// values have been read (lane 0 reads the column that lane 63 writes back).
+template <class F, int W, bool STREAM>
 __global__ __launch_bounds__(64) void k_align_plain(AlignArgs args) {
   constexpr int T = 64 * W;
   using X = typename F::xlds;
@@ -424,9 +486,21 @@ __global__ __launch_bounds__(64) void k_align_plain(AlignArgs args) {
   X* const xs = (X*)(B + args.max_m);
   uint32_t* const my_slot = slot + lane * W;
 
-  const int32_t rd = args.order ? args.order[item] : item;
-  const int64_t q0 = args.offs ? args.offs[rd] : 0;
-  const int32_t M = args.offs ? (int32_t)(args.offs[rd + 1] - q0) : args.single_m;
+  int32_t rd, M, m_old = 0;
+  int64_t q0;
+  uint32_t* acc = nullptr;
+  if constexpr (STREAM) {
+    const StreamItem it = args.items[item];
+    q0 = it.q0;
+    M = it.m;
+    m_old = it.m_old;
+    rd = it.out;
+    acc = it.acc;
+  } else {
+    rd = args.order ? args.order[item] : item;
+    q0 = args.offs ? args.offs[rd] : 0;
+    M = args.offs ? (int32_t)(args.offs[rd + 1] - q0) : args.single_m;
+  }
   const typename F::qin* __restrict__ qv = (const typename F::qin*)args.q + q0;
   for (int k = lane; k < M; k += 64) {
     xs[k] = F::to_lds(qv[k]);
@@ -441,9 +515,28 @@ __global__ __launch_bounds__(64) void k_align_plain(AlignArgs args) {
   for (int32_t t = 0; t < ntiles; ++t) {
     uint32_t y[W], a[W], b[W];
     load_strip<W>(y, args.ref + (int64_t)t * T + lane * W);
-#pragma unroll
-    for (int w = 0; w < W; ++w) a[w] = b[w] = 0u;
     uint32_t dprev = F::kInf;
+    const int64_t c0 = (int64_t)t * T + lane * W;
+    if (STREAM && m_old > 0) {
+      load_strip<W>(a, acc + c0);
+      if (c0 > 0) dprev = acc[c0 - 1];
+#pragma unroll
+      for (int w = 0; w < W; ++w) b[w] = a[w];
+    } else {
+#pragma unroll
+      for (int w = 0; w < W; ++w) a[w] = b[w] = 0u;
+    }
+    if constexpr (STREAM) {
+      if (t > 0) {
+        // the resident values above are in registers before any write-back
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < W; w += 4)
+          *(uint4*)(acc + c0 - T + w) =
+              make_uint4(my_slot[w], my_slot[w + 1], my_slot[w + 2], my_slot[w + 3]);
+      }
+    }
     auto step = [&](int32_t s, const uint32_t(&up)[W], uint32_t(&nw)[W]) {
       const uint32_t left = from_left_lane(up[W - 1], B[s < M ? s : M - 1]);
       const int32_t i = s - lane;
@@ -473,6 +566,13 @@ __global__ __launch_bounds__(64) void k_align_plain(AlignArgs args) {
     }
     __syncthreads();
   }
+  if constexpr (STREAM) {
+    const int64_t c0 = (int64_t)(ntiles - 1) * T + lane * W;
+#pragma unroll
+    for (int w = 0; w < W; w += 4)
+      *(uint4*)(acc + c0 + w) =
+          make_uint4(my_slot[w], my_slot[w + 1], my_slot[w + 2], my_slot[w + 3]);
+  }
   wave_argmin(best, bestj);
   if (lane == 0) {
     F::store_cost(args.cost, rd, best);
@@ -484,58 +584,70 @@ __global__ void k_reset_counter(int32_t* c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
 }
 
-template <class F, int W, int K>
+template <class F, int W, int K, bool STREAM>
 hipError_t launch_skew_t(int blocks, const AlignArgs& a, hipStream_t st) {
-  const size_t lds = SkewLds<F, W, K>::bytes(a.max_m);
-  hipError_t e = hipFuncSetAttribute((const void*)k_align_skew<F, W, K>,
+  const size_t lds = SkewLds<F, W, K, STREAM>::bytes(a.max_m);
+  hipError_t e = hipFuncSetAttribute((const void*)k_align_skew<F, W, K, STREAM>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, a.counter);
-  hipLaunchKernelGGL((k_align_skew<F, W, K>), dim3(blocks), dim3(64), lds, st, a);
+  hipLaunchKernelGGL((k_align_skew<F, W, K, STREAM>), dim3(blocks), dim3(64), lds, st, a);
   return hipGetLastError();
+}
+
+template <class F, int W, int K>
+hipError_t launch_skew_s(int blocks, const AlignArgs& a, hipStream_t st, bool stream) {
+  return stream ? launch_skew_t<F, W, K, true>(blocks, a, st)
+                : launch_skew_t<F, W, K, false>(blocks, a, st);
 }
 
 template <class F, int W>
-hipError_t launch_plain_t(const AlignArgs& a, hipStream_t st) {
+hipError_t launch_plain_t(const AlignArgs& a, hipStream_t st, bool stream) {
   const size_t lds = PlainLds<F, W>::bytes(a.max_m);
-  hipError_t e = hipFuncSetAttribute((const void*)k_align_plain<F, W>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const void* fn = stream ? (const void*)k_align_plain<F, W, true>
+                          : (const void*)k_align_plain<F, W, false>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_align_plain<F, W>), dim3(a.nwork), dim3(64), lds, st, a);
+  if (stream)
+    hipLaunchKernelGGL((k_align_plain<F, W, true>), dim3(a.nwork), dim3(64), lds, st, a);
+  else
+    hipLaunchKernelGGL((k_align_plain<F, W, false>), dim3(a.nwork), dim3(64), lds, st, a);
   return hipGetLastError();
 }
 
 template <class F>
-hipError_t launch_skew_f(int strip, int chains, int blocks, const AlignArgs& a, hipStream_t st) {
+hipError_t launch_skew_f(int strip, int chains, int blocks, const AlignArgs& a, hipStream_t st,
+                         bool stream) {
   switch (strip * 8 + chains) {
-    case 8 * 8 + 1: return launch_skew_t<F, 8, 1>(blocks, a, st);
-    case 8 * 8 + 2: return launch_skew_t<F, 8, 2>(blocks, a, st);
-    case 16 * 8 + 1: return launch_skew_t<F, 16, 1>(blocks, a, st);
-    case 16 * 8 + 2: return launch_skew_t<F, 16, 2>(blocks, a, st);
-    case 16 * 8 + 4: return launch_skew_t<F, 16, 4>(blocks, a, st);
-    case 32 * 8 + 1: return launch_skew_t<F, 32, 1>(blocks, a, st);
-    case 32 * 8 + 2: return launch_skew_t<F, 32, 2>(blocks, a, st);
-    case 32 * 8 + 4: return launch_skew_t<F, 32, 4>(blocks, a, st);
+    case 8 * 8 + 1: return launch_skew_s<F, 8, 1>(blocks, a, st, stream);
+    case 8 * 8 + 2: return launch_skew_s<F, 8, 2>(blocks, a, st, stream);
+    case 16 * 8 + 1: return launch_skew_s<F, 16, 1>(blocks, a, st, stream);
+    case 16 * 8 + 2: return launch_skew_s<F, 16, 2>(blocks, a, st, stream);
+    case 16 * 8 + 4: return launch_skew_s<F, 16, 4>(blocks, a, st, stream);
+    case 32 * 8 + 1: return launch_skew_s<F, 32, 1>(blocks, a, st, stream);
+    case 32 * 8 + 2: return launch_skew_s<F, 32, 2>(blocks, a, st, stream);
+    case 32 * 8 + 4: return launch_skew_s<F, 32, 4>(blocks, a, st, stream);
   }
   return hipErrorInvalidValue;
 }
 
 template <class F>
-hipError_t launch_plain_f(int strip, const AlignArgs& a, hipStream_t st) {
+hipError_t launch_plain_f(int strip, const AlignArgs& a, hipStream_t st, bool stream) {
   switch (strip) {
-    case 8: return launch_plain_t<F, 8>(a, st);
-    case 16: return launch_plain_t<F, 16>(a, st);
-    case 32: return launch_plain_t<F, 32>(a, st);
+    case 8: return launch_plain_t<F, 8>(a, st, stream);
+    case 16: return launch_plain_t<F, 16>(a, st, stream);
+    case 32: return launch_plain_t<F, 32>(a, st, stream);
   }
   return hipErrorInvalidValue;
 }
 
 template <class F>
-size_t skew_bytes_f(int strip, int chains, int max_m) {
+size_t skew_bytes_f(int strip, int chains, int max_m, bool stream) {
   if (!valid_strip_chains(strip, chains)) return 0;
-  // the layout depends on (W, K) only through 4(64W + W) + 8(M + 64K)
-  return (4 * ((size_t)64 * strip + strip) + 8 * ((size_t)max_m + 64 * chains) + 15) &
-         ~(size_t)15;
+  // mirrors SkewLds: stage (+ resident strips and left values) or zeros,
+  // then the query/boundary entries
+  const size_t u32 = stream ? (size_t)64 * strip * 2 + 64 : (size_t)64 * strip + strip;
+  return (4 * u32 + 8 * ((size_t)max_m + 64 * chains) + 15) & ~(size_t)15;
 }
 
 template <class F>
@@ -551,19 +663,20 @@ size_t plain_bytes_f(int strip, int max_m) {
 }  // namespace
 
 hipError_t launch_align_skew(int dtype, int strip, int chains, int blocks, const AlignArgs& a,
-                             hipStream_t st) {
-  return dtype == SDTW_I16 ? launch_skew_f<FmtI16>(strip, chains, blocks, a, st)
-                           : launch_skew_f<FmtF32>(strip, chains, blocks, a, st);
+                             hipStream_t st, bool stream) {
+  return dtype == SDTW_I16 ? launch_skew_f<FmtI16>(strip, chains, blocks, a, st, stream)
+                           : launch_skew_f<FmtF32>(strip, chains, blocks, a, st, stream);
 }
 
-hipError_t launch_align_plain(int dtype, int strip, const AlignArgs& a, hipStream_t st) {
-  return dtype == SDTW_I16 ? launch_plain_f<FmtI16>(strip, a, st)
-                           : launch_plain_f<FmtF32>(strip, a, st);
+hipError_t launch_align_plain(int dtype, int strip, const AlignArgs& a, hipStream_t st,
+                              bool stream) {
+  return dtype == SDTW_I16 ? launch_plain_f<FmtI16>(strip, a, st, stream)
+                           : launch_plain_f<FmtF32>(strip, a, st, stream);
 }
 
-size_t skew_lds_bytes(int dtype, int strip, int chains, int max_m) {
-  return dtype == SDTW_I16 ? skew_bytes_f<FmtI16>(strip, chains, max_m)
-                           : skew_bytes_f<FmtF32>(strip, chains, max_m);
+size_t skew_lds_bytes(int dtype, int strip, int chains, int max_m, bool stream) {
+  return dtype == SDTW_I16 ? skew_bytes_f<FmtI16>(strip, chains, max_m, stream)
+                           : skew_bytes_f<FmtF32>(strip, chains, max_m, stream);
 }
 
 size_t plain_lds_bytes(int dtype, int strip, int max_m) {

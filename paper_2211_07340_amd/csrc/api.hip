@@ -5,8 +5,13 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <new>
 #include <numeric>
+#include <set>
 #include <vector>
 
 #include "common.h"
@@ -17,7 +22,25 @@ struct sdtw_ref_s {
   int64_t n;       // true length
   int64_t n_pad;   // device layout length
   uint32_t* data;  // u32 biased int16 or float bits
-  int open_streams;
+  std::atomic<int> open_streams;
+};
+
+namespace sdtw {
+// Completion of one sdtw_stream_extend call (one event per call, shared by
+// the streams it extended); the event returns to a pool when released.
+struct CallToken {
+  hipEvent_t ev = nullptr;
+  ~CallToken();
+};
+}  // namespace sdtw
+
+struct sdtw_stream_s {
+  int device;
+  sdtw_ref ref;
+  uint32_t* row;        // resident row gamma(rows, .), n_pad entries
+  size_t bytes;
+  int32_t rows;         // query rows folded in so far
+  std::shared_ptr<sdtw::CallToken> last;  // last extend that used the row
 };
 
 struct sdtw_plan_s {
@@ -79,6 +102,82 @@ static bool valid_strip(int s) { return s == 8 || s == 16 || s == 32; }
 
 }  // namespace sdtw
 
+namespace sdtw {
+
+// ---- events recycled across extend calls -----------------------------------
+static std::mutex g_ev_mu;
+static std::vector<hipEvent_t> g_ev_free;
+
+static hipEvent_t event_get() {
+  {
+    std::lock_guard<std::mutex> g(g_ev_mu);
+    if (!g_ev_free.empty()) {
+      hipEvent_t e = g_ev_free.back();
+      g_ev_free.pop_back();
+      return e;
+    }
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+  return e;
+}
+
+CallToken::~CallToken() {
+  if (!ev) return;
+  std::lock_guard<std::mutex> g(g_ev_mu);
+  g_ev_free.push_back(ev);
+}
+
+// ---- resident-row pool: a byte budget per device, rows cached by size ----
+struct RowPool {
+  std::mutex mu;
+  int64_t budget = int64_t(16) << 30;
+  int64_t in_use = 0;
+  int64_t cached = 0;
+  std::map<size_t, std::vector<void*>> free_rows;
+};
+constexpr int kMaxDevices = 64;
+static RowPool g_pool[kMaxDevices];
+
+static RowPool* pool_for(int dev) {
+  return (dev >= 0 && dev < kMaxDevices) ? &g_pool[dev] : nullptr;
+}
+
+// ---- pinned descriptor slots for stream_extend -----------------------------
+struct DescSlot {
+  StreamItem* host = nullptr;
+  StreamItem* dev = nullptr;  // cap items, then one int32 work counter
+  int32_t cap = 0;
+  std::shared_ptr<CallToken> last;
+};
+constexpr int kDescSlots = 8;
+struct DescRing {
+  std::mutex mu;
+  DescSlot slot[kDescSlots];
+  int next = 0;
+};
+static DescRing g_ring[kMaxDevices];
+
+static int ensure_slot(DescSlot& sl, int32_t n) {
+  if (sl.cap >= n) return SDTW_OK;
+  int32_t cap = std::max<int32_t>(n, std::max<int32_t>(2 * sl.cap, 1024));
+  if (sl.host) (void)hipHostFree(sl.host);
+  if (sl.dev) (void)hipFree(sl.dev);
+  sl.host = nullptr;
+  sl.dev = nullptr;
+  sl.cap = 0;
+  int rc = check_hip(hipHostMalloc((void**)&sl.host, sizeof(StreamItem) * (size_t)cap),
+                     "sdtw_stream_extend: pinned descriptors");
+  if (!rc)
+    rc = check_hip(hipMalloc((void**)&sl.dev, sizeof(StreamItem) * (size_t)cap + 64),
+                   "sdtw_stream_extend: device descriptors");
+  if (rc) return rc;
+  sl.cap = cap;
+  return SDTW_OK;
+}
+
+}  // namespace sdtw
+
 using namespace sdtw;
 
 #define SDTW_REQUIRE(cond, ...) \
@@ -124,9 +223,21 @@ int sdtw_prepare_queries(const float* raw_dev, const int64_t* offsets_dev, int32
   SDTW_REQUIRE(raw_dev && offsets_dev && z_dev, "sdtw_prepare_queries: null pointer");
   SDTW_REQUIRE(nq >= 1, "sdtw_prepare_queries: nq=%d < 1", nq);
   SDTW_REQUIRE(isfinite(scale) && scale > 0.0, "sdtw_prepare_queries: scale must be > 0");
-  return check_hip(launch_prepare_queries(raw_dev, offsets_dev, nq, scale, z_dev, codes_dev,
-                                          nsat_dev, (hipStream_t)stream),
+  return check_hip(launch_prepare_queries(raw_dev, offsets_dev, nq, scale, nullptr, nullptr,
+                                          z_dev, codes_dev, nsat_dev, (hipStream_t)stream),
                    "sdtw_prepare_queries: launch");
+}
+
+int sdtw_prepare_queries_ex(const float* raw_dev, const int64_t* offsets_dev, int32_t nq,
+                            double scale, const double* stats_in_dev, double* stats_out_dev,
+                            float* z_dev, int16_t* codes_dev, int64_t* nsat_dev, void* stream) {
+  SDTW_REQUIRE(raw_dev && offsets_dev && z_dev, "sdtw_prepare_queries_ex: null pointer");
+  SDTW_REQUIRE(nq >= 1, "sdtw_prepare_queries_ex: nq=%d < 1", nq);
+  SDTW_REQUIRE(isfinite(scale) && scale > 0.0, "sdtw_prepare_queries_ex: scale must be > 0");
+  return check_hip(launch_prepare_queries(raw_dev, offsets_dev, nq, scale, stats_in_dev,
+                                          stats_out_dev, z_dev, codes_dev, nsat_dev,
+                                          (hipStream_t)stream),
+                   "sdtw_prepare_queries_ex: launch");
 }
 
 // ---------------------------------------------------------------------------
@@ -195,7 +306,8 @@ int sdtw_reference_info(sdtw_ref ref, int64_t* n, int* dtype) {
 int sdtw_free_reference(sdtw_ref ref) {
   SDTW_REQUIRE(ref, "sdtw_free_reference: null reference");
   if (ref->open_streams > 0)
-    return set_error(SDTW_ESTATE, "sdtw_free_reference: %d streams still open", ref->open_streams);
+    return set_error(SDTW_ESTATE, "sdtw_free_reference: %d streams still open",
+                     ref->open_streams.load());
   int rc = check_hip(hipFree(ref->data), "sdtw_free_reference");
   delete ref;
   return rc;
@@ -410,4 +522,215 @@ int sdtw_align_one(sdtw_ref ref, const void* q_dev, int32_t M, void* cost_dev, i
                    "sdtw_align_one: launch");
 }
 
+// ---------------------------------------------------------------------------
+// streaming extension
+// ---------------------------------------------------------------------------
+
+int sdtw_set_row_budget(int64_t bytes) {
+  SDTW_REQUIRE(bytes >= 0, "sdtw_set_row_budget: negative budget");
+  RowPool* pl = pool_for(current_device());
+  SDTW_REQUIRE(pl, "sdtw_set_row_budget: no current device");
+  std::lock_guard<std::mutex> g(pl->mu);
+  pl->budget = bytes;
+  return SDTW_OK;
+}
+
+int sdtw_row_budget_info(int64_t* budget, int64_t* in_use, int64_t* cached) {
+  RowPool* pl = pool_for(current_device());
+  SDTW_REQUIRE(pl, "sdtw_row_budget_info: no current device");
+  std::lock_guard<std::mutex> g(pl->mu);
+  if (budget) *budget = pl->budget;
+  if (in_use) *in_use = pl->in_use;
+  if (cached) *cached = pl->cached;
+  return SDTW_OK;
+}
+
+int sdtw_stream_open(sdtw_ref ref, sdtw_stream* out) {
+  SDTW_REQUIRE(ref && out, "sdtw_stream_open: null pointer");
+  RowPool* pl = pool_for(ref->device);
+  SDTW_REQUIRE(pl, "sdtw_stream_open: bad device");
+  const size_t bytes = sizeof(uint32_t) * (size_t)ref->n_pad;
+  void* row = nullptr;
+  {
+    std::lock_guard<std::mutex> g(pl->mu);
+    if (pl->in_use + (int64_t)bytes > pl->budget)
+      return set_error(SDTW_EBUDGET, "sdtw_stream_open: %zu more bytes exceed the row budget "
+                       "(%lld in use of %lld)", bytes, (long long)pl->in_use,
+                       (long long)pl->budget);
+    auto it = pl->free_rows.find(bytes);
+    if (it != pl->free_rows.end() && !it->second.empty()) {
+      row = it->second.back();
+      it->second.pop_back();
+      pl->cached -= (int64_t)bytes;
+    } else {
+      // make room in the budget by releasing cached rows of other sizes
+      for (auto& kv : pl->free_rows) {
+        while (pl->in_use + pl->cached + (int64_t)bytes > pl->budget && !kv.second.empty()) {
+          (void)hipFree(kv.second.back());
+          kv.second.pop_back();
+          pl->cached -= (int64_t)kv.first;
+        }
+      }
+      if (hipMalloc(&row, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(SDTW_ENOMEM, "sdtw_stream_open: device allocation of %zu bytes", bytes);
+      }
+    }
+    pl->in_use += (int64_t)bytes;
+  }
+  sdtw_stream_s* s = new (std::nothrow) sdtw_stream_s();
+  if (!s) {
+    std::lock_guard<std::mutex> g(pl->mu);
+    pl->free_rows[bytes].push_back(row);
+    pl->in_use -= (int64_t)bytes;
+    pl->cached += (int64_t)bytes;
+    return set_error(SDTW_ENOMEM, "sdtw_stream_open: host allocation");
+  }
+  s->device = ref->device;
+  s->ref = ref;
+  s->row = (uint32_t*)row;
+  s->bytes = bytes;
+  s->rows = 0;
+  ref->open_streams++;
+  *out = s;
+  return SDTW_OK;
+}
+
+int sdtw_stream_info(sdtw_stream s, int32_t* rows, int64_t* n) {
+  SDTW_REQUIRE(s, "sdtw_stream_info: null stream");
+  if (rows) *rows = s->rows;
+  if (n) *n = s->ref->n;
+  return SDTW_OK;
+}
+
+int sdtw_stream_close(sdtw_stream s) {
+  SDTW_REQUIRE(s, "sdtw_stream_close: null stream");
+  // the row may still be read or written by enqueued work
+  if (s->last && s->last->ev) {
+    int rc = check_hip(hipEventSynchronize(s->last->ev), "sdtw_stream_close: wait");
+    if (rc) return rc;
+  }
+  RowPool* pl = pool_for(s->device);
+  {
+    std::lock_guard<std::mutex> g(pl->mu);
+    pl->free_rows[s->bytes].push_back(s->row);
+    pl->in_use -= (int64_t)s->bytes;
+    pl->cached += (int64_t)s->bytes;
+  }
+  s->ref->open_streams--;
+  delete s;
+  return SDTW_OK;
+}
+
+int sdtw_stream_copy_row(sdtw_stream s, void* dst_dev, void* stream) {
+  SDTW_REQUIRE(s && dst_dev, "sdtw_stream_copy_row: null pointer");
+  if (s->rows == 0)
+    return set_error(SDTW_ESTATE, "sdtw_stream_copy_row: the stream has no rows yet");
+  return check_hip(hipMemcpyAsync(dst_dev, s->row, sizeof(uint32_t) * (size_t)s->ref->n,
+                                  hipMemcpyDeviceToDevice, (hipStream_t)stream),
+                   "sdtw_stream_copy_row");
+}
+
+int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk_dev,
+                       const int64_t* chunk_offsets_host, void* cost_dev, int32_t* end_dev,
+                       void* stream) {
+  SDTW_REQUIRE(streams && chunk_dev && chunk_offsets_host && cost_dev && end_dev,
+               "sdtw_stream_extend: null pointer");
+  SDTW_REQUIRE(ns >= 1, "sdtw_stream_extend: ns=%d < 1", ns);
+  SDTW_REQUIRE(streams[0], "sdtw_stream_extend: stream 0 is null");
+  const sdtw_ref ref = streams[0]->ref;
+  const int dtype = ref->dtype;
+  const int32_t row_cap = dtype == SDTW_I16 ? 32767 : INT32_MAX;
+  std::set<const sdtw_stream_s*> seen;
+  std::vector<int32_t> order((size_t)ns);
+  int32_t max_m = 0;
+  for (int32_t i = 0; i < ns; ++i) {
+    const sdtw_stream s = streams[i];
+    SDTW_REQUIRE(s, "sdtw_stream_extend: stream %d is null", i);
+    SDTW_REQUIRE(s->ref == ref, "sdtw_stream_extend: stream %d uses another reference", i);
+    SDTW_REQUIRE(seen.insert(s).second, "sdtw_stream_extend: stream %d appears twice", i);
+    const int64_t m = chunk_offsets_host[i + 1] - chunk_offsets_host[i];
+    SDTW_REQUIRE(chunk_offsets_host[i] >= 0 && m >= 1 && m <= SDTW_MAX_QUERY,
+                 "sdtw_stream_extend: chunk %d has length %lld outside [1, %d]", i,
+                 (long long)m, SDTW_MAX_QUERY);
+    SDTW_REQUIRE((int64_t)s->rows + m <= row_cap,
+                 "sdtw_stream_extend: stream %d would exceed %d rows", i, row_cap);
+    order[(size_t)i] = i;
+    max_m = std::max<int32_t>(max_m, (int32_t)m);
+  }
+  auto len = [&](int32_t i) { return chunk_offsets_host[i + 1] - chunk_offsets_host[i]; };
+  std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return len(a) != len(b) ? len(a) > len(b) : a < b;
+  });
+  constexpr int kStrip = 16, kChains = 1;
+  int32_t nbig = 0;
+  while (nbig < ns && len(order[(size_t)nbig]) >= skew_min_m(kChains)) ++nbig;
+  const size_t lds_max = (size_t)max_lds_bytes();
+  SDTW_REQUIRE(skew_lds_bytes(dtype, kStrip, kChains, max_m, true) <= lds_max &&
+                   plain_lds_bytes(dtype, kStrip, max_m) <= lds_max,
+               "sdtw_stream_extend: chunk of %d rows needs more LDS than available", max_m);
+
+  const int dev = ref->device;
+  DescRing& ring = g_ring[dev >= 0 && dev < kMaxDevices ? dev : 0];
+  std::lock_guard<std::mutex> g(ring.mu);
+  DescSlot& sl = ring.slot[ring.next];
+  if (sl.last && sl.last->ev) {
+    int rc = check_hip(hipEventSynchronize(sl.last->ev), "sdtw_stream_extend: slot wait");
+    if (rc) return rc;
+  }
+  int rc = ensure_slot(sl, ns);
+  if (rc) return rc;
+  for (int32_t t = 0; t < ns; ++t) {
+    const int32_t i = order[(size_t)t];
+    StreamItem& it = sl.host[t];
+    it.acc = streams[i]->row;
+    it.q0 = chunk_offsets_host[i];
+    it.m = (int32_t)len(i);
+    it.m_old = streams[i]->rows;
+    it.out = i;
+    it.pad = 0;
+  }
+  auto tok = std::make_shared<CallToken>();
+  tok->ev = event_get();
+  if (!tok->ev) return set_error(SDTW_EDEVICE, "sdtw_stream_extend: event creation failed");
+  hipStream_t st = (hipStream_t)stream;
+  rc = check_hip(hipMemcpyAsync(sl.dev, sl.host, sizeof(StreamItem) * (size_t)ns,
+                                hipMemcpyHostToDevice, st),
+                 "sdtw_stream_extend: descriptors");
+  AlignArgs a{};
+  a.ref = ref->data;
+  a.n = ref->n;
+  a.q = chunk_dev;
+  a.counter = (int32_t*)(sl.dev + sl.cap);
+  a.cost = cost_dev;
+  a.end = end_dev;
+  if (!rc && nbig) {
+    a.items = sl.dev;
+    a.nwork = nbig;
+    a.max_m = (int32_t)len(order[0]);
+    const int cus = std::max(cu_count(), 1);
+    const size_t per = skew_lds_bytes(dtype, kStrip, kChains, a.max_m, true);
+    const int wpc = (int)std::max<size_t>(1, std::min<size_t>(16, (160 * 1024) / per));
+    const int blocks = (int)std::min<int64_t>((int64_t)cus * wpc, nbig);
+    rc = check_hip(launch_align_skew(dtype, kStrip, kChains, blocks, a, st, true),
+                   "sdtw_stream_extend: launch");
+  }
+  if (!rc && nbig < ns) {
+    a.items = sl.dev + nbig;
+    a.nwork = ns - nbig;
+    a.max_m = (int32_t)len(order[(size_t)nbig]);
+    rc = check_hip(launch_align_plain(dtype, kStrip, a, st, true), "sdtw_stream_extend: launch");
+  }
+  if (!rc) rc = check_hip(hipEventRecord(tok->ev, st), "sdtw_stream_extend: record");
+  if (rc) return rc;
+  sl.last = tok;
+  ring.next = (ring.next + 1) % kDescSlots;
+  for (int32_t i = 0; i < ns; ++i) {
+    streams[i]->rows += (int32_t)len(i);
+    streams[i]->last = tok;
+  }
+  return SDTW_OK;
+}
+
 }  // extern "C"
+

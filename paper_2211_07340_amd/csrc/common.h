@@ -43,13 +43,23 @@ hipError_t launch_prepare_reference(const uint8_t* g, int64_t L, const float* ta
                                     int64_t* nsat, double* scratch, hipStream_t st);
 constexpr int kRefPartials = 512;  // doubles of scratch: partials + 2 stats
 hipError_t launch_prepare_queries(const float* raw, const int64_t* offs, int32_t nq,
-                                  double scale, float* z, int16_t* codes,
-                                  int64_t* nsat, hipStream_t st);
+                                  double scale, const double* stats_in, double* stats_out,
+                                  float* z, int16_t* codes, int64_t* nsat, hipStream_t st);
 hipError_t launch_layout_reference(const void* src, int64_t n, int dtype,
                                    uint32_t* dst, int64_t n_pad, int32_t* nonfinite,
                                    hipStream_t st);
 
 // ---- launchers (align.hip) --------------------------------------------------
+// One streaming work item: extend a resident row by the rows of one chunk.
+struct StreamItem {
+  uint32_t* acc;   // resident row gamma(m_old, 0..N) in the kernel's cost encoding
+  int64_t q0;      // first chunk value in the query array
+  int32_t m;       // chunk rows (>= 1)
+  int32_t m_old;   // rows already folded into acc (0: acc is not read)
+  int32_t out;     // output slot for (cost, end)
+  int32_t pad;
+};
+
 struct AlignArgs {
   const uint32_t* ref;   // padded device layout (u32 biased int16, or f32 bits)
   int64_t n;             // true reference length
@@ -62,14 +72,17 @@ struct AlignArgs {
   void* cost;            // int32[nq] or float[nq]
   int32_t* end;          // int32[nq]
   int32_t single_m;      // used when offs == nullptr: one read of this length
+  const StreamItem* items;  // streaming launches: work item descriptors
 };
 // Continuous-skew persistent kernel with `chains` chains per lane; every read
-// in the list must have M >= skew_min_m(chains).
+// in the list must have M >= skew_min_m(chains).  `stream`: work items come
+// from a.items and extend resident rows.
 hipError_t launch_align_skew(int dtype, int strip, int chains, int blocks, const AlignArgs& a,
-                             hipStream_t st);
+                             hipStream_t st, bool stream = false);
 // Synchronised-tile single-wave kernel; any M >= 1; one block per work item.
-hipError_t launch_align_plain(int dtype, int strip, const AlignArgs& a, hipStream_t st);
-size_t skew_lds_bytes(int dtype, int strip, int chains, int max_m);
+hipError_t launch_align_plain(int dtype, int strip, const AlignArgs& a, hipStream_t st,
+                              bool stream = false);
+size_t skew_lds_bytes(int dtype, int strip, int chains, int max_m, bool stream = false);
 size_t plain_lds_bytes(int dtype, int strip, int max_m);
 int max_lds_bytes();
 

@@ -134,9 +134,14 @@ __device__ __forceinline__ double wave_seq_sum(const float* __restrict__ raw, in
   return __shfl(acc, 0);
 }
 
+// stats_in (optional): per-read (mean, sd) to apply instead of the read's
+// own statistics; stats_out (optional): the (mean, sd) applied.
 __global__ __launch_bounds__(64) void k_prep_queries(const float* __restrict__ raw,
                                                      const int64_t* __restrict__ offs, int32_t nq,
-                                                     double scale, float* __restrict__ z,
+                                                     double scale,
+                                                     const double* __restrict__ stats_in,
+                                                     double* __restrict__ stats_out,
+                                                     float* __restrict__ z,
                                                      int16_t* __restrict__ codes,
                                                      int64_t* __restrict__ nsat) {
   __shared__ float buf[kQChunk];
@@ -144,9 +149,19 @@ __global__ __launch_bounds__(64) void k_prep_queries(const float* __restrict__ r
   if (r >= nq) return;
   const int64_t a = offs[r], b = offs[r + 1];
   if (b <= a) return;
-  const double n = (double)(b - a);
-  const double mean = wave_seq_sum(raw, a, b, 0.0, false, buf) / n;
-  const double sd = sqrt(wave_seq_sum(raw, a, b, mean, true, buf) / n);
+  double mean, sd;
+  if (stats_in) {
+    mean = stats_in[2 * r];
+    sd = stats_in[2 * r + 1];
+  } else {
+    const double n = (double)(b - a);
+    mean = wave_seq_sum(raw, a, b, 0.0, false, buf) / n;
+    sd = sqrt(wave_seq_sum(raw, a, b, mean, true, buf) / n);
+  }
+  if (stats_out && threadIdx.x == 0) {
+    stats_out[2 * r] = mean;
+    stats_out[2 * r + 1] = sd;
+  }
   unsigned long long sat = 0;
   for (int64_t i = a + threadIdx.x; i < b; i += 64) {
     const float zi = sd > 0.0 ? (float)(((double)raw[i] - mean) / sd) : 0.0f;
@@ -205,11 +220,11 @@ hipError_t launch_prepare_reference(const uint8_t* g, int64_t L, const float* ta
 }
 
 hipError_t launch_prepare_queries(const float* raw, const int64_t* offs, int32_t nq,
-                                  double scale, float* z, int16_t* codes, int64_t* nsat,
-                                  hipStream_t st) {
+                                  double scale, const double* stats_in, double* stats_out,
+                                  float* z, int16_t* codes, int64_t* nsat, hipStream_t st) {
   if (nsat) hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, st, nsat);
-  hipLaunchKernelGGL(k_prep_queries, dim3(nq), dim3(64), 0, st, raw, offs, nq, scale, z, codes,
-                     nsat);
+  hipLaunchKernelGGL(k_prep_queries, dim3(nq), dim3(64), 0, st, raw, offs, nq, scale, stats_in,
+                     stats_out, z, codes, nsat);
   return hipGetLastError();
 }
 

@@ -70,3 +70,18 @@ def test_argument_validation(lib):
     assert lib.sdtw_free_reference(None) == 1
     assert lib.sdtw_plan_destroy(None) == 1
     assert "null" in _err(lib)
+
+
+def test_stream_argument_validation(lib):
+    p = C.c_void_p(1)
+    assert lib.sdtw_stream_open(None, C.byref(C.c_void_p())) == 1
+    assert lib.sdtw_stream_close(None) == 1
+    assert lib.sdtw_stream_copy_row(None, p, None) == 1
+    assert lib.sdtw_stream_info(None, None, None) == 1
+    offs = np.array([0, 10], np.int64)
+    assert lib.sdtw_stream_extend(None, 1, p, offs.ctypes.data_as(C.c_void_p), p, p, None) == 1
+    arr = (C.c_void_p * 1)(None)
+    assert lib.sdtw_stream_extend(arr, 0, p, offs.ctypes.data_as(C.c_void_p), p, p, None) == 1
+    assert lib.sdtw_stream_extend(arr, 1, p, offs.ctypes.data_as(C.c_void_p), p, p, None) == 1
+    assert lib.sdtw_set_row_budget(-5) == 1
+    assert lib.sdtw_prepare_queries_ex(None, p, 1, 64.0, None, None, p, p, p, None) == 1

@@ -1,0 +1,195 @@
+"""GPU streaming extension against the oracle.
+
+A read that arrives in chunks is normalised with the statistics of its first
+chunk; extending its resident row chunk by chunk must give exactly what the
+oracle gives on the concatenated prefix (row i of Eq. 1 depends on X[1..i]
+only): the same cost and end after every chunk, and the same last row.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+sd = pytest.importorskip("paper_2211_07340_amd")
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sd.load_library()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def prepared():
+    w = synth.workload(1, nq=16)
+    z, codes, _ = oracle.prepare_reference(w.genome, w.table, w.k)
+    return w, z, codes
+
+
+def chunked_reads(w, plans, seed=0):
+    """Raw pA events of reads cut into chunks; each chunk scaled with the
+    statistics of its read's first chunk (oracle)."""
+    rng = np.random.default_rng(seed)
+    reads = []
+    for r, sizes in enumerate(plans):
+        total = int(sum(sizes))
+        if r % 2 == 0:
+            sim = synth.simulate_reads(w.genome, w.table, [total], 1.0, seed + r)
+        else:
+            sim = synth.simulate_reads(w.genome, w.table, [total], 0.0, seed + r)
+        raw = sim.values
+        cuts = np.concatenate([[0], np.cumsum(sizes)])
+        mean, sdv = oracle.zstats(raw[:cuts[1]])
+        z = oracle.zapply(raw, mean, sdv)
+        codes, _ = oracle.quantize(z, 64.0)
+        reads.append((raw, z, codes, cuts))
+    return reads
+
+
+def run_rounds(dev, ref_np, reads, dt):
+    """Extend every stream round by round (one batched call per round) and
+    check each result against the oracle on the concatenated prefix."""
+    ref = sd.Reference(torch.from_numpy(ref_np).to(dev))
+    streams = [sd.Stream(ref) for _ in reads]
+    nrounds = max(len(c) - 1 for _, _, _, c in reads)
+    got_all = []
+    for k in range(nrounds):
+        live = [i for i, (_, _, _, c) in enumerate(reads) if k < len(c) - 1]
+        vals = [(reads[i][2] if dt == sd.I16 else reads[i][1])[reads[i][3][k]:reads[i][3][k + 1]]
+                for i in live]
+        q, offs = synth.csr(vals)
+        q = q.astype(np.int16 if dt == sd.I16 else np.float32)
+        note(f"round {k}: {len(live)} streams, chunk lengths {np.diff(offs).tolist()}")
+        cost, end = sd.stream_extend([streams[i] for i in live], torch.from_numpy(q).to(dev),
+                                     offs)
+        torch.cuda.synchronize()
+        cost, end = cost.cpu().numpy(), end.cpu().numpy()
+        for t, i in enumerate(live):
+            cut = reads[i][3][k + 1]
+            prefix = (reads[i][2] if dt == sd.I16 else reads[i][1])[:cut]
+            if dt == sd.I16:
+                wc, we, lr = oracle.sdtw_i64(prefix, ref_np, lastrow=True)
+                assert (int(cost[t]), int(end[t])) == (wc, we), (i, k)
+            else:
+                wc, we, lr = oracle.sdtw_f32(prefix, ref_np, lastrow=True)
+                assert (np.float32(cost[t]), int(end[t])) == (wc, we), (i, k)
+            assert streams[i].rows == cut
+            row = streams[i].copy_row().cpu().numpy()
+            torch.cuda.synchronize()
+            if dt == sd.I16:
+                assert np.array_equal(row.astype(np.int64), lr), (i, k)
+            else:
+                assert np.array_equal(row.view(np.uint32), lr.view(np.uint32)), (i, k)
+            got_all.append((i, k, int(end[t]), float(cost[t])))
+    for s in streams:
+        s.close()
+    ref.close()
+    return got_all
+
+
+PLANS = [[400, 400, 400], [70, 30, 300], [1, 64, 65, 200], [250], [65, 65, 65, 65, 65],
+         [129, 1, 2], [300, 64]]
+
+
+@pytest.mark.parametrize("dt", ["i16", "f32"])
+def test_extend_equals_from_scratch(dev, prepared, dt):
+    w, z, codes = prepared
+    reads = chunked_reads(w, PLANS)
+    run_rounds(dev, codes if dt == "i16" else z, reads, sd.I16 if dt == "i16" else sd.F32)
+
+
+def test_extend_ragged_reference(dev):
+    rng = np.random.default_rng(4)
+    ref = rng.integers(-3000, 3000, size=3001).astype(np.int16)
+    reads = []
+    for sizes in ([100, 200, 5], [1, 1, 1], [64, 64], [70, 2000]):
+        total = int(sum(sizes))
+        codes = rng.integers(-3000, 3000, size=total).astype(np.int16)
+        reads.append((None, None, codes, np.concatenate([[0], np.cumsum(sizes)])))
+    run_rounds(dev, ref, reads, sd.I16)
+
+
+def test_alone_equals_mixed(dev, prepared):
+    w, z, codes = prepared
+    reads = chunked_reads(w, PLANS, seed=10)
+    mixed = run_rounds(dev, codes, reads, sd.I16)
+    alone = []
+    for i in range(len(reads)):
+        alone += [(i, k, e, c) for (_, k, e, c) in run_rounds(dev, codes, [reads[i]], sd.I16)]
+    assert sorted(mixed) == sorted(alone)
+
+
+def test_prepare_queries_with_fixed_statistics(dev):
+    w = synth.workload(1, nq=20)
+    raw = w.reads.values
+    offs = w.reads.offsets
+    stats = np.array([oracle.zstats(raw[offs[r]:offs[r] + 100]) for r in range(20)])
+    z, codes, nsat, used = sd.prepare_queries_ex(torch.from_numpy(raw).to(dev),
+                                                 torch.from_numpy(offs).to(dev), 64.0,
+                                                 torch.from_numpy(stats).to(dev))
+    torch.cuda.synchronize()
+    want = np.concatenate([oracle.zapply(raw[offs[r]:offs[r + 1]], *stats[r])
+                           for r in range(20)])
+    assert np.array_equal(z.cpu().numpy().view(np.uint32), want.view(np.uint32))
+    assert np.array_equal(codes.cpu().numpy(), oracle.quantize(want, 64.0)[0])
+    assert np.array_equal(used.cpu().numpy(), stats)
+    # without stats_in the statistics are each read's own (oracle.zstats)
+    _, _, _, own = sd.prepare_queries_ex(torch.from_numpy(raw).to(dev),
+                                         torch.from_numpy(offs).to(dev), 64.0)
+    torch.cuda.synchronize()
+    assert np.array_equal(own.cpu().numpy(),
+                          np.array([oracle.zstats(raw[offs[r]:offs[r + 1]]) for r in range(20)]))
+
+
+def test_budget_and_state_errors(dev, prepared):
+    w, z, codes = prepared
+    ref = sd.Reference(torch.from_numpy(codes).to(dev))
+    other = sd.Reference(torch.from_numpy(codes[:5000].copy()).to(dev))
+    budget0 = sd.row_budget_info()[0]
+    try:
+        row_bytes = 4 * (((codes.size + 2047) // 2048) * 2048 + 2048)
+        sd.set_row_budget(row_bytes * 2)
+        a, b = sd.Stream(ref), sd.Stream(ref)
+        with pytest.raises(sd.SdtwError) as ei:
+            sd.Stream(ref)
+        assert ei.value.code == "EBUDGET"
+        with pytest.raises(sd.SdtwError) as ei:
+            a.copy_row()
+        assert ei.value.code == "ESTATE"
+        with pytest.raises(sd.SdtwError) as ei:
+            ref.close()  # streams are open on it
+        assert ei.value.code == "ESTATE"
+        q = torch.zeros(100, dtype=torch.int16, device=dev)
+        with pytest.raises(sd.SdtwError) as ei:
+            sd.stream_extend([a, a], q, [0, 50, 100])
+        assert ei.value.code == "EINVAL"
+        b.close()
+        c = sd.Stream(ref)  # room again after a close
+        cost, end = sd.stream_extend([a, c], q, [0, 50, 100])
+        torch.cuda.synchronize()
+        assert a.rows == 50 and c.rows == 50
+        o = None
+        sd.set_row_budget(row_bytes * 3)
+        o = sd.Stream(other)
+        with pytest.raises(sd.SdtwError) as ei:
+            sd.stream_extend([a, o], q, [0, 50, 100])  # different references
+        assert ei.value.code == "EINVAL"
+        for s in (a, c, o):
+            s.close()
+    finally:
+        sd.set_row_budget(budget0)
+    other.close()
+    ref.close()
