@@ -51,6 +51,13 @@ def parse():
                     help="skip the float32 and one-read-per-launch comparison legs")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="reads in the oracle's timed sample (0: sized for ~10 s)")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="measured seconds of the streaming server leg (0: skip)")
+    ap.add_argument("--serve-warmup", type=float, default=5.0)
+    ap.add_argument("--serve-channels", type=int, default=512)
+    ap.add_argument("--serve-recompute-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-small-only", action="store_true",
+                    help="serve the 29,903-base target only")
     return ap.parse_args()
 
 
@@ -142,6 +149,11 @@ def main():
     if not args.no_extras:
         out["extras"] = extras(sd, torch, dev, w, reads, zref, cref, args, stream)
 
+    if args.serve_seconds > 0:
+        out["serving"] = serving(torch, dev, args.serve_seconds, args.serve_warmup,
+                                 args.serve_channels, args.serve_recompute_seconds,
+                                 large=not args.serve_small_only)
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, reads, args)
     print(json.dumps(out), flush=True)
@@ -187,6 +199,44 @@ def extras(sd, torch, dev, w, reads, zref, cref, args, stream):
     res["plain_one_read_per_launch"] = {"reads": n1, "ms_per_read": round(t * 1e3 / n1, 4),
                                         "gcups": round(c1 / t / 1e9, 2)}
     return res
+
+
+def serving_targets(torch, dev, pool: int = 512, seed: int = 4400, large: bool = True):
+    """Workload 4's two targets: the 29,903-base and the 5,000,000-base genome,
+    each with a pool of 2,000-event reads (50% on-target)."""
+    import synth
+    from paper_2211_07340_amd import server as srv
+    table = synth.make_level_table()
+    specs = []
+    genomes = [("29,903-base", synth.SMALL_GENOME)]
+    if large:
+        genomes.append(("5,000,000-base", synth.LARGE_GENOME))
+    for i, (name, L) in enumerate(genomes):
+        genome = synth.make_genome(L, L)
+        rd = synth.simulate_reads(genome, table, np.full(pool, 2000), 0.5, seed + i)
+        raws = [rd.values[rd.offsets[r]:rd.offsets[r + 1]] for r in range(pool)]
+        specs.append((name, genome, table, raws, rd.on_target))
+    return srv.make_targets(specs, dev)
+
+
+def serving(torch, dev, seconds: float, warmup: float, channels: int, recompute_s: float,
+            large: bool = True):
+    """Streaming Read Until: incremental extension, then recompute from scratch."""
+    from paper_2211_07340_amd import server as srv
+    targets = serving_targets(torch, dev, large=large)
+    cfg = srv.ServerConfig(channels=channels)
+    inc = srv.ReadUntilServer(targets, cfg, mode="extend")
+    inc.calibrate()
+    out = {"workload": f"{channels} channels, 400-event chunks every 0.1 s, reads to "
+                       f"{cfg.max_events} events, targets " +
+                       " and ".join(t.name for t in targets) + " (50/50)",
+           "incremental": inc.run(seconds, warmup)}
+    if recompute_s > 0:
+        rec = srv.ReadUntilServer(targets, cfg, mode="recompute")
+        out["recompute"] = rec.run(recompute_s, min(warmup, 2.0))
+    for t in targets:
+        t.ref.close()
+    return out
 
 
 def cpu_baseline(w, reads, args):

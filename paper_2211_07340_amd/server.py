@@ -1,0 +1,362 @@
+"""Read Until serving loop over the streaming sDTW library.
+
+Signal-level Read Until (section 2.2): every pore channel streams a read's
+events; after each chunk the read is aligned against a target reference and
+either kept, rejected (the pore voltage is reversed to eject it) or left to
+sequence further.  A rejection is only useful while most of the molecule is
+still unread, so decisions must come within a fraction of a second.
+
+This module simulates the channels and runs the decisions through the C ABI:
+
+* each channel emits a chunk of ``chunk_events`` events every
+  ``chunk_period_s`` seconds of wall-clock time, from reads drawn from a
+  pre-simulated pool per target (a channel starts its next read as soon as
+  the current one is decided);
+* a read's first chunk fixes its normalisation (sdtw_prepare_queries_ex
+  returns the statistics, later chunks pass them back in), so that
+  extending its resident row equals aligning the concatenated read;
+* admission: a read gets a stream (a resident row) when the row budget
+  allows; otherwise it waits, and its chunks queue;
+* continuous batching: on every tick all chunks that have arrived (and whose
+  read has no chunk in flight) are normalised and extended in one launch per
+  target; targets run on separate HIP streams so that short-reference work
+  never waits behind long-reference work;
+* decision rule (a reading; the paper only says that position and score
+  feed the selection criteria): s = cost / (scale * rows), the mean
+  per-event distance in z-units; keep if s <= tau, reject if rows >=
+  ``max_events`` or (rows >= ``min_reject_events`` and s >= tau), else
+  continue.  tau is set per target as the midpoint of the median s of
+  on-target and off-target reads on a calibration batch with its own seed.
+
+``mode="recompute"`` aligns every chunk's whole prefix from scratch instead
+(a fresh stream extended by the full prefix), for comparison.
+"""
+from __future__ import annotations
+
+import heapq
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import binding as sd
+
+
+@dataclass
+class ServerConfig:
+    channels: int = 512
+    chunk_events: int = 400
+    chunk_period_s: float = 0.1
+    max_events: int = 2000
+    min_reject_events: int = 800
+    scale: float = 64.0
+    row_budget_bytes: int | None = None
+    seed: int = 4004
+
+
+@dataclass
+class Target:
+    """A reference to align against, with a pool of simulated raw reads."""
+    name: str
+    ref: sd.Reference                  # int16 reference (prepared on the device)
+    reads: list                        # raw pA event arrays (float32), >= max_events each
+    on_target: np.ndarray              # bool per pool read
+    tau: float = float("nan")          # decision threshold (z-units per event)
+    stream: object = None              # torch.cuda.Stream for this target's work
+
+
+@dataclass
+class _Read:
+    target: int
+    pool_idx: int
+    raw: np.ndarray
+    start: float                       # time its first event was produced
+    on: bool
+    handle: object = None              # sd.Stream once admitted
+    stats: object = None               # (1, 2) float64 device tensor after chunk 1
+    rows: int = 0
+    chunks_done: int = 0
+
+
+@dataclass
+class _Tick:
+    event: object
+    target: int
+    entries: list                      # (channel, read, arrival, rows after)
+    cost: object
+    end: object
+    t_submit: float
+    cells: float
+    scratch: list                      # recompute mode: fresh streams to close
+
+
+@dataclass
+class ServerStats:
+    decisions: int = 0
+    kept: int = 0
+    rejected: int = 0
+    decided_on_target: int = 0
+    correct: int = 0
+    chunks: int = 0
+    cells: float = 0.0
+    chunk_latency: list = field(default_factory=list)
+    decision_latency: list = field(default_factory=list)
+    admission_waits: int = 0
+    max_queue: int = 0
+
+
+def _median(x):
+    return float(np.median(np.asarray(x))) if len(x) else float("nan")
+
+
+class ReadUntilServer:
+    def __init__(self, targets: list[Target], cfg: ServerConfig | None = None,
+                 mode: str = "extend", record: list | None = None):
+        """record: optional list receiving (target, pool read, rows, cost, end)
+        for every served chunk."""
+        import torch
+        self.torch = torch
+        self.record = record
+        self.targets = targets
+        self.cfg = cfg or ServerConfig()
+        if mode not in ("extend", "recompute"):
+            raise ValueError("mode must be 'extend' or 'recompute'")
+        self.mode = mode
+        self.rng = np.random.default_rng(self.cfg.seed)
+        for t in self.targets:
+            if t.stream is None:
+                t.stream = torch.cuda.Stream()
+        if self.cfg.row_budget_bytes is not None:
+            sd.set_row_budget(self.cfg.row_budget_bytes)
+
+    # ------------------------------------------------------------------
+    def calibrate(self, n_each: int = 128, seed: int = 77):
+        """Set each target's tau from reads of its pool with another seed."""
+        torch = self.torch
+        rng = np.random.default_rng(seed)
+        M = self.cfg.chunk_events
+        for t in self.targets:
+            on_idx = np.nonzero(t.on_target)[0]
+            off_idx = np.nonzero(~t.on_target)[0]
+            pick = np.concatenate([rng.choice(on_idx, min(n_each, on_idx.size), replace=False),
+                                   rng.choice(off_idx, min(n_each, off_idx.size), replace=False)])
+            raw = np.concatenate([t.reads[i][:M] for i in pick]).astype(np.float32)
+            offs = np.arange(pick.size + 1, dtype=np.int64) * M
+            dev = torch.device("cuda")
+            _, codes, _ = sd.prepare_queries(torch.from_numpy(raw).to(dev),
+                                             torch.from_numpy(offs).to(dev), self.cfg.scale)
+            plan = sd.Plan(offs, sd.I16)
+            cost, _ = sd.align_batch(t.ref, plan, codes)
+            torch.cuda.synchronize()
+            s = cost.cpu().numpy().astype(np.float64) / (self.cfg.scale * M)
+            on = t.on_target[pick]
+            t.tau = 0.5 * (_median(s[on]) + _median(s[~on]))
+            plan.close()
+        return {t.name: t.tau for t in self.targets}
+
+    # ------------------------------------------------------------------
+    def _new_read(self, now: float) -> _Read:
+        ti = int(self.rng.integers(0, len(self.targets)))
+        t = self.targets[ti]
+        pi = int(self.rng.integers(0, len(t.reads)))
+        return _Read(ti, pi, t.reads[pi], now, bool(t.on_target[pi]))
+
+    def _decide(self, rd: _Read, cost: float):
+        s = cost / (self.cfg.scale * rd.rows)
+        tau = self.targets[rd.target].tau
+        if s <= tau:
+            return "keep"
+        if rd.rows >= self.cfg.max_events or (rd.rows >= self.cfg.min_reject_events and s >= tau):
+            return "reject"
+        return None
+
+    def run(self, duration_s: float, warmup_s: float = 0.0) -> dict:
+        """Serve for warmup_s + duration_s seconds of wall-clock time; report
+        what was decided and measured during the last duration_s seconds."""
+        torch = self.torch
+        cfg = self.cfg
+        dev = torch.device("cuda")
+        P = cfg.chunk_period_s
+        t0 = time.perf_counter()
+        t_meas = t0 + warmup_s
+        t_end = t_meas + duration_s
+        stats = ServerStats()
+        chan_read: list[_Read] = []
+        arrivals = []  # heap of (arrival time of the channel's next chunk, channel)
+        for c in range(cfg.channels):
+            start = t0 + float(self.rng.random()) * P
+            chan_read.append(self._new_read(start))
+            heapq.heappush(arrivals, (start + P, c))
+        inflight: list[_Tick] = []
+        waiting = []  # chunks that have arrived but are not submitted yet
+
+        def harvest(block=False):
+            done = [tk for tk in inflight if block or tk.event.query()]
+            for tk in done:
+                inflight.remove(tk)
+                tk.event.synchronize()
+                costs = tk.cost.cpu().numpy()
+                ends = tk.end.cpu().numpy() if self.record is not None else None
+                for s in tk.scratch:
+                    s.close()
+                now = time.perf_counter()
+                in_window = t_meas <= now <= t_end
+                if in_window:
+                    stats.cells += tk.cells
+                for k, (c, rd, arr, rows) in enumerate(tk.entries):
+                    if in_window:
+                        stats.chunks += 1
+                        stats.chunk_latency.append(now - arr)
+                    if self.record is not None:
+                        self.record.append((rd.target, rd.pool_idx, rows, int(costs[k]),
+                                            int(ends[k])))
+                    verdict = self._decide(rd, float(costs[k]))
+                    if verdict is None:  # the read's next chunk
+                        heapq.heappush(arrivals, (rd.start + (rd.chunks_done + 1) * P, c))
+                        continue
+                    if in_window:
+                        stats.decisions += 1
+                        stats.decision_latency.append(now - arr)
+                        stats.kept += verdict == "keep"
+                        stats.rejected += verdict == "reject"
+                        stats.decided_on_target += rd.on
+                        stats.correct += (verdict == "keep") == rd.on
+                    if rd.handle is not None:
+                        rd.handle.close()
+                        rd.handle = None
+                    chan_read[c] = self._new_read(now)
+                    heapq.heappush(arrivals, (now + P, c))
+
+        while True:
+            now = time.perf_counter()
+            if now > t_end:
+                break
+            harvest()
+            while arrivals and arrivals[0][0] <= now:
+                waiting.append(heapq.heappop(arrivals))
+            stats.max_queue = max(stats.max_queue, len(waiting))
+            groups: dict[int, list] = {}
+            keep_waiting = []
+            for arr, c in waiting:
+                rd = chan_read[c]
+                if self.mode == "extend" and rd.handle is None:
+                    try:
+                        rd.handle = sd.Stream(self.targets[rd.target].ref)
+                    except sd.SdtwError as e:
+                        if e.code != "EBUDGET":
+                            raise
+                        stats.admission_waits += 1
+                        keep_waiting.append((arr, c))
+                        continue
+                groups.setdefault(rd.target, []).append((arr, c))
+            waiting = keep_waiting
+            for ti, items in groups.items():
+                self._submit(ti, items, chan_read, inflight, dev)
+            if not groups:
+                nxt = arrivals[0][0] if arrivals else now + 0.002
+                time.sleep(max(0.0, min(nxt - time.perf_counter(), 0.0005 if inflight else 0.002)))
+        harvest(block=True)
+        for rd in chan_read:
+            if rd.handle is not None:
+                rd.handle.close()
+                rd.handle = None
+        lat = np.asarray(stats.decision_latency)
+        clat = np.asarray(stats.chunk_latency)
+
+        def pct(a, q):
+            return round(float(np.percentile(a, q)) * 1e3, 2) if a.size else None
+
+        return {
+            "mode": self.mode,
+            "seconds": round(duration_s, 2),
+            "reads_per_s": round(stats.decisions / duration_s, 1),
+            "decisions": stats.decisions,
+            "kept": stats.kept,
+            "rejected": stats.rejected,
+            "decision_accuracy": round(stats.correct / max(stats.decisions, 1), 4),
+            "chunks_per_s": round(stats.chunks / duration_s, 1),
+            "gcups": round(stats.cells / duration_s / 1e9, 1),
+            "decision_latency_p50_ms": pct(lat, 50),
+            "decision_latency_p99_ms": pct(lat, 99),
+            "chunk_latency_p50_ms": pct(clat, 50),
+            "chunk_latency_p99_ms": pct(clat, 99),
+            "admission_waits": stats.admission_waits,
+            "max_waiting_chunks": stats.max_queue,
+            "tau": {t.name: round(t.tau, 4) for t in self.targets},
+        }
+
+    def _submit(self, ti, items, chan_read, inflight, dev):
+        """Normalise and extend the ready chunks of one target in one launch."""
+        torch = self.torch
+        cfg = self.cfg
+        t = self.targets[ti]
+        E = cfg.chunk_events
+        first = [(a, c) for a, c in items if chan_read[c].chunks_done == 0]
+        cont = [(a, c) for a, c in items if chan_read[c].chunks_done > 0]
+        entries, code_parts, lens, scratch = [], [], [], []
+        with torch.cuda.stream(t.stream):
+            for group, fresh in ((first, True), (cont, False)):
+                if not group:
+                    continue
+                lo = 0 if self.mode == "recompute" else None
+                segs = []
+                for _, c in group:
+                    rd = chan_read[c]
+                    a = 0 if lo == 0 else rd.chunks_done * E
+                    segs.append(rd.raw[a:(rd.chunks_done + 1) * E])
+                raw = torch.from_numpy(np.concatenate(segs).astype(np.float32)).to(dev)
+                offs_np = np.zeros(len(segs) + 1, np.int64)
+                np.cumsum([x.size for x in segs], out=offs_np[1:])
+                offs = torch.from_numpy(offs_np).to(dev)
+                if fresh:
+                    # the read's statistics are those of its first chunk
+                    _, codes, _, st = sd.prepare_queries_ex(raw, offs, cfg.scale, stream=t.stream)
+                    for k, (_, c) in enumerate(group):
+                        chan_read[c].stats = st[k:k + 1]
+                else:
+                    st_in = torch.cat([chan_read[c].stats for _, c in group])
+                    _, codes, _, _ = sd.prepare_queries_ex(raw, offs, cfg.scale, st_in,
+                                                           stream=t.stream)
+                code_parts.append(codes)
+                lens += [x.size for x in segs]
+                entries += [(c, chan_read[c], arr) for arr, c in group]
+            codes = torch.cat(code_parts) if len(code_parts) > 1 else code_parts[0]
+            offs_np = np.zeros(len(lens) + 1, np.int64)
+            np.cumsum(lens, out=offs_np[1:])
+            if self.mode == "extend":
+                handles = [rd.handle for _, rd, _ in entries]
+            else:  # from scratch: a fresh stream extended by the whole prefix
+                for _ in entries:
+                    while True:
+                        try:
+                            scratch.append(sd.Stream(t.ref))
+                            break
+                        except sd.SdtwError as e:
+                            if e.code != "EBUDGET":
+                                raise
+                            time.sleep(0.001)
+                handles = scratch
+            cost, end = sd.stream_extend(handles, codes, offs_np, stream=t.stream)
+            ev = torch.cuda.Event()
+            ev.record(t.stream)
+        out = []
+        for c, rd, arr in entries:
+            rd.chunks_done += 1
+            rd.rows = rd.chunks_done * E
+            out.append((c, rd, arr, rd.rows))
+        inflight.append(_Tick(ev, ti, out, cost, end, time.perf_counter(),
+                              float(sum(lens)) * t.ref.n, scratch))
+
+
+def make_targets(specs, torch_device, k: int = 6, scale: float = 64.0):
+    """Targets from (name, genome uint8 array, level table, read pool raw
+    arrays, on-target flags) tuples: the reference is prepared on the device
+    (sdtw_prepare_reference) and loaded as int16."""
+    torch = __import__("torch")
+    out = []
+    for name, genome, table, reads, on in specs:
+        g = torch.from_numpy(genome).to(torch_device)
+        t = torch.from_numpy(table).to(torch_device)
+        _, codes, _ = sd.prepare_reference(g, t, k, scale)
+        out.append(Target(name, sd.Reference(codes), reads, np.asarray(on, bool)))
+    return out
