@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--strip", type=int, default=0)
     ap.add_argument("--chains", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--bands", type=int, default=0, help="waves per read (row bands): 1, 2, 4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the float32 and one-read-per-launch comparison legs")
@@ -87,8 +88,8 @@ def main():
     raw = torch.from_numpy(reads.values).to(dev)
     offs_dev = torch.from_numpy(reads.offsets).to(dev)
     plan = sd.Plan(reads.offsets, dt)
-    if args.strip or args.chains or args.waves:
-        plan.set_config(args.strip, args.chains, args.waves)
+    if args.strip or args.chains or args.waves or args.bands:
+        plan.set_config(args.strip, args.chains, args.waves, args.bands)
     cost = torch.empty(nq, dtype=torch.int32 if dt == sd.I16 else torch.float32, device=dev)
     end = torch.empty(nq, dtype=torch.int32, device=dev)
     cells = float(reads.lengths.sum()) * N
@@ -120,7 +121,7 @@ def main():
     gcups = cells / (ms_step * 1e-3) / 1e9
     kern_tcups = cells / (kern_ms * 1e-3) / 1e12
     peak = valu_peak_tcups(args.dtype)
-    strip, chains, waves = plan.config
+    pcfg = plan.config
 
     out = {
         "metric": "sDTW GCUPS at 1 GPU (% VALU peak)",
@@ -137,7 +138,7 @@ def main():
         "data": "synthetic (seeded genome, stand-in 6-mer pore model, simulated reads)",
         "config": {"workload": w.name, "reads": nq, "query_values": int(reads.values.size),
                    "reference_values": N, "cells_per_step": cells,
-                   "strip": strip, "chains": chains, "waves_per_cu": waves},
+                   **pcfg},
         "reads_per_s": round(nq / (ms_step * 1e-3), 1),
         "pct_valu_peak": round(100 * gcups / (peak * 1e3), 2),
         "roofline": {"bound": "alu", "kernel": "sdtw_align_batch",

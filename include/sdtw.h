@@ -192,11 +192,19 @@ int sdtw_plan_info(sdtw_plan plan, int32_t* nq, int* dtype, int32_t* max_m);
  *           4 (0 = keep); strip / chains must be a multiple of 4.  Reads
  *           with M >= 64 * chains + 1 use that many; shorter reads fall back
  *           to fewer chains, and reads with M <= 64 to the one-wave kernel.
+ *   bands   waves per read: 1, 2 or 4 (0 = keep the plan's where they fit the
+ *           other settings, else 1); more than 1 needs strip 16
+ *           and at most 2 chains.  A read's rows are cut into up to `bands`
+ *           row bands of at least 64 * chains + 1 rows each (Eq. 1: a row
+ *           depends on the rows above only through the previous row), one
+ *           wave per band, pipelined over the reference tiles.
  *   waves_per_cu  resident waves per compute unit for the persistent grid,
- *           1..32 (0 = keep).
+ *           1..32 (0 = keep); a multiple of bands.
+ * EINVAL for values outside these sets.
  */
-int sdtw_plan_set_config(sdtw_plan plan, int strip, int chains, int waves_per_cu);
-int sdtw_plan_get_config(sdtw_plan plan, int* strip, int* chains, int* waves_per_cu);
+int sdtw_plan_set_config(sdtw_plan plan, int strip, int chains, int bands, int waves_per_cu);
+int sdtw_plan_get_config(sdtw_plan plan, int* strip, int* chains, int* bands,
+                         int* waves_per_cu);
 
 /* Release a plan (synchronise the streams that used it first). */
 int sdtw_plan_destroy(sdtw_plan plan);
@@ -283,6 +291,15 @@ int sdtw_stream_copy_row(sdtw_stream s, void* dst_dev, void* stream);
 int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk_dev,
                        const int64_t* chunk_offsets_host, void* cost_dev, int32_t* end_dev,
                        void* stream);
+
+/*
+ * Waves per chunk for later sdtw_stream_extend calls in this process (the
+ * row bands of sdtw_plan_set_config): 1, 2 or 4, or 0 (the default) for
+ * automatic: 4 when a call has fewer than 8 chunks per compute unit and its
+ * longest chunk has at least 130 rows, else 1.  Results never depend on it.
+ * EINVAL for other values.
+ */
+int sdtw_stream_set_bands(int bands);
 
 #ifdef __cplusplus
 }

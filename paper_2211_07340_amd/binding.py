@@ -49,13 +49,14 @@ def load_library():
         "sdtw_free_reference": ([p], C.c_int),
         "sdtw_plan_create": ([p, i32, C.c_int, C.POINTER(p)], C.c_int),
         "sdtw_plan_info": ([p, C.POINTER(i32), C.POINTER(C.c_int), C.POINTER(i32)], C.c_int),
-        "sdtw_plan_set_config": ([p, C.c_int, C.c_int, C.c_int], C.c_int),
+        "sdtw_plan_set_config": ([p, C.c_int, C.c_int, C.c_int, C.c_int], C.c_int),
         "sdtw_plan_get_config": ([p, C.POINTER(C.c_int), C.POINTER(C.c_int),
-                                  C.POINTER(C.c_int)], C.c_int),
+                                  C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
         "sdtw_plan_destroy": ([p], C.c_int),
         "sdtw_align_batch": ([p, p, p, p, p, p], C.c_int),
         "sdtw_align_one": ([p, p, i32, p, p, p], C.c_int),
         "sdtw_prepare_queries_ex": ([p, p, i32, dbl, p, p, p, p, p, p], C.c_int),
+        "sdtw_stream_set_bands": ([C.c_int], C.c_int),
         "sdtw_set_row_budget": ([i64], C.c_int),
         "sdtw_row_budget_info": ([C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)], C.c_int),
         "sdtw_stream_open": ([p, C.POINTER(p)], C.c_int),
@@ -233,16 +234,20 @@ class Plan:
             raise SdtwError(5, "plan is closed")
         return self._h
 
-    def set_config(self, strip: int = 0, chains: int = 0, waves_per_cu: int = 0):
-        _check(load_library().sdtw_plan_set_config(self.handle, strip, chains, waves_per_cu))
+    def set_config(self, strip: int = 0, chains: int = 0, waves_per_cu: int = 0,
+                   bands: int = 0):
+        """sdtw_plan_set_config; 0 keeps a setting."""
+        _check(load_library().sdtw_plan_set_config(self.handle, strip, chains, bands,
+                                                   waves_per_cu))
 
     @property
     def config(self):
-        """(strip, chains, waves_per_cu)"""
-        s, k, w = C.c_int(), C.c_int(), C.c_int()
+        """dict(strip, chains, bands, waves_per_cu)"""
+        s, k, b, w = C.c_int(), C.c_int(), C.c_int(), C.c_int()
         _check(load_library().sdtw_plan_get_config(self.handle, C.byref(s), C.byref(k),
-                                                   C.byref(w)))
-        return s.value, k.value, w.value
+                                                   C.byref(b), C.byref(w)))
+        return {"strip": s.value, "chains": k.value, "bands": b.value,
+                "waves_per_cu": w.value}
 
     def close(self):
         if self._h is not None:
@@ -294,6 +299,11 @@ def align_one(ref: Reference, q, cost=None, end=None, stream=None):
 def set_row_budget(nbytes: int):
     """Byte budget of resident rows on the current device."""
     _check(load_library().sdtw_set_row_budget(int(nbytes)))
+
+
+def set_stream_bands(bands: int):
+    """Waves per chunk of later stream_extend calls: 1, 2, 4 or 0 (automatic)."""
+    _check(load_library().sdtw_stream_set_bands(int(bands)))
 
 
 def row_budget_info():

@@ -203,19 +203,6 @@ __device__ __forceinline__ void load_strip(uint32_t (&dst)[W], const uint32_t* _
 // Continuous-skew kernel
 // ---------------------------------------------------------------------------
 
-template <class F, int W, int K, bool STREAM>
-struct SkewLds {
-  static constexpr int kStage = 64 * W;             // next tile's strips / finished last rows
-  static constexpr int kAcc = STREAM ? 64 * W : 0;  // next tile's resident-row strips
-  static constexpr int kLeft = STREAM ? 64 : 0;     // resident value left of each strip
-  static constexpr int kZeros = STREAM ? 0 : W;     // gamma(0, .) = 0 for fresh reads
-  // + query/boundary pairs: max_m + 64K entries of 8 bytes
-  static size_t bytes(int max_m) {
-    size_t b = 4 * ((size_t)kStage + kAcc + kLeft + kZeros) + 8 * ((size_t)max_m + 64 * K);
-    return (b + 15) & ~(size_t)15;
-  }
-};
-
 // K chains per lane.  Lane l's strip of W columns is cut into K sub-strips of
 // H = W/K columns; sub-strip h is "sub-lane" s = K*l + h and works on row
 // (t - s) mod M of its tile at step t.  Within a step the K sub-strips of a
@@ -224,58 +211,100 @@ struct SkewLds {
 // chain 0 takes lane l-1's last-column edge by DPP, chain h > 0 takes the
 // lane's own chain h-1 edge, still in its row buffer.
 //
-// LDS layout of the query and the left-boundary column, one 8-byte entry per
-// k in [0, M + 64K):
-//   bx[k].x = query row (k - (64K - 1)) mod M   (biased int16 or float bits)
-//   bx[k].y = boundary gamma(row k - (64K - 1), last column of the previous
-//             tile) for k in [64K - 1, M + 64K - 1)
+// P row bands.  A workgroup of P waves aligns one read: its M rows are cut
+// into Pe <= P bands of consecutive rows (band g: rows [g M / Pe,
+// (g + 1) M / Pe), each at least 64K + 1 rows) and wave g sweeps band g over
+// every tile with the one-wave schedule above.  Row i of Eq. 1 depends on the
+// rows above it only through row i - 1, so band g's "previous row" on a tile
+// is band g - 1's last row on that tile; it is handed over through an LDS ring
+// of two tile slots (and a ring of four values for each tile's last column,
+// the diagonal lane 0 needs when it enters the next tile).  The workgroup
+// runs global periods with one barrier after each; wave g runs its local
+// period p = G - 2g, so a slot is written (during the writer's switch steps
+// of its period t + 1) one barrier before it is read (during the reader's
+// switch steps of its period t) and rewritten only after its last read.
+// Pe = min(P, M / (64K + 1)); waves g >= Pe idle through the barriers.
+//
+// LDS layout of the query and the left-boundary column of a band, one 8-byte
+// entry per k in [0, M_g + 64K):
+//   bx[k].x = band row (k - (64K - 1)) mod M_g   (biased int16 or float bits)
+//   bx[k].y = boundary gamma(band row k - (64K - 1), last column of the
+//             previous tile) for k in [64K - 1, M_g + 64K - 1)
 // Chain h of lane l reads its row r of the current period at entry
 // K(63 - l) + r + (K - 1 - h); so lane 0's chain 0 finds boundary row r at
 // entry 64K - 1 + r, and the last sub-lane (lane 63, chain K-1) writes its
-// boundary row r - (64K - 1) at entry r, its own entry (at r + M while that
+// boundary row r - (64K - 1) at entry r, its own entry (at r + M_g while that
 // row is in the previous period).
 //
 // STREAM: each work item extends a resident row acc = gamma(m_old, .) by the
 // M rows of one chunk (rows m_old+1 .. m_old+M of the read): when a sub-lane
-// enters a tile its previous row is acc's strip (instead of zeros) and its
-// diagonal is acc one column to the left (+inf left of column 0); the
-// finished last row of every tile is written back to acc.  A tile's acc is
-// staged one period before that tile's write-back, so reads see the row as
-// it was before this extension.
-template <class F, int W, int K, bool STREAM>
-__global__ __launch_bounds__(64) void k_align_skew(AlignArgs args) {
-  using Lay = SkewLds<F, W, K, STREAM>;
+// of band 0 enters a tile its previous row is acc's strip (instead of zeros)
+// and its diagonal is acc one column to the left (+inf left of column 0);
+// the last band writes the finished last row of every tile back to acc.  A
+// tile's acc is staged one period before that tile's write-back, so reads
+// see the row as it was before this extension.
+//
+// LDS (uint32 words, every array on 16 bytes): zeros[W] and a +inf cell
+// (4 words); STREAM: acc strips [64W] and the value left of each [64];
+// ring[P-1][2][64W]; edge[P-1][4]; per band: stage[64W] (next tile's strips;
+// in the last band also the finished last rows) and bx.
+template <class F, int W, int K, int P, bool STREAM>
+__global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
   constexpr int T = 64 * W;
   constexpr int H = W / K;
   constexpr int S = 64 * K;                   // sub-lanes = switch steps per period
   constexpr int U = K > 2 ? K : 2;            // phase-A unroll: chain index compile-time
   static_assert(W % K == 0 && H % 4 == 0, "sub-strips are whole uint4 groups");
   extern __shared__ __align__(16) uint32_t smem[];
-  const int lane = (int)threadIdx.x;
-  uint32_t* const stage = smem;
-  uint32_t* const accst = stage + Lay::kStage;
-  uint32_t* const accleft = accst + Lay::kAcc;
-  uint32_t* const zeros = accleft + Lay::kLeft;
-  uint2* const bx = (uint2*)(zeros + Lay::kZeros);
+  __shared__ int32_t s_item;
+  const int lane = (int)threadIdx.x & 63;
+  const int wave = P > 1 ? __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6) : 0;
+  uint32_t* const zeros = smem;
+  uint32_t* const inf_cell = zeros + W;
+  uint32_t* const accst = inf_cell + 4;
+  uint32_t* const accleft = accst + (STREAM ? T : 0);
+  uint32_t* const ring = accleft + (STREAM ? 64 : 0);
+  uint32_t* const edge = ring + (P - 1) * 2 * T;
+  uint32_t* const stage = edge + (P - 1) * 4 + wave * skew_band_words(W, K, args.max_band);
+  uint2* const bx = (uint2*)(stage + T);
   uint32_t* const my_stage = stage + lane * W;
   uint32_t* const my_acc = accst + lane * W;
   uint2* const bxl = bx + K * (63 - lane);
+  uint32_t* const ring_in = ring + (wave > 0 ? wave - 1 : 0) * 2 * T + lane * W;
+  uint32_t* const ring_out = ring + (wave < P - 1 ? wave : 0) * 2 * T + lane * W;
+  uint32_t* const edge_in = edge + (wave > 0 ? wave - 1 : 0) * 4;
+  uint32_t* const edge_out = edge + (wave < P - 1 ? wave : 0) * 4;
 
-  if constexpr (!STREAM) {
+  if (wave == 0) {
     if (lane < W) zeros[lane] = 0u;
+    if (lane == 0) *inf_cell = F::kInf;
   }
   const int32_t N = (int32_t)args.n;
   const int32_t ntiles = (N + T - 1) / T;
 
   for (;;) {
-    // Work pull without a divergent branch: every lane takes part in the
-    // atomic and only lane 0 adds 1, so lane 0's return value is the item
-    // whatever order the lanes are serviced in.  (Guarding the atomic with
-    // `if (lane == 0)` lets the loop structurizer split the wave around the
-    // readfirstlane below, leaving lanes 1..63 to re-read a stale item.)
-    int32_t item = atomicAdd(args.counter, lane == 0 ? 1 : 0);
-    item = __builtin_amdgcn_readfirstlane(item);
-    if (item >= args.nwork) break;
+    // Work pull without a divergent branch around the atomic: every lane of
+    // the pulling wave takes part and only lane 0 adds 1, so lane 0's return
+    // value is the item whatever order the lanes are serviced in.  (Guarding
+    // the atomic with `if (lane == 0)` lets the loop structurizer split the
+    // wave around the readfirstlane, leaving lanes 1..63 a stale item.)
+    int32_t item;
+    if constexpr (P == 1) {
+      item = atomicAdd(args.counter, lane == 0 ? 1 : 0);
+      item = __builtin_amdgcn_readfirstlane(item);
+      if (item >= args.nwork) break;
+      __syncthreads();  // previous read's LDS use is complete
+    } else {
+      __syncthreads();  // every wave is done with the previous item and its LDS
+      if (wave == 0) {
+        int32_t it = atomicAdd(args.counter, lane == 0 ? 1 : 0);
+        it = __builtin_amdgcn_readfirstlane(it);
+        if (lane == 0) s_item = it;
+      }
+      __syncthreads();
+      item = __builtin_amdgcn_readfirstlane(s_item);
+      if (item >= args.nwork) break;
+    }
     int32_t rd, M, m_old = 0;
     int64_t q0;
     uint32_t* acc = nullptr;
@@ -292,7 +321,16 @@ __global__ __launch_bounds__(64) void k_align_skew(AlignArgs args) {
       M = __builtin_amdgcn_readfirstlane(args.offs ? (int32_t)(args.offs[rd + 1] - q0)
                                                    : args.single_m);
     }
-    const typename F::qin* __restrict__ qv = (const typename F::qin*)args.q + q0;
+    int32_t Pe = 1;
+    if constexpr (P > 1) {
+      Pe = M / (S + 1);
+      Pe = Pe < 1 ? 1 : (Pe > P ? P : Pe);
+    }
+    const bool active = wave < Pe;
+    const bool last = wave == Pe - 1;
+    const int32_t r0 = (wave * M) / Pe;
+    const int32_t Mb = ((wave + 1) * M) / Pe - r0;  // this band's rows
+    const typename F::qin* __restrict__ qv = (const typename F::qin*)args.q + q0 + r0;
     // resident row of tile t into this lane's LDS strip (and the value left
     // of the strip); a fresh read (m_old == 0) stages gamma(0, .) = 0
     auto stage_acc = [&](int32_t t) {
@@ -313,19 +351,18 @@ __global__ __launch_bounds__(64) void k_align_skew(AlignArgs args) {
       }
     };
 
-    __syncthreads();  // previous read's LDS use is complete
-    for (int k = lane; k < M + S; k += 64) {
-      int s = k - (S - 1);
-      s = s < 0 ? s + M : (s >= M ? s - M : s);
-      bx[k] = make_uint2((uint32_t)F::to_lds(qv[s]), F::kInf);  // gamma(i, 0) = +inf
-    }
-    {
+    if (active) {
+      for (int k = lane; k < Mb + S; k += 64) {
+        int s = k - (S - 1);
+        s = s < 0 ? s + Mb : (s >= Mb ? s - Mb : s);
+        bx[k] = make_uint2((uint32_t)F::to_lds(qv[s]), F::kInf);  // gamma(i, 0) = +inf
+      }
       uint32_t t0[W];
       load_strip<W>(t0, args.ref + lane * W);
 #pragma unroll
       for (int w = 0; w < W; ++w) my_stage[w] = t0[w];
+      if (wave == 0) stage_acc(0);
     }
-    stage_acc(0);
     __syncthreads();
 
     uint32_t y[W], a[W], b[W], dprev[K];
@@ -338,35 +375,50 @@ __global__ __launch_bounds__(64) void k_align_skew(AlignArgs args) {
 
     // The entries of step r + 1 are read during step r (before step r's own
     // boundary write): lane 0's row r + 1 was written by the last sub-lane
-    // at least two steps earlier when M >= 64K + 1, which the launcher
-    // guarantees.
-    uint2 nxt[K];
-    auto load_entries = [&](int32_t r, uint2(&e)[K]) {
+    // at least two steps earlier when M_g >= 64K + 1, which the launcher
+    // guarantees.  Only chain 0 takes a boundary value; chains h > 0 load the
+    // query half of their entry alone, so that every register a prefetch
+    // writes stays live until the next step (a dead half would let the
+    // register allocator reuse it at once and wait for the load right there).
+    uint2 nxt0;
+    uint32_t nxtx[K];
+    auto load_entries = [&](int32_t r) {
+      nxt0 = bxl[r + (K - 1)];
 #pragma unroll
-      for (int h = 0; h < K; ++h) e[h] = bxl[r + (K - 1 - h)];
+      for (int h = 1; h < K; ++h) nxtx[h] = bxl[r + (K - 1 - h)].x;
     };
+    // Per period: where a sub-lane entering tile p takes its previous row
+    // (zeros, the staged resident row, or the band above's ring slot) and the
+    // diagonal left of it, and where its finished strip of tile p - 1 goes
+    // (the stage in the last band, for the fold; the ring otherwise).
+    int32_t p = 0;
+    const uint32_t* upsrc = zeros;
+    const uint32_t* d0src = zeros;
+    uint32_t* fin = my_stage;
     // One row step.  CH >= 0: sub-lane r (lane r / K, chain CH == r % K)
     // enters its next tile in this step; the edges its right neighbours need
     // are read before the switch overwrites `up`.
     auto step = [&](auto ch, int32_t r, uint32_t(&up)[W], uint32_t(&nw)[W], bool write_b,
                     bool wrap) {
       constexpr int CH = decltype(ch)::value;
-      uint2 e[K];
+      const uint2 e0 = nxt0;
+      uint32_t xs[K];
 #pragma unroll
-      for (int h = 0; h < K; ++h) e[h] = nxt[h];
-      load_entries(r + 1, nxt);
+      for (int h = 1; h < K; ++h) xs[h] = nxtx[h];
+      xs[0] = e0.x;
+      load_entries(r + 1);
       uint32_t left[K];
-      left[0] = asm_from_left_lane(up[W - 1], e[0].y);
+      left[0] = asm_from_left_lane(up[W - 1], e0.y);
 #pragma unroll
       for (int h = 1; h < K; ++h) left[h] = up[h * H - 1];
       if constexpr (CH >= 0) {
         if (lane == r / K) {
-          const uint32_t* const src = STREAM ? my_acc : zeros;
+          const uint32_t old_last = up[W - 1];
 #pragma unroll
           for (int w = CH * H; w < (CH + 1) * H; w += 4) {
             const uint4 nv = *(const uint4*)(my_stage + w);
-            *(uint4*)(my_stage + w) = make_uint4(up[w], up[w + 1], up[w + 2], up[w + 3]);
-            const uint4 zv = *(const uint4*)(src + (STREAM ? w : w - CH * H));
+            *(uint4*)(fin + w) = make_uint4(up[w], up[w + 1], up[w + 2], up[w + 3]);
+            const uint4 zv = *(const uint4*)(upsrc + w);
             y[w] = nv.x;
             y[w + 1] = nv.y;
             y[w + 2] = nv.z;
@@ -376,83 +428,99 @@ __global__ __launch_bounds__(64) void k_align_skew(AlignArgs args) {
             up[w + 2] = zv.z;
             up[w + 3] = zv.w;
           }
-          if constexpr (STREAM) dprev[CH] = CH == 0 ? accleft[lane] : my_acc[CH * H - 1];
+          dprev[CH] = CH == 0 ? *d0src : upsrc[CH * H - 1];
+          if constexpr (P > 1 && CH == K - 1) {
+            if (!last && lane == 63) edge_out[(p - 1) & 3] = old_last;
+          }
         }
       }
-      uint32_t xs[K];
-#pragma unroll
-      for (int h = 0; h < K; ++h) xs[h] = e[h].x;
       chains_row<F, K, H, W>(xs, y, up, nw, dprev, left);
 #pragma unroll
       for (int h = 0; h < K; ++h) dprev[h] = left[h];
-      if (write_b && lane == 63) bxl[wrap ? r + M : r].y = nw[W - 1];
+      if (write_b && lane == 63) bxl[wrap ? r + Mb : r].y = nw[W - 1];
     };
     using NoSwitch = std::integral_constant<int, -1>;
 
-    for (int32_t p = 0;; ++p) {
-      // phase A: the 64K switch steps
-      const bool first = (p == 0);
-      load_entries(0, nxt);  // row 0 of the period (entry 64K - 1 + M is not kept)
-      for (int32_t r = 0; r < S; r += U) {
-        // chain index of step r + u is (r + u) % K == u % K since U % K == 0
-        static_for<0, U / 2>([&](auto uu) {
-          constexpr int u = 2 * decltype(uu)::value;
-          step(std::integral_constant<int, u % K>{}, r + u, a, b, !first || r + u == S - 1,
-               r + u != S - 1);
-          step(std::integral_constant<int, (u + 1) % K>{}, r + u + 1, b, a,
-               !first || r + u + 1 == S - 1, r + u + 1 != S - 1);
-        });
-      }
-      // every lane has finished tile p-1: fold its last row (and write it
-      // back as the new resident row), stage tile p+1
-      if (p >= 1) {
-        const int32_t jb = (p - 1) * T + lane * W;
-        uint32_t lr[W];
+    const int32_t nglob = ntiles + 1 + 2 * (Pe - 1);
+    for (int32_t G = 0; G < nglob; ++G) {
+      p = G - 2 * wave;
+      if (active && p >= 0 && p <= ntiles) {
+        if (wave == 0) {
+          upsrc = STREAM ? my_acc : zeros;
+          d0src = STREAM ? accleft + lane : zeros;
+        } else {
+          upsrc = ring_in + (p & 1) * T;
+          d0src = lane > 0 ? upsrc - 1 : (p > 0 ? edge_in + ((p - 1) & 3) : inf_cell);
+        }
+        fin = last ? my_stage : ring_out + ((p - 1) & 1) * T;
+        // phase A: the 64K switch steps
+        const bool first = (p == 0);
+        load_entries(0);  // row 0 of the period (entry 64K - 1 + M_g is not kept)
+        for (int32_t r = 0; r < S; r += U) {
+          // chain index of step r + u is (r + u) % K == u % K since U % K == 0
+          static_for<0, U / 2>([&](auto uu) {
+            constexpr int u = 2 * decltype(uu)::value;
+            step(std::integral_constant<int, u % K>{}, r + u, a, b, !first || r + u == S - 1,
+                 r + u != S - 1);
+            step(std::integral_constant<int, (u + 1) % K>{}, r + u + 1, b, a,
+                 !first || r + u + 1 == S - 1, r + u + 1 != S - 1);
+          });
+        }
+        // every lane has finished tile p-1: the last band folds its last row
+        // (and writes it back as the new resident row); stage tile p+1
+        if (p >= 1 && last) {
+          const int32_t jb = (p - 1) * T + lane * W;
+          uint32_t lr[W];
 #pragma unroll
-        for (int w = 0; w < W; ++w) {
-          lr[w] = my_stage[w];
-          if (jb + w < N && lr[w] < best) {
-            best = lr[w];
-            bestj = jb + w;
+          for (int w = 0; w < W; ++w) {
+            lr[w] = my_stage[w];
+            if (jb + w < N && lr[w] < best) {
+              best = lr[w];
+              bestj = jb + w;
+            }
+          }
+          if constexpr (STREAM) {
+#pragma unroll
+            for (int w = 0; w < W; w += 4)
+              *(uint4*)(acc + jb + w) = make_uint4(lr[w], lr[w + 1], lr[w + 2], lr[w + 3]);
           }
         }
-        if constexpr (STREAM) {
+        if (p + 1 < ntiles) {
+          uint32_t t1[W];
+          load_strip<W>(t1, args.ref + (int64_t)(p + 1) * T + lane * W);
 #pragma unroll
-          for (int w = 0; w < W; w += 4)
-            *(uint4*)(acc + jb + w) = make_uint4(lr[w], lr[w + 1], lr[w + 2], lr[w + 3]);
+          for (int w = 0; w < W; ++w) my_stage[w] = t1[w];
+          if (wave == 0) stage_acc(p + 1);
+        }
+        if (p < ntiles) {
+          // phase B: plain steps, four per iteration
+          int32_t r = S;
+          for (; r + 3 < Mb; r += 4) {
+            step(NoSwitch{}, r, a, b, true, false);
+            step(NoSwitch{}, r + 1, b, a, true, false);
+            step(NoSwitch{}, r + 2, a, b, true, false);
+            step(NoSwitch{}, r + 3, b, a, true, false);
+          }
+          for (; r + 1 < Mb; r += 2) {
+            step(NoSwitch{}, r, a, b, true, false);
+            step(NoSwitch{}, r + 1, b, a, true, false);
+          }
+          if (r < Mb) {
+            step(NoSwitch{}, r, a, b, true, false);
+#pragma unroll
+            for (int w = 0; w < W; ++w) a[w] = b[w];
+          }
         }
       }
-      if (p + 1 < ntiles) {
-        uint32_t t1[W];
-        load_strip<W>(t1, args.ref + (int64_t)(p + 1) * T + lane * W);
-#pragma unroll
-        for (int w = 0; w < W; ++w) my_stage[w] = t1[w];
-        stage_acc(p + 1);
-      }
-      if (p == ntiles) break;
-      // phase B: plain steps, four per iteration
-      int32_t r = S;
-      for (; r + 3 < M; r += 4) {
-        step(NoSwitch{}, r, a, b, true, false);
-        step(NoSwitch{}, r + 1, b, a, true, false);
-        step(NoSwitch{}, r + 2, a, b, true, false);
-        step(NoSwitch{}, r + 3, b, a, true, false);
-      }
-      for (; r + 1 < M; r += 2) {
-        step(NoSwitch{}, r, a, b, true, false);
-        step(NoSwitch{}, r + 1, b, a, true, false);
-      }
-      if (r < M) {
-        step(NoSwitch{}, r, a, b, true, false);
-#pragma unroll
-        for (int w = 0; w < W; ++w) a[w] = b[w];
-      }
+      if constexpr (P > 1) __syncthreads();
     }
 
-    wave_argmin(best, bestj);
-    if (lane == 0) {
-      F::store_cost(args.cost, rd, best);
-      args.end[rd] = bestj;
+    if (last) {
+      wave_argmin(best, bestj);
+      if (lane == 0) {
+        F::store_cost(args.cost, rd, best);
+        args.end[rd] = bestj;
+      }
     }
   }
 }
@@ -584,21 +652,21 @@ __global__ void k_reset_counter(int32_t* c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
 }
 
-template <class F, int W, int K, bool STREAM>
+template <class F, int W, int K, int P, bool STREAM>
 hipError_t launch_skew_t(int blocks, const AlignArgs& a, hipStream_t st) {
-  const size_t lds = SkewLds<F, W, K, STREAM>::bytes(a.max_m);
-  hipError_t e = hipFuncSetAttribute((const void*)k_align_skew<F, W, K, STREAM>,
+  const size_t lds = skew_lds_bytes(W, K, P, a.max_band, STREAM);
+  hipError_t e = hipFuncSetAttribute((const void*)k_align_skew<F, W, K, P, STREAM>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, a.counter);
-  hipLaunchKernelGGL((k_align_skew<F, W, K, STREAM>), dim3(blocks), dim3(64), lds, st, a);
+  hipLaunchKernelGGL((k_align_skew<F, W, K, P, STREAM>), dim3(blocks), dim3(64 * P), lds, st, a);
   return hipGetLastError();
 }
 
-template <class F, int W, int K>
+template <class F, int W, int K, int P>
 hipError_t launch_skew_s(int blocks, const AlignArgs& a, hipStream_t st, bool stream) {
-  return stream ? launch_skew_t<F, W, K, true>(blocks, a, st)
-                : launch_skew_t<F, W, K, false>(blocks, a, st);
+  return stream ? launch_skew_t<F, W, K, P, true>(blocks, a, st)
+                : launch_skew_t<F, W, K, P, false>(blocks, a, st);
 }
 
 template <class F, int W>
@@ -615,18 +683,23 @@ hipError_t launch_plain_t(const AlignArgs& a, hipStream_t st, bool stream) {
   return hipGetLastError();
 }
 
+// the (strip, chains, bands) set valid_skew_config() admits
 template <class F>
-hipError_t launch_skew_f(int strip, int chains, int blocks, const AlignArgs& a, hipStream_t st,
-                         bool stream) {
-  switch (strip * 8 + chains) {
-    case 8 * 8 + 1: return launch_skew_s<F, 8, 1>(blocks, a, st, stream);
-    case 8 * 8 + 2: return launch_skew_s<F, 8, 2>(blocks, a, st, stream);
-    case 16 * 8 + 1: return launch_skew_s<F, 16, 1>(blocks, a, st, stream);
-    case 16 * 8 + 2: return launch_skew_s<F, 16, 2>(blocks, a, st, stream);
-    case 16 * 8 + 4: return launch_skew_s<F, 16, 4>(blocks, a, st, stream);
-    case 32 * 8 + 1: return launch_skew_s<F, 32, 1>(blocks, a, st, stream);
-    case 32 * 8 + 2: return launch_skew_s<F, 32, 2>(blocks, a, st, stream);
-    case 32 * 8 + 4: return launch_skew_s<F, 32, 4>(blocks, a, st, stream);
+hipError_t launch_skew_f(int strip, int chains, int bands, int blocks, const AlignArgs& a,
+                         hipStream_t st, bool stream) {
+  switch ((strip * 8 + chains) * 8 + bands) {
+    case (8 * 8 + 1) * 8 + 1: return launch_skew_s<F, 8, 1, 1>(blocks, a, st, stream);
+    case (8 * 8 + 2) * 8 + 1: return launch_skew_s<F, 8, 2, 1>(blocks, a, st, stream);
+    case (16 * 8 + 1) * 8 + 1: return launch_skew_s<F, 16, 1, 1>(blocks, a, st, stream);
+    case (16 * 8 + 2) * 8 + 1: return launch_skew_s<F, 16, 2, 1>(blocks, a, st, stream);
+    case (16 * 8 + 4) * 8 + 1: return launch_skew_s<F, 16, 4, 1>(blocks, a, st, stream);
+    case (32 * 8 + 1) * 8 + 1: return launch_skew_s<F, 32, 1, 1>(blocks, a, st, stream);
+    case (32 * 8 + 2) * 8 + 1: return launch_skew_s<F, 32, 2, 1>(blocks, a, st, stream);
+    case (32 * 8 + 4) * 8 + 1: return launch_skew_s<F, 32, 4, 1>(blocks, a, st, stream);
+    case (16 * 8 + 1) * 8 + 2: return launch_skew_s<F, 16, 1, 2>(blocks, a, st, stream);
+    case (16 * 8 + 1) * 8 + 4: return launch_skew_s<F, 16, 1, 4>(blocks, a, st, stream);
+    case (16 * 8 + 2) * 8 + 2: return launch_skew_s<F, 16, 2, 2>(blocks, a, st, stream);
+    case (16 * 8 + 2) * 8 + 4: return launch_skew_s<F, 16, 2, 4>(blocks, a, st, stream);
   }
   return hipErrorInvalidValue;
 }
@@ -642,15 +715,6 @@ hipError_t launch_plain_f(int strip, const AlignArgs& a, hipStream_t st, bool st
 }
 
 template <class F>
-size_t skew_bytes_f(int strip, int chains, int max_m, bool stream) {
-  if (!valid_strip_chains(strip, chains)) return 0;
-  // mirrors SkewLds: stage (+ resident strips and left values) or zeros,
-  // then the query/boundary entries
-  const size_t u32 = stream ? (size_t)64 * strip * 2 + 64 : (size_t)64 * strip + strip;
-  return (4 * u32 + 8 * ((size_t)max_m + 64 * chains) + 15) & ~(size_t)15;
-}
-
-template <class F>
 size_t plain_bytes_f(int strip, int max_m) {
   switch (strip) {
     case 8: return PlainLds<F, 8>::bytes(max_m);
@@ -662,21 +726,17 @@ size_t plain_bytes_f(int strip, int max_m) {
 
 }  // namespace
 
-hipError_t launch_align_skew(int dtype, int strip, int chains, int blocks, const AlignArgs& a,
-                             hipStream_t st, bool stream) {
-  return dtype == SDTW_I16 ? launch_skew_f<FmtI16>(strip, chains, blocks, a, st, stream)
-                           : launch_skew_f<FmtF32>(strip, chains, blocks, a, st, stream);
+hipError_t launch_align_skew(int dtype, int strip, int chains, int bands, int blocks,
+                             const AlignArgs& a, hipStream_t st, bool stream) {
+  if (!valid_skew_config(strip, chains, bands)) return hipErrorInvalidValue;
+  return dtype == SDTW_I16 ? launch_skew_f<FmtI16>(strip, chains, bands, blocks, a, st, stream)
+                           : launch_skew_f<FmtF32>(strip, chains, bands, blocks, a, st, stream);
 }
 
 hipError_t launch_align_plain(int dtype, int strip, const AlignArgs& a, hipStream_t st,
                               bool stream) {
   return dtype == SDTW_I16 ? launch_plain_f<FmtI16>(strip, a, st, stream)
                            : launch_plain_f<FmtF32>(strip, a, st, stream);
-}
-
-size_t skew_lds_bytes(int dtype, int strip, int chains, int max_m, bool stream) {
-  return dtype == SDTW_I16 ? skew_bytes_f<FmtI16>(strip, chains, max_m, stream)
-                           : skew_bytes_f<FmtF32>(strip, chains, max_m, stream);
 }
 
 size_t plain_lds_bytes(int dtype, int strip, int max_m) {

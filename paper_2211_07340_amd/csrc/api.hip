@@ -54,7 +54,8 @@ struct sdtw_plan_s {
   int32_t* counter_dev;           // [1]
   int strip;                      // columns per lane
   int chains;                     // most chains per lane (K) the long reads use
-  int waves_per_cu;               // persistent grid density
+  int bands;                      // waves per read (row bands) of the skew kernel
+  int waves_per_cu;               // persistent grid density (bands x workgroups per CU)
   int cus;                        // compute units of the device
 };
 
@@ -157,6 +158,7 @@ struct DescRing {
   int next = 0;
 };
 static DescRing g_ring[kMaxDevices];
+static std::atomic<int> g_stream_bands{0};  // sdtw_stream_set_bands (0: automatic)
 
 static int ensure_slot(DescSlot& sl, int32_t n) {
   if (sl.cap >= n) return SDTW_OK;
@@ -317,11 +319,11 @@ int sdtw_free_reference(sdtw_ref ref) {
 // plans
 // ---------------------------------------------------------------------------
 
-// One launch of the batch: reads order[first, first + count), all with
-// lengths in [min_m, max_m], run by the skew kernel with `chains` chains per
-// lane (chains == 0: the synchronised single-wave kernel).
+// One launch of the batch: reads order[first, first + count), longest first,
+// run by the skew kernel with `chains` chains per lane and `bands` waves per
+// read (chains == 0: the synchronised single-wave kernel).
 struct LaunchGroup {
-  int32_t first, count, max_m, chains;
+  int32_t first, count, max_m, chains, bands, max_band;
 };
 
 static std::vector<LaunchGroup> launch_groups(const sdtw_plan_s* p) {
@@ -330,31 +332,56 @@ static std::vector<LaunchGroup> launch_groups(const sdtw_plan_s* p) {
   const int32_t n = p->nq;
   for (int k = p->chains; k >= 1; k /= 2) {
     if (!valid_strip_chains(p->strip, k)) continue;
+    const int bands = valid_skew_config(p->strip, k, p->bands) ? p->bands : 1;
     const int32_t lo = skew_min_m(k);
     const int32_t start = pos;
-    while (pos < n && p->sorted_m[pos] >= lo) ++pos;
-    if (pos > start) g.push_back({start, pos - start, p->sorted_m[start], k});
+    int32_t max_band = 0;
+    while (pos < n && p->sorted_m[pos] >= lo) {
+      max_band = std::max(max_band, skew_band_rows(p->sorted_m[pos], k, bands));
+      ++pos;
+    }
+    if (pos > start) g.push_back({start, pos - start, p->sorted_m[start], k, bands, max_band});
   }
-  if (pos < n) g.push_back({pos, n - pos, p->sorted_m[pos], 0});
+  if (pos < n) g.push_back({pos, n - pos, p->sorted_m[pos], 0, 1, 0});
   return g;
 }
 
+// Resident waves per CU for a skew launch: whole workgroups of `bands` waves
+// within the CU's 160 KiB of LDS, at most 16 waves (four per SIMD).
+static int skew_waves_per_cu(int strip, int chains, int bands, int max_band, bool stream) {
+  const size_t per = skew_lds_bytes(strip, chains, bands, max_band, stream);
+  const int groups = (int)std::min<size_t>(16 / bands, (160 * 1024) / std::max<size_t>(per, 1));
+  return std::max(groups, 1) * bands;
+}
+
+// Default launch shape.  A wave issues about one VALU instruction per 10
+// cycles when its instructions depend on each other and no faster than one
+// per 5 cycles however independent they are (measured on gfx950), while a
+// SIMD issues one per about 4.3 cycles from two or more waves.  So every SIMD
+// needs two or more waves: with four or more reads per SIMD one wave per
+// read and one chain per lane; with fewer, each read is cut into row bands
+// (four waves per read) when its rows allow, else two chains per lane.
 static void choose_config(sdtw_plan_s* p) {
   p->strip = 16;
-  // Chains per lane follow occupancy.  Each lane's row is a serial chain of
-  // dependent instructions (about 10 cycles apart on gfx950); four or more
-  // waves per SIMD hide that and the kernel is issue-bound, so one chain
-  // suffices.  With fewer reads two chains per lane supply independent work
-  // (measured: 1,024 reads x 10 M columns run 12% faster with 2 than with 1;
-  // 4 chains lose to the 256 tile-switch steps they need per period).
   const int64_t simds = (int64_t)p->cus * 4;
-  p->chains = p->nq >= 4 * simds ? 1 : 2;
-  // resident waves per CU: limited by LDS (the CU holds 160 KiB) and capped
-  // at 16 (four per SIMD)
-  const size_t per = skew_lds_bytes(p->dtype, p->strip, p->chains,
-                                    std::max(p->max_m, skew_min_m(p->chains)));
-  int w = (int)std::min<size_t>(16, (160 * 1024) / std::max<size_t>(per, 1));
-  p->waves_per_cu = std::max(w, 1);
+  const int32_t median_m = p->sorted_m[(size_t)p->nq / 2];
+  if (p->nq >= 4 * simds) {
+    p->chains = 1;
+    p->bands = 1;
+  } else if (median_m >= 4 * skew_min_m(1)) {
+    p->chains = 1;
+    p->bands = 4;
+  } else if (median_m >= 2 * skew_min_m(1)) {
+    p->chains = 1;
+    p->bands = 2;
+  } else {
+    p->chains = 2;
+    p->bands = 1;
+  }
+  p->waves_per_cu = skew_waves_per_cu(p->strip, p->chains, p->bands,
+                                      std::max(skew_band_rows(p->max_m, p->chains, p->bands),
+                                               skew_min_m(p->chains)),
+                                      false);
 }
 
 int sdtw_plan_create(const int64_t* offsets_host, int32_t nq, int dtype, sdtw_plan* out) {
@@ -417,29 +444,43 @@ int sdtw_plan_info(sdtw_plan plan, int32_t* nq, int* dtype, int32_t* max_m) {
   return SDTW_OK;
 }
 
-int sdtw_plan_set_config(sdtw_plan plan, int strip, int chains, int waves_per_cu) {
+int sdtw_plan_set_config(sdtw_plan plan, int strip, int chains, int bands, int waves_per_cu) {
   SDTW_REQUIRE(plan, "sdtw_plan_set_config: null plan");
   SDTW_REQUIRE(strip == 0 || valid_strip(strip), "sdtw_plan_set_config: strip %d not in {8,16,32}",
                strip);
   SDTW_REQUIRE(chains == 0 || chains == 1 || chains == 2 || chains == 4,
                "sdtw_plan_set_config: chains %d not in {1,2,4}", chains);
+  SDTW_REQUIRE(bands == 0 || bands == 1 || bands == 2 || bands == 4,
+               "sdtw_plan_set_config: bands %d not in {1,2,4}", bands);
   SDTW_REQUIRE(waves_per_cu >= 0 && waves_per_cu <= 32,
                "sdtw_plan_set_config: waves_per_cu %d outside [0, 32]", waves_per_cu);
   const int s2 = strip ? strip : plan->strip;
   const int k2 = chains ? chains : plan->chains;
+  const int w2 = waves_per_cu ? waves_per_cu : plan->waves_per_cu;
   SDTW_REQUIRE(valid_strip_chains(s2, k2),
                "sdtw_plan_set_config: strip %d with %d chains (strip/chains must be a multiple "
                "of 4)", s2, k2);
+  int b2 = bands;
+  if (b2 == 0) {  // keep the plan's bands where they fit the rest, else one wave per read
+    b2 = plan->bands;
+    if (!valid_skew_config(s2, k2, b2) || w2 % b2 != 0) b2 = 1;
+  }
+  SDTW_REQUIRE(valid_skew_config(s2, k2, b2),
+               "sdtw_plan_set_config: %d bands need strip 16 and at most 2 chains", b2);
+  SDTW_REQUIRE(w2 % b2 == 0, "sdtw_plan_set_config: waves_per_cu %d is not a multiple of %d bands",
+               w2, b2);
   plan->strip = s2;
   plan->chains = k2;
-  if (waves_per_cu) plan->waves_per_cu = waves_per_cu;
+  plan->bands = b2;
+  plan->waves_per_cu = w2;
   return SDTW_OK;
 }
 
-int sdtw_plan_get_config(sdtw_plan plan, int* strip, int* chains, int* waves_per_cu) {
+int sdtw_plan_get_config(sdtw_plan plan, int* strip, int* chains, int* bands, int* waves_per_cu) {
   SDTW_REQUIRE(plan, "sdtw_plan_get_config: null plan");
   if (strip) *strip = plan->strip;
   if (chains) *chains = plan->chains;
+  if (bands) *bands = plan->bands;
   if (waves_per_cu) *waves_per_cu = plan->waves_per_cu;
   return SDTW_OK;
 }
@@ -469,7 +510,7 @@ int sdtw_align_batch(sdtw_ref ref, sdtw_plan plan, const void* q_dev, void* cost
   const std::vector<LaunchGroup> groups = launch_groups(plan);
   const size_t lds_max = (size_t)max_lds_bytes();
   for (const LaunchGroup& g : groups) {
-    const size_t lds = g.chains ? skew_lds_bytes(plan->dtype, plan->strip, g.chains, g.max_m)
+    const size_t lds = g.chains ? skew_lds_bytes(plan->strip, g.chains, g.bands, g.max_band, false)
                                 : plain_lds_bytes(plan->dtype, plan->strip, g.max_m);
     SDTW_REQUIRE(lds <= lds_max, "sdtw_align_batch: %zu bytes of LDS needed, %zu available", lds,
                  lds_max);
@@ -487,10 +528,12 @@ int sdtw_align_batch(sdtw_ref ref, sdtw_plan plan, const void* q_dev, void* cost
     a.order = plan->order_dev + g.first;
     a.nwork = g.count;
     a.max_m = g.max_m;
+    a.max_band = g.max_band;
     int rc;
     if (g.chains) {
-      const int blocks = (int)std::min<int64_t>((int64_t)plan->cus * plan->waves_per_cu, g.count);
-      rc = check_hip(launch_align_skew(plan->dtype, plan->strip, g.chains, blocks, a, st),
+      const int groups_per_cu = std::max(plan->waves_per_cu / g.bands, 1);
+      const int blocks = (int)std::min<int64_t>((int64_t)plan->cus * groups_per_cu, g.count);
+      rc = check_hip(launch_align_skew(plan->dtype, plan->strip, g.chains, g.bands, blocks, a, st),
                      "sdtw_align_batch: launch");
     } else {
       rc = check_hip(launch_align_plain(plan->dtype, plan->strip, a, st),
@@ -631,6 +674,13 @@ int sdtw_stream_copy_row(sdtw_stream s, void* dst_dev, void* stream) {
                    "sdtw_stream_copy_row");
 }
 
+int sdtw_stream_set_bands(int bands) {
+  SDTW_REQUIRE(bands == 0 || bands == 1 || bands == 2 || bands == 4,
+               "sdtw_stream_set_bands: bands %d not in {0,1,2,4}", bands);
+  g_stream_bands.store(bands);
+  return SDTW_OK;
+}
+
 int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk_dev,
                        const int64_t* chunk_offsets_host, void* cost_dev, int32_t* end_dev,
                        void* stream) {
@@ -662,11 +712,19 @@ int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk
   std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
     return len(a) != len(b) ? len(a) > len(b) : a < b;
   });
+  // One chain per lane; row bands (four waves per chunk) when the chunks are
+  // too few to give every SIMD two waves and long enough to be cut.
   constexpr int kStrip = 16, kChains = 1;
-  int32_t nbig = 0;
-  while (nbig < ns && len(order[(size_t)nbig]) >= skew_min_m(kChains)) ++nbig;
+  const int cus = std::max(cu_count(), 1);
+  int bands = g_stream_bands.load();
+  if (bands == 0) bands = (ns < 2 * 4 * cus && max_m >= 2 * skew_min_m(kChains)) ? 4 : 1;
+  int32_t nbig = 0, max_band = 0;
+  while (nbig < ns && len(order[(size_t)nbig]) >= skew_min_m(kChains)) {
+    max_band = std::max(max_band, skew_band_rows((int32_t)len(order[(size_t)nbig]), kChains, bands));
+    ++nbig;
+  }
   const size_t lds_max = (size_t)max_lds_bytes();
-  SDTW_REQUIRE(skew_lds_bytes(dtype, kStrip, kChains, max_m, true) <= lds_max &&
+  SDTW_REQUIRE(skew_lds_bytes(kStrip, kChains, bands, max_band, true) <= lds_max &&
                    plain_lds_bytes(dtype, kStrip, max_m) <= lds_max,
                "sdtw_stream_extend: chunk of %d rows needs more LDS than available", max_m);
 
@@ -708,11 +766,10 @@ int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk
     a.items = sl.dev;
     a.nwork = nbig;
     a.max_m = (int32_t)len(order[0]);
-    const int cus = std::max(cu_count(), 1);
-    const size_t per = skew_lds_bytes(dtype, kStrip, kChains, a.max_m, true);
-    const int wpc = (int)std::max<size_t>(1, std::min<size_t>(16, (160 * 1024) / per));
-    const int blocks = (int)std::min<int64_t>((int64_t)cus * wpc, nbig);
-    rc = check_hip(launch_align_skew(dtype, kStrip, kChains, blocks, a, st, true),
+    a.max_band = max_band;
+    const int wpc = skew_waves_per_cu(kStrip, kChains, bands, max_band, true);
+    const int blocks = (int)std::min<int64_t>((int64_t)cus * (wpc / bands), nbig);
+    rc = check_hip(launch_align_skew(dtype, kStrip, kChains, bands, blocks, a, st, true),
                    "sdtw_stream_extend: launch");
   }
   if (!rc && nbig < ns) {

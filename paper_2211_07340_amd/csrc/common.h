@@ -20,9 +20,9 @@ constexpr int64_t kPadUnit = int64_t(kLanes) * kMaxStrip;
 // Offset that maps int16 onto [0, 65535]; |x - y| is translation invariant.
 constexpr uint32_t kI16Bias = 32768u;
 
-// Shortest read the continuous-skew kernel takes with K chains per lane: its
-// one-step-ahead LDS prefetch needs the last sub-lane's boundary write two
-// steps before lane 0's read, i.e. M >= 64K + 1.
+// Shortest read (or row band) the continuous-skew kernel takes with K chains
+// per lane: its one-step-ahead LDS prefetch needs the last sub-lane's boundary
+// write two steps before lane 0's read, i.e. M >= 64K + 1.
 inline int32_t skew_min_m(int chains) { return 64 * chains + 1; }
 
 // Strip widths and chains-per-lane the skew kernel is built for: W in
@@ -31,6 +31,37 @@ inline bool valid_strip_chains(int strip, int chains) {
   if (strip != 8 && strip != 16 && strip != 32) return false;
   if (chains != 1 && chains != 2 && chains != 4) return false;
   return (strip / chains) % 4 == 0;
+}
+
+// Row bands per workgroup (waves per read): 1 for every (strip, chains)
+// above; 2 or 4 with strip 16 and 1 or 2 chains.
+inline bool valid_skew_config(int strip, int chains, int bands) {
+  if (!valid_strip_chains(strip, chains)) return false;
+  if (bands == 1) return true;
+  return (bands == 2 || bands == 4) && strip == 16 && chains <= 2;
+}
+
+// Bands a read of M rows is cut into: as many as allowed, each >= 64K + 1 rows.
+inline int32_t skew_read_bands(int32_t m, int chains, int bands) {
+  int32_t pe = m / skew_min_m(chains);
+  return pe < 1 ? 1 : (pe > bands ? bands : pe);
+}
+// Rows of the tallest band of a read of M rows.
+inline int32_t skew_band_rows(int32_t m, int chains, int bands) {
+  const int32_t pe = skew_read_bands(m, chains, bands);
+  return (m + pe - 1) / pe;
+}
+
+// LDS words of the skew kernel: shared part (zeros and a +inf cell; resident
+// row strips when streaming; the band-to-band rings) and, per band, the tile
+// stage and the query/boundary entries of up to band_rows rows.
+__host__ __device__ constexpr int skew_band_words(int strip, int chains, int band_rows) {
+  return (64 * strip + 2 * (band_rows + 64 * chains) + 3) & ~3;
+}
+inline size_t skew_lds_bytes(int strip, int chains, int bands, int band_rows, bool stream) {
+  const size_t shared = (size_t)strip + 4 + (stream ? (size_t)64 * strip + 64 : 0) +
+                        (size_t)(bands - 1) * (2 * 64 * (size_t)strip + 4);
+  return 4 * (shared + (size_t)bands * (size_t)skew_band_words(strip, chains, band_rows));
 }
 
 inline int64_t padded_length(int64_t n) {
@@ -68,21 +99,23 @@ struct AlignArgs {
   const int32_t* order;  // work list: read indices
   int32_t nwork;         // entries in the work list
   int32_t max_m;         // longest read in the work list (LDS sizing)
+  int32_t max_band;      // skew kernel: rows of the tallest band of any item (LDS sizing)
   int32_t* counter;      // persistent work counter (device, reset by launcher)
   void* cost;            // int32[nq] or float[nq]
   int32_t* end;          // int32[nq]
   int32_t single_m;      // used when offs == nullptr: one read of this length
   const StreamItem* items;  // streaming launches: work item descriptors
 };
-// Continuous-skew persistent kernel with `chains` chains per lane; every read
-// in the list must have M >= skew_min_m(chains).  `stream`: work items come
-// from a.items and extend resident rows.
-hipError_t launch_align_skew(int dtype, int strip, int chains, int blocks, const AlignArgs& a,
-                             hipStream_t st, bool stream = false);
+// Continuous-skew persistent kernel: `bands` waves per workgroup (one read per
+// workgroup, cut into row bands), `chains` chains per lane; every read in the
+// list must have M >= skew_min_m(chains) and a.max_band must bound
+// skew_band_rows() of every read.  `stream`: work items come from a.items and
+// extend resident rows.  `blocks` workgroups pull items until none is left.
+hipError_t launch_align_skew(int dtype, int strip, int chains, int bands, int blocks,
+                             const AlignArgs& a, hipStream_t st, bool stream = false);
 // Synchronised-tile single-wave kernel; any M >= 1; one block per work item.
 hipError_t launch_align_plain(int dtype, int strip, const AlignArgs& a, hipStream_t st,
                               bool stream = false);
-size_t skew_lds_bytes(int dtype, int strip, int chains, int max_m, bool stream = false);
 size_t plain_lds_bytes(int dtype, int strip, int max_m);
 int max_lds_bytes();
 

@@ -66,7 +66,7 @@ def test_argument_validation(lib):
     assert lib.sdtw_prepare_reference(p, 3, p, 6, 64.0, p, p, p, None) == 1  # L < k
     assert lib.sdtw_prepare_reference(p, 100, p, 6, -1.0, p, p, p, None) == 1
     assert lib.sdtw_prepare_queries(p, p, 0, 64.0, p, p, p, None) == 1
-    assert lib.sdtw_plan_set_config(None, 16, 2, 4) == 1
+    assert lib.sdtw_plan_set_config(None, 16, 2, 1, 4) == 1
     assert lib.sdtw_free_reference(None) == 1
     assert lib.sdtw_plan_destroy(None) == 1
     assert "null" in _err(lib)

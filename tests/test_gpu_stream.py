@@ -105,10 +105,37 @@ PLANS = [[400, 400, 400], [70, 30, 300], [1, 64, 65, 200], [250], [65, 65, 65, 6
 
 
 @pytest.mark.parametrize("dt", ["i16", "f32"])
-def test_extend_equals_from_scratch(dev, prepared, dt):
+@pytest.mark.parametrize("bands", [0, 1, 2, 4])
+def test_extend_equals_from_scratch(dev, prepared, dt, bands):
     w, z, codes = prepared
     reads = chunked_reads(w, PLANS)
-    run_rounds(dev, codes if dt == "i16" else z, reads, sd.I16 if dt == "i16" else sd.F32)
+    sd.set_stream_bands(bands)
+    try:
+        run_rounds(dev, codes if dt == "i16" else z, reads, sd.I16 if dt == "i16" else sd.F32)
+    finally:
+        sd.set_stream_bands(0)
+
+
+@pytest.mark.parametrize("bands", [1, 4])
+def test_extend_diagonal_at_chunk_and_band_boundaries(dev, bands):
+    # a read that is an exact substring of the reference, cut into chunks so
+    # that its zero-cost diagonal crosses the first chunk boundary exactly at
+    # a tile boundary (column 2T) and, with four bands, the boundary between
+    # bands 0 and 1 of the third chunk (2016 rows, bands of 504) at column 3T
+    T = 64 * 16
+    rng = np.random.default_rng(17 + bands)
+    ref = rng.permutation(np.arange(-30000, 30000, 9))[:6 * T].astype(np.int16)
+    s = 2 * T - 300
+    x = ref[s:s + 300 + 520 + 2016].copy()
+    assert s + 300 + 520 + 504 == 3 * T
+    reads = [(None, None, x, np.array([0, 300, 300 + 520, x.size]))]
+    sd.set_stream_bands(bands)
+    try:
+        got = run_rounds(dev, ref, reads, sd.I16)
+    finally:
+        sd.set_stream_bands(0)
+    assert [(e, c) for (_, _, e, c) in got] == [(s + 299, 0.0), (s + 819, 0.0),
+                                                (s + x.size - 1, 0.0)]
 
 
 def test_extend_ragged_reference(dev):
