@@ -12,8 +12,13 @@ SARS-CoV-2 workload's shape), int16 inputs with 32-bit accumulation.
 
 `value` is GCUPS (cells = sum over reads of M x N, per second of step time).
 The roofline object reports the alignment kernel's cell rate, timed with HIP
-events on the launch stream, against the VALU roof: 256 CUs x 64 lanes x
-2.4 GHz / (VALU instructions per cell: 2 for int16, 3 for float32).
+events on the launch stream, against the VALU roof of the chip: 256 CUs x 4
+SIMDs x 2.4 GHz, where a SIMD spends 4 cycles on a full-rate 32-bit VALU
+instruction of a 64-lane wave (min, max, min3, sad; 16 lanes per cycle) and 2
+cycles on a float32 add/sub (the published 157.3 TFLOP/s float32 vector peak
+is twice the full rate).  A cell costs v_min3_u32 + v_sad_u32 = 8 SIMD cycles
+per 64 cells on the int16 path and v_sub_f32 + v_min3_u32 + v_add_f32 = 2 + 4
++ 2 = 8 on the float32 path: 19.66 TCUPS for both.
 """
 from __future__ import annotations
 
@@ -28,12 +33,13 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-CUS, LANES, CLOCK_GHZ = 256, 64, 2.4
-INSTR_PER_CELL = {"i16": 2, "f32": 3}
+CUS, SIMDS_PER_CU, CLOCK_GHZ = 256, 4, 2.4
+# SIMD cycles per 64 cells (one wave-wide row of a strip column)
+SIMD_CYCLES_PER_64_CELLS = {"i16": 4 + 4, "f32": 2 + 4 + 2}
 
 
 def valu_peak_tcups(dtype: str) -> float:
-    return CUS * LANES * CLOCK_GHZ * 1e9 / INSTR_PER_CELL[dtype] / 1e12
+    return CUS * SIMDS_PER_CU * CLOCK_GHZ * 1e9 * 64 / SIMD_CYCLES_PER_64_CELLS[dtype] / 1e12
 
 
 def parse():
@@ -117,7 +123,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
-    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    kern_ms = float(np.median([a.elapsed_time(b) for a, b in evs]))
     gcups = cells / (ms_step * 1e-3) / 1e9
     kern_tcups = cells / (kern_ms * 1e-3) / 1e12
     peak = valu_peak_tcups(args.dtype)

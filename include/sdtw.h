@@ -193,11 +193,12 @@ int sdtw_plan_info(sdtw_plan plan, int32_t* nq, int* dtype, int32_t* max_m);
  *           with M >= 64 * chains + 1 use that many; shorter reads fall back
  *           to fewer chains, and reads with M <= 64 to the one-wave kernel.
  *   bands   waves per read: 1, 2 or 4 (0 = keep the plan's where they fit the
- *           other settings, else 1); more than 1 needs strip 16
- *           and at most 2 chains.  A read's rows are cut into up to `bands`
- *           row bands of at least 64 * chains + 1 rows each (Eq. 1: a row
- *           depends on the rows above only through the previous row), one
- *           wave per band, pipelined over the reference tiles.
+ *           other settings, else 1); more than 1 needs strip 16 with at most
+ *           2 chains or strip 32 with 1 chain.  A read's rows are cut into
+ *           up to `bands` row bands of at least 64 * chains + 1 rows each
+ *           (Eq. 1: a row depends on the rows above only through the
+ *           previous row), one wave per band, pipelined over the
+ *           reference tiles.
  *   waves_per_cu  resident waves per compute unit for the persistent grid,
  *           1..32 (0 = keep); a multiple of bands.
  * EINVAL for values outside these sets.
@@ -295,8 +296,9 @@ int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk
 /*
  * Waves per chunk for later sdtw_stream_extend calls in this process (the
  * row bands of sdtw_plan_set_config): 1, 2 or 4, or 0 (the default) for
- * automatic: 4 when a call has fewer than 8 chunks per compute unit and its
- * longest chunk has at least 130 rows, else 1.  Results never depend on it.
+ * automatic: 4 for at most one chunk per compute unit, 2 for fewer than
+ * four, else 1 (a chunk of M rows uses at most M / 65 bands).  Results never
+ * depend on it.
  * EINVAL for other values.
  */
 int sdtw_stream_set_bands(int bands);

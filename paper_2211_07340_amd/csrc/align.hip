@@ -38,6 +38,7 @@
 // 65 rows and as the one-read-per-launch baseline.
 #include <limits.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "common.h"
@@ -241,8 +242,8 @@ __device__ __forceinline__ void load_strip(uint32_t (&dst)[W], const uint32_t* _
 // of band 0 enters a tile its previous row is acc's strip (instead of zeros)
 // and its diagonal is acc one column to the left (+inf left of column 0);
 // the last band writes the finished last row of every tile back to acc.  A
-// tile's acc is staged one period before that tile's write-back, so reads
-// see the row as it was before this extension.
+// tile's acc is read at least one period before that tile's write-back, so
+// reads see the row as it was before this extension.
 //
 // LDS (uint32 words, every array on 16 bytes): zeros[W] and a +inf cell
 // (4 words); STREAM: acc strips [64W] and the value left of each [64];
@@ -331,23 +332,29 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
     const int32_t r0 = (wave * M) / Pe;
     const int32_t Mb = ((wave + 1) * M) / Pe - r0;  // this band's rows
     const typename F::qin* __restrict__ qv = (const typename F::qin*)args.q + q0 + r0;
-    // resident row of tile t into this lane's LDS strip (and the value left
-    // of the strip); a fresh read (m_old == 0) stages gamma(0, .) = 0
-    auto stage_acc = [&](int32_t t) {
+    // Tiles are loaded from global memory one period before they are staged
+    // in LDS (registers ynext / accnext), so the loads' latency is hidden.
+    // Resident row of tile t (and the value left of the lane's strip); a
+    // fresh read (m_old == 0) has gamma(0, .) = 0.
+    uint32_t ynext[W], accnext[STREAM ? W : 1], accleftnext = F::kInf;
+    auto load_acc = [&](int32_t t) {
       if constexpr (STREAM) {
         const int64_t c0 = (int64_t)t * T + lane * W;
-        uint32_t v[W];
-        uint32_t left = F::kInf;
+        accleftnext = F::kInf;
         if (m_old > 0) {
-          load_strip<W>(v, acc + c0);
-          if (c0 > 0) left = acc[c0 - 1];
+          load_strip<W>(accnext, acc + c0);
+          if (c0 > 0) accleftnext = acc[c0 - 1];
         } else {
 #pragma unroll
-          for (int w = 0; w < W; ++w) v[w] = 0u;
+          for (int w = 0; w < W; ++w) accnext[w] = 0u;
         }
+      }
+    };
+    auto store_acc = [&]() {
+      if constexpr (STREAM) {
 #pragma unroll
-        for (int w = 0; w < W; ++w) my_acc[w] = v[w];
-        accleft[lane] = left;
+        for (int w = 0; w < W; ++w) my_acc[w] = accnext[w];
+        accleft[lane] = accleftnext;
       }
     };
 
@@ -357,11 +364,15 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
         s = s < 0 ? s + Mb : (s >= Mb ? s - Mb : s);
         bx[k] = make_uint2((uint32_t)F::to_lds(qv[s]), F::kInf);  // gamma(i, 0) = +inf
       }
-      uint32_t t0[W];
-      load_strip<W>(t0, args.ref + lane * W);
+      load_strip<W>(ynext, args.ref + lane * W);
 #pragma unroll
-      for (int w = 0; w < W; ++w) my_stage[w] = t0[w];
-      if (wave == 0) stage_acc(0);
+      for (int w = 0; w < W; ++w) my_stage[w] = ynext[w];
+      if (ntiles > 1) load_strip<W>(ynext, args.ref + T + lane * W);
+      if (wave == 0) {
+        load_acc(0);
+        store_acc();
+        if (ntiles > 1) load_acc(1);
+      }
     }
     __syncthreads();
 
@@ -408,21 +419,33 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
       xs[0] = e0.x;
       load_entries(r + 1);
       uint32_t left[K];
-      left[0] = asm_from_left_lane(up[W - 1], e0.y);
+      if constexpr (K == 1)
+        left[0] = from_left_lane(up[W - 1], e0.y);
+      else
+        left[0] = asm_from_left_lane(up[W - 1], e0.y);
 #pragma unroll
       for (int h = 1; h < K; ++h) left[h] = up[h * H - 1];
       if constexpr (CH >= 0) {
         if (lane == r / K) {
-          const uint32_t old_last = up[W - 1];
+          [[maybe_unused]] const uint32_t old_last = up[W - 1];
+          // new reference strip, then the finished row out (the last band's
+          // fin is the stage itself), then the new previous row: ordered so
+          // that the loads can land in the registers they replace
 #pragma unroll
           for (int w = CH * H; w < (CH + 1) * H; w += 4) {
             const uint4 nv = *(const uint4*)(my_stage + w);
-            *(uint4*)(fin + w) = make_uint4(up[w], up[w + 1], up[w + 2], up[w + 3]);
-            const uint4 zv = *(const uint4*)(upsrc + w);
             y[w] = nv.x;
             y[w + 1] = nv.y;
             y[w + 2] = nv.z;
             y[w + 3] = nv.w;
+          }
+#pragma unroll
+          for (int w = CH * H; w < (CH + 1) * H; w += 4)
+            *(uint4*)(fin + w) = make_uint4(up[w], up[w + 1], up[w + 2], up[w + 3]);
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int w = CH * H; w < (CH + 1) * H; w += 4) {
+            const uint4 zv = *(const uint4*)(upsrc + w);
             up[w] = zv.x;
             up[w + 1] = zv.y;
             up[w + 2] = zv.z;
@@ -434,7 +457,10 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
           }
         }
       }
-      chains_row<F, K, H, W>(xs, y, up, nw, dprev, left);
+      if constexpr (K == 1)
+        strip_row<F, W>(xs[0], y, up, nw, dprev[0], left[0]);
+      else
+        chains_row<F, K, H, W>(xs, y, up, nw, dprev, left);
 #pragma unroll
       for (int h = 0; h < K; ++h) dprev[h] = left[h];
       if (write_b && lane == 63) bxl[wrap ? r + Mb : r].y = nw[W - 1];
@@ -486,11 +512,13 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
           }
         }
         if (p + 1 < ntiles) {
-          uint32_t t1[W];
-          load_strip<W>(t1, args.ref + (int64_t)(p + 1) * T + lane * W);
 #pragma unroll
-          for (int w = 0; w < W; ++w) my_stage[w] = t1[w];
-          if (wave == 0) stage_acc(p + 1);
+          for (int w = 0; w < W; ++w) my_stage[w] = ynext[w];
+          if (p + 2 < ntiles) load_strip<W>(ynext, args.ref + (int64_t)(p + 2) * T + lane * W);
+          if (wave == 0) {
+            store_acc();
+            if (p + 2 < ntiles) load_acc(p + 2);
+          }
         }
         if (p < ntiles) {
           // phase B: plain steps, four per iteration
@@ -654,7 +682,7 @@ __global__ void k_reset_counter(int32_t* c) {
 
 template <class F, int W, int K, int P, bool STREAM>
 hipError_t launch_skew_t(int blocks, const AlignArgs& a, hipStream_t st) {
-  const size_t lds = skew_lds_bytes(W, K, P, a.max_band, STREAM);
+  const size_t lds = std::max(skew_lds_bytes(W, K, P, a.max_band, STREAM), (size_t)a.lds_bytes);
   hipError_t e = hipFuncSetAttribute((const void*)k_align_skew<F, W, K, P, STREAM>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -700,6 +728,8 @@ hipError_t launch_skew_f(int strip, int chains, int bands, int blocks, const Ali
     case (16 * 8 + 1) * 8 + 4: return launch_skew_s<F, 16, 1, 4>(blocks, a, st, stream);
     case (16 * 8 + 2) * 8 + 2: return launch_skew_s<F, 16, 2, 2>(blocks, a, st, stream);
     case (16 * 8 + 2) * 8 + 4: return launch_skew_s<F, 16, 2, 4>(blocks, a, st, stream);
+    case (32 * 8 + 1) * 8 + 2: return launch_skew_s<F, 32, 1, 2>(blocks, a, st, stream);
+    case (32 * 8 + 1) * 8 + 4: return launch_skew_s<F, 32, 1, 4>(blocks, a, st, stream);
   }
   return hipErrorInvalidValue;
 }

@@ -354,13 +354,31 @@ static int skew_waves_per_cu(int strip, int chains, int bands, int max_band, boo
   return std::max(groups, 1) * bands;
 }
 
+// LDS to reserve per workgroup so that `blocks` workgroups spread evenly over
+// the compute units: when there are fewer than the CUs could hold, reserve a
+// 1/ceil(blocks/cus) share of a CU's 160 KiB (whole KiB) so that no CU takes
+// more than its share (the dispatcher would otherwise fill some CUs up to
+// their limit and leave others with less work).
+static int32_t spread_lds(size_t need, int blocks, int groups_per_cu, int cus) {
+  constexpr size_t kCuLds = 160 * 1024;
+  if ((int64_t)blocks >= (int64_t)groups_per_cu * cus) return 0;
+  const int share = (blocks + cus - 1) / cus;
+  // 1 KiB less than the share leaves room for the kernel's static LDS (a
+  // share-sized reservation would let only share - 1 workgroups in)
+  const size_t cap = (size_t)max_lds_bytes() - 1024;
+  const size_t want = (std::min(kCuLds / (size_t)share, cap + 1024) - 1024) & ~(size_t)1023;
+  return want > need ? (int32_t)want : 0;
+}
+
 // Default launch shape.  A wave issues about one VALU instruction per 10
 // cycles when its instructions depend on each other and no faster than one
 // per 5 cycles however independent they are (measured on gfx950), while a
 // SIMD issues one per about 4.3 cycles from two or more waves.  So every SIMD
 // needs two or more waves: with four or more reads per SIMD one wave per
-// read and one chain per lane; with fewer, each read is cut into row bands
-// (four waves per read) when its rows allow, else two chains per lane.
+// read and one chain per lane; with fewer, each read is cut into two row
+// bands when its rows allow (measured on 1,024 reads of 250-500 rows x 10 M
+// columns: 1.73x one band, 1.23x four bands, whose 64 tile-switch steps per
+// band of ~94 rows cost more than the extra waves bring), else two chains.
 static void choose_config(sdtw_plan_s* p) {
   p->strip = 16;
   const int64_t simds = (int64_t)p->cus * 4;
@@ -368,9 +386,6 @@ static void choose_config(sdtw_plan_s* p) {
   if (p->nq >= 4 * simds) {
     p->chains = 1;
     p->bands = 1;
-  } else if (median_m >= 4 * skew_min_m(1)) {
-    p->chains = 1;
-    p->bands = 4;
   } else if (median_m >= 2 * skew_min_m(1)) {
     p->chains = 1;
     p->bands = 2;
@@ -533,6 +548,8 @@ int sdtw_align_batch(sdtw_ref ref, sdtw_plan plan, const void* q_dev, void* cost
     if (g.chains) {
       const int groups_per_cu = std::max(plan->waves_per_cu / g.bands, 1);
       const int blocks = (int)std::min<int64_t>((int64_t)plan->cus * groups_per_cu, g.count);
+      a.lds_bytes = spread_lds(skew_lds_bytes(plan->strip, g.chains, g.bands, g.max_band, false),
+                               blocks, groups_per_cu, plan->cus);
       rc = check_hip(launch_align_skew(plan->dtype, plan->strip, g.chains, g.bands, blocks, a, st),
                      "sdtw_align_batch: launch");
     } else {
@@ -716,8 +733,11 @@ int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk
   // too few to give every SIMD two waves and long enough to be cut.
   constexpr int kStrip = 16, kChains = 1;
   const int cus = std::max(cu_count(), 1);
+  // Automatic: more waves per chunk the fewer chunks there are (a chunk's
+  // latency shrinks with its bands while the device is not full), one per
+  // chunk from four chunks per compute unit on.
   int bands = g_stream_bands.load();
-  if (bands == 0) bands = (ns < 2 * 4 * cus && max_m >= 2 * skew_min_m(kChains)) ? 4 : 1;
+  if (bands == 0) bands = ns <= cus ? 4 : (ns < 4 * cus ? 2 : 1);
   int32_t nbig = 0, max_band = 0;
   while (nbig < ns && len(order[(size_t)nbig]) >= skew_min_m(kChains)) {
     max_band = std::max(max_band, skew_band_rows((int32_t)len(order[(size_t)nbig]), kChains, bands));
@@ -769,6 +789,8 @@ int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk
     a.max_band = max_band;
     const int wpc = skew_waves_per_cu(kStrip, kChains, bands, max_band, true);
     const int blocks = (int)std::min<int64_t>((int64_t)cus * (wpc / bands), nbig);
+    a.lds_bytes = spread_lds(skew_lds_bytes(kStrip, kChains, bands, max_band, true), blocks,
+                             wpc / bands, cus);
     rc = check_hip(launch_align_skew(dtype, kStrip, kChains, bands, blocks, a, st, true),
                    "sdtw_stream_extend: launch");
   }

@@ -34,11 +34,12 @@ inline bool valid_strip_chains(int strip, int chains) {
 }
 
 // Row bands per workgroup (waves per read): 1 for every (strip, chains)
-// above; 2 or 4 with strip 16 and 1 or 2 chains.
+// above; 2 or 4 with strip 16 and 1 or 2 chains, or strip 32 and 1 chain.
 inline bool valid_skew_config(int strip, int chains, int bands) {
   if (!valid_strip_chains(strip, chains)) return false;
   if (bands == 1) return true;
-  return (bands == 2 || bands == 4) && strip == 16 && chains <= 2;
+  if (bands != 2 && bands != 4) return false;
+  return (strip == 16 && chains <= 2) || (strip == 32 && chains == 1);
 }
 
 // Bands a read of M rows is cut into: as many as allowed, each >= 64K + 1 rows.
@@ -100,6 +101,9 @@ struct AlignArgs {
   int32_t nwork;         // entries in the work list
   int32_t max_m;         // longest read in the work list (LDS sizing)
   int32_t max_band;      // skew kernel: rows of the tallest band of any item (LDS sizing)
+  int32_t lds_bytes;     // skew kernel: LDS to reserve per workgroup if more than it needs
+                         // (caps the workgroups a compute unit takes, spreading a short
+                         // work list over every compute unit)
   int32_t* counter;      // persistent work counter (device, reset by launcher)
   void* cost;            // int32[nq] or float[nq]
   int32_t* end;          // int32[nq]

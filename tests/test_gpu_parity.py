@@ -133,32 +133,34 @@ def _ragged_case(seed, Ms, N, lo=-3000, hi=3000):
     return ref, vals.astype(np.int16), offs
 
 
-@pytest.mark.parametrize("chains,bands,waves", [(1, 2, 2), (1, 2, 8), (1, 4, 4), (1, 4, 16),
-                                                 (2, 2, 4), (2, 4, 8)])
-def test_band_schedule_invariance(dev, chains, bands, waves):
+@pytest.mark.parametrize("strip,chains,bands,waves", [
+    (16, 1, 2, 2), (16, 1, 2, 8), (16, 1, 4, 4), (16, 1, 4, 16), (16, 2, 2, 4), (16, 2, 4, 8),
+    (32, 1, 2, 4), (32, 1, 4, 8)])
+def test_band_schedule_invariance(dev, strip, chains, bands, waves):
     # row bands (several waves per read): reads whose band count ranges from
     # 1 to 4, band heights at the minimum and ragged, several tiles and a
     # ragged tail, few and many workgroups per compute unit
     Ms = [65, 129, 130, 131, 200, 259, 260, 261, 263, 400, 517, 1000, 2049, 4096]
-    ref, q, offs = _ragged_case(bands * 10 + chains, Ms, 5000)
-    note(f"bands={bands} chains={chains} waves={waves} Ms={Ms}")
-    check_i16(gpu_batch(dev, ref, q, offs, sd.I16, 16, waves, chains, bands), q, offs, ref)
+    ref, q, offs = _ragged_case(bands * 10 + chains + strip, Ms, 5000)
+    note(f"strip={strip} bands={bands} chains={chains} waves={waves} Ms={Ms}")
+    check_i16(gpu_batch(dev, ref, q, offs, sd.I16, strip, waves, chains, bands), q, offs, ref)
     rng = np.random.default_rng(bands + chains)
     zref = rng.normal(size=3001).astype(np.float32)
     zq, zoffs = synth.csr([rng.normal(size=m).astype(np.float32) for m in Ms[:12]])
-    check_f32(gpu_batch(dev, zref, zq.astype(np.float32), zoffs, sd.F32, 16, waves, chains, bands),
-              zq.astype(np.float32), zoffs, zref)
+    check_f32(gpu_batch(dev, zref, zq.astype(np.float32), zoffs, sd.F32, strip, waves, chains,
+                        bands), zq.astype(np.float32), zoffs, zref)
 
 
-@pytest.mark.parametrize("chains,bands", [(1, 2), (1, 4), (2, 2), (2, 4)])
-def test_band_boundary_diagonal_on_exact_substrings(dev, chains, bands):
+@pytest.mark.parametrize("strip,chains,bands", [(16, 1, 2), (16, 1, 4), (16, 2, 2), (16, 2, 4),
+                                                (32, 1, 2), (32, 1, 4)])
+def test_band_boundary_diagonal_on_exact_substrings(dev, strip, chains, bands):
     # each read is an exact substring of the reference whose zero-cost
     # diagonal crosses from band g - 1 into band g exactly at a tile
     # boundary, so the diagonal handed over with the previous tile's last
     # column decides the result (cost 0, end s + M - 1)
-    T = 64 * 16
-    rng = np.random.default_rng(5 + bands + chains)
-    ref = rng.permutation(np.arange(-30000, 30000, 9))[:6 * T].astype(np.int16)
+    T = 64 * strip
+    rng = np.random.default_rng(5 + bands + chains + strip)
+    ref = rng.permutation(np.arange(-32000, 32000, 5))[:6 * T].astype(np.int16)
     S1 = 64 * chains + 1
     qs, want = [], []
     for M in (bands * S1, bands * S1 + 37, 4 * bands * S1 + 3):
@@ -170,7 +172,7 @@ def test_band_boundary_diagonal_on_exact_substrings(dev, chains, bands):
     q, offs = synth.csr(qs)
     q = q.astype(np.int16)
     note(f"diagonal bands={bands} chains={chains} reads={len(qs)}")
-    got = gpu_batch(dev, ref, q, offs, sd.I16, 16, 4 * bands, chains, bands)
+    got = gpu_batch(dev, ref, q, offs, sd.I16, strip, 4 * bands, chains, bands)
     assert list(zip(got[0].tolist(), got[1].tolist())) == want
     check_i16(got, q, offs, ref)
 
