@@ -207,6 +207,30 @@ int sdtw_plan_set_config(sdtw_plan plan, int strip, int chains, int bands, int w
 int sdtw_plan_get_config(sdtw_plan plan, int* strip, int* chains, int* bands,
                          int* waves_per_cu);
 
+/*
+ * Autotune the plan's kernel configuration on this batch: run every
+ * candidate (strip 16 or 32, 1 or 2 chains, 1, 2 or 4 bands where valid,
+ * each at the waves per CU its LDS allows and at half that) once to warm up
+ * and once timed with HIP events on `stream`, keep the fastest on the plan
+ * and remember it for sdtw_plan_use_tuned (keyed by device, dtype, reference
+ * length, number of reads, longest read and total rows).
+ *   max_columns  time the candidates on the first min(n, max_columns)
+ *                reference columns (0 = all); the ranking does not depend on
+ *                the reference length beyond the first few tiles.
+ * cost_dev / end_dev receive intermediate results (scratch).  Synchronises
+ * `stream`; allocates nothing on the device.  Results of later calls never
+ * depend on the configuration chosen.
+ */
+int sdtw_plan_autotune(sdtw_ref ref, sdtw_plan plan, const void* q_dev, void* cost_dev,
+                       int32_t* end_dev, int64_t max_columns, void* stream);
+
+/*
+ * Apply a configuration sdtw_plan_autotune found earlier in this process for
+ * a batch of the same shape against a reference of the same length; *found
+ * (optional) is set to 1 if there was one, else 0 and the plan is unchanged.
+ */
+int sdtw_plan_use_tuned(sdtw_ref ref, sdtw_plan plan, int* found);
+
 /* Release a plan (synchronise the streams that used it first). */
 int sdtw_plan_destroy(sdtw_plan plan);
 

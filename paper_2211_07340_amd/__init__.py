@@ -6,13 +6,11 @@ This module only marshals arguments: every step runs in the HIP library.
 Device memory and streams come from PyTorch (``torch.cuda``).
 """
 from .binding import (F32, I16, Plan, Reference, SdtwError, Stream, align_batch, align_one,
-                      library_path, load_library, prepare_queries, prepare_queries_ex,
-                      prepare_reference, row_budget_info, set_row_budget, set_stream_bands,
-                      stream_extend,
-                      version)
+                      autotune, library_path, load_library, prepare_queries,
+                      prepare_queries_ex, prepare_reference, row_budget_info, set_row_budget,
+                      set_stream_bands, stream_extend, use_tuned, version)
 
 __all__ = ["F32", "I16", "Plan", "Reference", "SdtwError", "Stream", "align_batch",
-           "align_one", "library_path", "load_library", "prepare_queries",
+           "align_one", "autotune", "library_path", "load_library", "prepare_queries",
            "prepare_queries_ex", "prepare_reference", "row_budget_info", "set_row_budget",
-           "set_stream_bands",
-           "stream_extend", "version"]
+           "set_stream_bands", "stream_extend", "use_tuned", "version"]

@@ -53,6 +53,8 @@ def load_library():
         "sdtw_plan_get_config": ([p, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                   C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
         "sdtw_plan_destroy": ([p], C.c_int),
+        "sdtw_plan_autotune": ([p, p, p, p, p, i64, p], C.c_int),
+        "sdtw_plan_use_tuned": ([p, p, C.POINTER(C.c_int)], C.c_int),
         "sdtw_align_batch": ([p, p, p, p, p, p], C.c_int),
         "sdtw_align_one": ([p, p, i32, p, p, p], C.c_int),
         "sdtw_prepare_queries_ex": ([p, p, i32, dbl, p, p, p, p, p, p], C.c_int),
@@ -280,6 +282,26 @@ def align_batch(ref: Reference, plan: Plan, q, cost=None, end=None, stream=None)
                                            _dev(cost), _dev(end, torch.int32, "end"),
                                            _stream(stream)))
     return cost, end
+
+
+def autotune(ref: Reference, plan: Plan, q, max_columns: int = 1 << 17, stream=None):
+    """sdtw_plan_autotune: time the candidate configurations on this batch
+    (first max_columns reference columns), keep the fastest on the plan;
+    returns plan.config.  Synchronises the stream."""
+    torch = _torch()
+    qdt = torch.int16 if plan.dtype == I16 else torch.float32
+    cost, end = _outputs(plan.nq, plan.dtype, q.device, None, None)
+    _check(load_library().sdtw_plan_autotune(ref.handle, plan.handle, _dev(q, qdt, "q"),
+                                             _dev(cost), _dev(end, torch.int32, "end"),
+                                             int(max_columns), _stream(stream)))
+    return plan.config
+
+
+def use_tuned(ref: Reference, plan: Plan) -> bool:
+    """sdtw_plan_use_tuned: apply an earlier autotune result for this shape."""
+    found = C.c_int()
+    _check(load_library().sdtw_plan_use_tuned(ref.handle, plan.handle, C.byref(found)))
+    return bool(found.value)
 
 
 def align_one(ref: Reference, q, cost=None, end=None, stream=None):

@@ -12,6 +12,7 @@
 #include <new>
 #include <numeric>
 #include <set>
+#include <tuple>
 #include <vector>
 
 #include "common.h"
@@ -515,12 +516,22 @@ int sdtw_plan_destroy(sdtw_plan plan) {
 // alignment
 // ---------------------------------------------------------------------------
 
+// Enqueue the batch's launches; `n` reference columns (the autotuner times a
+// prefix of the reference).
+static int align_batch_impl(sdtw_ref ref, sdtw_plan plan, const void* q_dev, void* cost_dev,
+                            int32_t* end_dev, hipStream_t st, int64_t n);
+
 int sdtw_align_batch(sdtw_ref ref, sdtw_plan plan, const void* q_dev, void* cost_dev,
                      int32_t* end_dev, void* stream) {
   SDTW_REQUIRE(ref && plan, "sdtw_align_batch: null reference or plan");
   SDTW_REQUIRE(q_dev && cost_dev && end_dev, "sdtw_align_batch: null device pointer");
   SDTW_REQUIRE(ref->dtype == plan->dtype, "sdtw_align_batch: reference dtype %d != plan dtype %d",
                ref->dtype, plan->dtype);
+  return align_batch_impl(ref, plan, q_dev, cost_dev, end_dev, (hipStream_t)stream, ref->n);
+}
+
+static int align_batch_impl(sdtw_ref ref, sdtw_plan plan, const void* q_dev, void* cost_dev,
+                            int32_t* end_dev, hipStream_t st, int64_t n) {
   SDTW_REQUIRE(valid_strip(plan->strip), "sdtw_align_batch: bad strip");
   const std::vector<LaunchGroup> groups = launch_groups(plan);
   const size_t lds_max = (size_t)max_lds_bytes();
@@ -530,10 +541,9 @@ int sdtw_align_batch(sdtw_ref ref, sdtw_plan plan, const void* q_dev, void* cost
     SDTW_REQUIRE(lds <= lds_max, "sdtw_align_batch: %zu bytes of LDS needed, %zu available", lds,
                  lds_max);
   }
-  hipStream_t st = (hipStream_t)stream;
   AlignArgs a{};
   a.ref = ref->data;
-  a.n = ref->n;
+  a.n = n;
   a.q = q_dev;
   a.offs = plan->offs_dev;
   a.counter = plan->counter_dev;
@@ -580,6 +590,112 @@ int sdtw_align_one(sdtw_ref ref, const void* q_dev, int32_t M, void* cost_dev, i
   a.end = end_dev;
   return check_hip(launch_align_plain(ref->dtype, 16, a, (hipStream_t)stream),
                    "sdtw_align_one: launch");
+}
+
+// ---------------------------------------------------------------------------
+// autotuning
+// ---------------------------------------------------------------------------
+
+namespace {
+struct TuneKey {
+  int device, dtype;
+  int64_t n;
+  int32_t nq, max_m;
+  int64_t sum_m;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(device, dtype, n, nq, max_m, sum_m) <
+           std::tie(o.device, o.dtype, o.n, o.nq, o.max_m, o.sum_m);
+  }
+};
+struct TuneVal {
+  int strip, chains, bands, waves_per_cu;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tuned;  // best configuration per batch shape and reference length
+
+TuneKey tune_key(const sdtw_plan_s* p, int64_t n) {
+  int64_t sum = 0;
+  for (int32_t m : p->sorted_m) sum += m;
+  return {p->device, p->dtype, n, p->nq, p->max_m, sum};
+}
+}  // namespace
+
+int sdtw_plan_autotune(sdtw_ref ref, sdtw_plan plan, const void* q_dev, void* cost_dev,
+                       int32_t* end_dev, int64_t max_columns, void* stream) {
+  SDTW_REQUIRE(ref && plan, "sdtw_plan_autotune: null reference or plan");
+  SDTW_REQUIRE(q_dev && cost_dev && end_dev, "sdtw_plan_autotune: null device pointer");
+  SDTW_REQUIRE(ref->dtype == plan->dtype,
+               "sdtw_plan_autotune: reference dtype %d != plan dtype %d", ref->dtype,
+               plan->dtype);
+  SDTW_REQUIRE(max_columns >= 0, "sdtw_plan_autotune: negative max_columns");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t n = max_columns ? std::min<int64_t>(ref->n, max_columns) : ref->n;
+  // candidates: every strip / chains / bands the kernel is built for with
+  // strip >= 16 and at most 2 chains, each at the resident waves per CU its
+  // LDS allows and at half that
+  std::vector<TuneVal> cand;
+  for (int strip : {16, 32})
+    for (int chains : {1, 2})
+      for (int bands : {1, 2, 4}) {
+        if (!valid_skew_config(strip, chains, bands)) continue;
+        if (bands > 1 && plan->max_m < bands * skew_min_m(chains)) continue;
+        const int band_rows = std::max(skew_band_rows(plan->max_m, chains, bands),
+                                       skew_min_m(chains));
+        const int w = skew_waves_per_cu(strip, chains, bands, band_rows, false);
+        cand.push_back({strip, chains, bands, w});
+        if (w / 2 >= bands && (w / 2) % bands == 0) cand.push_back({strip, chains, bands, w / 2});
+      }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return set_error(SDTW_EDEVICE, "sdtw_plan_autotune: event creation failed");
+  }
+  const TuneVal keep = {plan->strip, plan->chains, plan->bands, plan->waves_per_cu};
+  TuneVal best = keep;
+  float best_ms = 0.f;
+  int rc = SDTW_OK;
+  for (const TuneVal& c : cand) {
+    plan->strip = c.strip;
+    plan->chains = c.chains;
+    plan->bands = c.bands;
+    plan->waves_per_cu = c.waves_per_cu;
+    rc = align_batch_impl(ref, plan, q_dev, cost_dev, end_dev, st, n);  // warm-up
+    if (!rc) rc = check_hip(hipEventRecord(e0, st), "sdtw_plan_autotune: record");
+    if (!rc) rc = align_batch_impl(ref, plan, q_dev, cost_dev, end_dev, st, n);
+    if (!rc) rc = check_hip(hipEventRecord(e1, st), "sdtw_plan_autotune: record");
+    if (!rc) rc = check_hip(hipEventSynchronize(e1), "sdtw_plan_autotune: wait");
+    float ms = 0.f;
+    if (!rc) rc = check_hip(hipEventElapsedTime(&ms, e0, e1), "sdtw_plan_autotune: time");
+    if (rc) break;
+    if (best_ms == 0.f || ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  plan->strip = best.strip;
+  plan->chains = best.chains;
+  plan->bands = best.bands;
+  plan->waves_per_cu = best.waves_per_cu;
+  if (rc) return rc;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tuned[tune_key(plan, ref->n)] = best;
+  return SDTW_OK;
+}
+
+int sdtw_plan_use_tuned(sdtw_ref ref, sdtw_plan plan, int* found) {
+  SDTW_REQUIRE(ref && plan, "sdtw_plan_use_tuned: null reference or plan");
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  auto it = g_tuned.find(tune_key(plan, ref->n));
+  if (found) *found = it != g_tuned.end();
+  if (it != g_tuned.end()) {
+    plan->strip = it->second.strip;
+    plan->chains = it->second.chains;
+    plan->bands = it->second.bands;
+    plan->waves_per_cu = it->second.waves_per_cu;
+  }
+  return SDTW_OK;
 }
 
 // ---------------------------------------------------------------------------

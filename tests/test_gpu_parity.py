@@ -318,3 +318,25 @@ def test_prepare_reference_matches_oracle(dev):
     sig = oracle.kmer_signal(w.genome, w.table, 6)
     assert np.allclose(gz, (sig - sig.astype(np.float64).mean()) / sig.astype(np.float64).std(),
                        atol=1e-5)
+
+
+def test_autotune_keeps_results_and_is_remembered(dev, small_ref):
+    w, z, codes, qz, qc = small_ref
+    offs = w.reads.offsets
+    ref = sd.Reference(torch.from_numpy(codes).to(dev))
+    plan = sd.Plan(offs, sd.I16)
+    q = torch.from_numpy(qc).to(dev)
+    note("autotune 64 x M=250 int16")
+    cfg = sd.autotune(ref, plan, q, max_columns=4096)
+    assert cfg["strip"] in (16, 32) and cfg["chains"] in (1, 2) and cfg["bands"] in (1, 2, 4)
+    assert cfg["waves_per_cu"] % cfg["bands"] == 0
+    cost, end = sd.align_batch(ref, plan, q)
+    torch.cuda.synchronize()
+    check_i16((cost.cpu().numpy(), end.cpu().numpy()), qc, offs, codes)
+    again = sd.Plan(offs, sd.I16)
+    assert sd.use_tuned(ref, again) and again.config == cfg
+    other = sd.Plan(offs[:9], sd.I16)
+    assert not sd.use_tuned(ref, other)
+    for pl in (plan, again, other):
+        pl.close()
+    ref.close()
