@@ -32,6 +32,12 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# The serving leg runs several HIP streams per target; HIP maps streams onto
+# this many hardware queues round-robin (4 by default), and two streams on one
+# queue run in order, so a short-reference batch could wait behind a
+# long-reference one.  Eight queues give every stream its own.  Read at HIP
+# initialisation, so set before torch touches the device.
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
 
 CUS, SIMDS_PER_CU, CLOCK_GHZ = 256, 4, 2.4
 # SIMD cycles per 64 cells (one wave-wide row of a strip column)
@@ -242,7 +248,8 @@ def serving(torch, dev, seconds: float, warmup: float, channels: int, recompute_
     """Streaming Read Until: incremental extension, then recompute from scratch."""
     from paper_2211_07340_amd import server as srv
     targets = serving_targets(torch, dev, large=large)
-    cfg = srv.ServerConfig(channels=channels)
+    cfg = srv.ServerConfig(channels=channels, row_budget_bytes=64 << 30,
+                           stream_strip=int(os.environ.get("SDTW_SERVE_STRIP", "0")))
     inc = srv.ReadUntilServer(targets, cfg, mode="extend")
     inc.calibrate()
     out = {"workload": f"{channels} channels, 400-event chunks every 0.1 s, reads to "

@@ -318,14 +318,15 @@ int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk
                        void* stream);
 
 /*
- * Waves per chunk for later sdtw_stream_extend calls in this process (the
- * row bands of sdtw_plan_set_config): 1, 2 or 4, or 0 (the default) for
- * automatic: 4 for at most one chunk per compute unit, 2 for fewer than
- * four, else 1 (a chunk of M rows uses at most M / 65 bands).  Results never
- * depend on it.
- * EINVAL for other values.
+ * Launch shape of later sdtw_stream_extend calls in this process (one chain
+ * per lane):
+ *   strip  columns per lane, 16 or 32; 0 (default) = 16.
+ *   bands  waves per chunk (the row bands of sdtw_plan_set_config), 1, 2 or
+ *          4; 0 (default) = 4 for at most one chunk per compute unit, 2 for
+ *          fewer than four, else 1 (a chunk of M rows uses at most M / 65).
+ * Results never depend on it.  EINVAL for other values.
  */
-int sdtw_stream_set_bands(int bands);
+int sdtw_stream_set_config(int strip, int bands);
 
 #ifdef __cplusplus
 }

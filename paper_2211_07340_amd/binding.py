@@ -58,7 +58,7 @@ def load_library():
         "sdtw_align_batch": ([p, p, p, p, p, p], C.c_int),
         "sdtw_align_one": ([p, p, i32, p, p, p], C.c_int),
         "sdtw_prepare_queries_ex": ([p, p, i32, dbl, p, p, p, p, p, p], C.c_int),
-        "sdtw_stream_set_bands": ([C.c_int], C.c_int),
+        "sdtw_stream_set_config": ([C.c_int, C.c_int], C.c_int),
         "sdtw_set_row_budget": ([i64], C.c_int),
         "sdtw_row_budget_info": ([C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)], C.c_int),
         "sdtw_stream_open": ([p, C.POINTER(p)], C.c_int),
@@ -323,9 +323,9 @@ def set_row_budget(nbytes: int):
     _check(load_library().sdtw_set_row_budget(int(nbytes)))
 
 
-def set_stream_bands(bands: int):
-    """Waves per chunk of later stream_extend calls: 1, 2, 4 or 0 (automatic)."""
-    _check(load_library().sdtw_stream_set_bands(int(bands)))
+def set_stream_config(strip: int = 0, bands: int = 0):
+    """Launch shape of later stream_extend calls (0 = automatic)."""
+    _check(load_library().sdtw_stream_set_config(int(strip), int(bands)))
 
 
 def row_budget_info():

@@ -152,14 +152,18 @@ struct DescSlot {
   int32_t cap = 0;
   std::shared_ptr<CallToken> last;
 };
-constexpr int kDescSlots = 8;
+// A call takes a slot whose previous call has completed, adding slots (up to
+// kMaxDescSlots) while every slot is still in use, so that a long call on
+// one HIP stream never holds back calls on other streams.
+constexpr int kMaxDescSlots = 64;
 struct DescRing {
   std::mutex mu;
-  DescSlot slot[kDescSlots];
-  int next = 0;
+  std::vector<std::unique_ptr<DescSlot>> slot;
+  int next = 0;  // round-robin victim when all kMaxDescSlots are busy
 };
 static DescRing g_ring[kMaxDevices];
-static std::atomic<int> g_stream_bands{0};  // sdtw_stream_set_bands (0: automatic)
+static std::atomic<int> g_stream_bands{0};  // sdtw_stream_set_config (0: automatic)
+static std::atomic<int> g_stream_strip{0};
 
 static int ensure_slot(DescSlot& sl, int32_t n) {
   if (sl.cap >= n) return SDTW_OK;
@@ -359,11 +363,13 @@ static int skew_waves_per_cu(int strip, int chains, int bands, int max_band, boo
 // the compute units: when there are fewer than the CUs could hold, reserve a
 // 1/ceil(blocks/cus) share of a CU's 160 KiB (whole KiB) so that no CU takes
 // more than its share (the dispatcher would otherwise fill some CUs up to
-// their limit and leave others with less work).
-static int32_t spread_lds(size_t need, int blocks, int groups_per_cu, int cus) {
+// their limit and leave others with less work).  `min_share` > 1 leaves room
+// for that many launches at once on every CU.
+static int32_t spread_lds(size_t need, int blocks, int groups_per_cu, int cus,
+                          int min_share = 1) {
   constexpr size_t kCuLds = 160 * 1024;
   if ((int64_t)blocks >= (int64_t)groups_per_cu * cus) return 0;
-  const int share = (blocks + cus - 1) / cus;
+  const int share = std::max((blocks + cus - 1) / cus, min_share);
   // 1 KiB less than the share leaves room for the kernel's static LDS (a
   // share-sized reservation would let only share - 1 workgroups in)
   const size_t cap = (size_t)max_lds_bytes() - 1024;
@@ -807,9 +813,12 @@ int sdtw_stream_copy_row(sdtw_stream s, void* dst_dev, void* stream) {
                    "sdtw_stream_copy_row");
 }
 
-int sdtw_stream_set_bands(int bands) {
+int sdtw_stream_set_config(int strip, int bands) {
+  SDTW_REQUIRE(strip == 0 || strip == 16 || strip == 32,
+               "sdtw_stream_set_config: strip %d not in {0,16,32}", strip);
   SDTW_REQUIRE(bands == 0 || bands == 1 || bands == 2 || bands == 4,
-               "sdtw_stream_set_bands: bands %d not in {0,1,2,4}", bands);
+               "sdtw_stream_set_config: bands %d not in {0,1,2,4}", bands);
+  g_stream_strip.store(strip);
   g_stream_bands.store(bands);
   return SDTW_OK;
 }
@@ -845,15 +854,17 @@ int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk
   std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
     return len(a) != len(b) ? len(a) > len(b) : a < b;
   });
-  // One chain per lane; row bands (four waves per chunk) when the chunks are
-  // too few to give every SIMD two waves and long enough to be cut.
-  constexpr int kStrip = 16, kChains = 1;
+  // One chain per lane.  Automatic shape: more waves per chunk the fewer
+  // chunks there are (a chunk's latency shrinks with its bands while the
+  // device is not full), one per chunk from four chunks per compute unit on;
+  // strip 16, whose workgroups need a third of strip 32's LDS, so that calls
+  // in flight on several HIP streams share the compute units.
+  constexpr int kChains = 1;
   const int cus = std::max(cu_count(), 1);
-  // Automatic: more waves per chunk the fewer chunks there are (a chunk's
-  // latency shrinks with its bands while the device is not full), one per
-  // chunk from four chunks per compute unit on.
   int bands = g_stream_bands.load();
   if (bands == 0) bands = ns <= cus ? 4 : (ns < 4 * cus ? 2 : 1);
+  int kStrip = g_stream_strip.load();
+  if (kStrip == 0) kStrip = 16;
   int32_t nbig = 0, max_band = 0;
   while (nbig < ns && len(order[(size_t)nbig]) >= skew_min_m(kChains)) {
     max_band = std::max(max_band, skew_band_rows((int32_t)len(order[(size_t)nbig]), kChains, bands));
@@ -867,11 +878,24 @@ int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk
   const int dev = ref->device;
   DescRing& ring = g_ring[dev >= 0 && dev < kMaxDevices ? dev : 0];
   std::lock_guard<std::mutex> g(ring.mu);
-  DescSlot& sl = ring.slot[ring.next];
-  if (sl.last && sl.last->ev) {
-    int rc = check_hip(hipEventSynchronize(sl.last->ev), "sdtw_stream_extend: slot wait");
+  DescSlot* pick = nullptr;
+  for (auto& c : ring.slot) {
+    if (!c->last || !c->last->ev || hipEventQuery(c->last->ev) == hipSuccess) {
+      pick = c.get();
+      break;
+    }
+  }
+  if (!pick && (int)ring.slot.size() < kMaxDescSlots) {
+    ring.slot.push_back(std::make_unique<DescSlot>());
+    pick = ring.slot.back().get();
+  }
+  if (!pick) {
+    pick = ring.slot[(size_t)ring.next].get();
+    ring.next = (ring.next + 1) % kMaxDescSlots;
+    int rc = check_hip(hipEventSynchronize(pick->last->ev), "sdtw_stream_extend: slot wait");
     if (rc) return rc;
   }
+  DescSlot& sl = *pick;
   int rc = ensure_slot(sl, ns);
   if (rc) return rc;
   for (int32_t t = 0; t < ns; ++t) {
@@ -903,10 +927,11 @@ int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk
     a.nwork = nbig;
     a.max_m = (int32_t)len(order[0]);
     a.max_band = max_band;
+    // no LDS reservation (spread_lds): calls in flight on other HIP streams
+    // (other targets, the next batch) must find room on every CU
     const int wpc = skew_waves_per_cu(kStrip, kChains, bands, max_band, true);
     const int blocks = (int)std::min<int64_t>((int64_t)cus * (wpc / bands), nbig);
-    a.lds_bytes = spread_lds(skew_lds_bytes(kStrip, kChains, bands, max_band, true), blocks,
-                             wpc / bands, cus);
+    a.lds_bytes = 0;
     rc = check_hip(launch_align_skew(dtype, kStrip, kChains, bands, blocks, a, st, true),
                    "sdtw_stream_extend: launch");
   }
@@ -919,7 +944,6 @@ int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk
   if (!rc) rc = check_hip(hipEventRecord(tok->ev, st), "sdtw_stream_extend: record");
   if (rc) return rc;
   sl.last = tok;
-  ring.next = (ring.next + 1) % kDescSlots;
   for (int32_t i = 0; i < ns; ++i) {
     streams[i]->rows += (int32_t)len(i);
     streams[i]->last = tok;

@@ -17,10 +17,12 @@ This module simulates the channels and runs the decisions through the C ABI:
   extending its resident row equals aligning the concatenated read;
 * admission: a read gets a stream (a resident row) when the row budget
   allows; otherwise it waits, and its chunks queue;
-* continuous batching: on every tick all chunks that have arrived (and whose
-  read has no chunk in flight) are normalised and extended in one launch per
-  target; targets run on separate HIP streams so that short-reference work
-  never waits behind long-reference work;
+* continuous batching: all chunks that have arrived (and whose read has no
+  chunk in flight) are normalised and extended in one launch per target as
+  soon as one of the target's HIP streams has no batch in flight; chunks
+  that arrive meanwhile wait and join the next batch.  Targets have their
+  own streams, so short-reference work never waits behind long-reference
+  work;
 * decision rule (a reading; the paper only says that position and score
   feed the selection criteria): s = cost / (scale * rows), the mean
   per-event distance in z-units; keep if s <= tau, reject if rows >=
@@ -52,6 +54,9 @@ class ServerConfig:
     scale: float = 64.0
     row_budget_bytes: int | None = None
     seed: int = 4004
+    streams_per_target: int = 2        # HIP streams per target: launches of later ticks overlap
+    stream_strip: int = 0              # sdtw_stream_set_config strip (0: the library's choice)
+    prewarm_rows: bool = True          # open (and close) rows for every channel before serving
 
 
 @dataclass
@@ -62,7 +67,7 @@ class Target:
     reads: list                        # raw pA event arrays (float32), >= max_events each
     on_target: np.ndarray              # bool per pool read
     tau: float = float("nan")          # decision threshold (z-units per event)
-    stream: object = None              # torch.cuda.Stream for this target's work
+    streams: list = field(default_factory=list)  # torch.cuda.Streams for this target's work
 
 
 @dataclass
@@ -82,8 +87,9 @@ class _Read:
 class _Tick:
     event: object
     target: int
+    slot: int                          # which of the target's streams
     entries: list                      # (channel, read, arrival, rows after)
-    cost: object
+    cost: object                       # pinned host copies of the results
     end: object
     t_submit: float
     cells: float
@@ -101,6 +107,7 @@ class ServerStats:
     cells: float = 0.0
     chunk_latency: list = field(default_factory=list)
     decision_latency: list = field(default_factory=list)
+    decision_target: list = field(default_factory=list)
     admission_waits: int = 0
     max_queue: int = 0
 
@@ -124,8 +131,8 @@ class ReadUntilServer:
         self.mode = mode
         self.rng = np.random.default_rng(self.cfg.seed)
         for t in self.targets:
-            if t.stream is None:
-                t.stream = torch.cuda.Stream()
+            while len(t.streams) < max(1, self.cfg.streams_per_target):
+                t.streams.append(torch.cuda.Stream())
         if self.cfg.row_budget_bytes is not None:
             sd.set_row_budget(self.cfg.row_budget_bytes)
 
@@ -170,12 +177,30 @@ class ReadUntilServer:
             return "reject"
         return None
 
+    def prewarm(self):
+        """Fill the library's row pool: open as many rows per target as there
+        are channels (or as the budget allows) and close them again, so that
+        admissions while serving reuse cached rows instead of allocating."""
+        for t in self.targets:
+            rows = []
+            try:
+                for _ in range(self.cfg.channels):
+                    rows.append(sd.Stream(t.ref))
+            except sd.SdtwError as e:
+                if e.code != "EBUDGET":
+                    raise
+            for r in rows:
+                r.close()
+
     def run(self, duration_s: float, warmup_s: float = 0.0) -> dict:
         """Serve for warmup_s + duration_s seconds of wall-clock time; report
         what was decided and measured during the last duration_s seconds."""
         torch = self.torch
         cfg = self.cfg
         dev = torch.device("cuda")
+        sd.set_stream_config(cfg.stream_strip, 0)
+        if cfg.prewarm_rows and self.mode == "extend":
+            self.prewarm()
         P = cfg.chunk_period_s
         t0 = time.perf_counter()
         t_meas = t0 + warmup_s
@@ -189,16 +214,28 @@ class ReadUntilServer:
             heapq.heappush(arrivals, (start + P, c))
         inflight: list[_Tick] = []
         waiting = []  # chunks that have arrived but are not submitted yet
+        host = {}  # host time per loop phase: key -> [total s, max s, calls]
+
+        def timed(key, t_start):
+            d = time.perf_counter() - t_start
+            v = host.setdefault(key, [0.0, 0.0, 0])
+            v[0] += d
+            v[1] = max(v[1], d)
+            v[2] += 1
 
         def harvest(block=False):
             done = [tk for tk in inflight if block or tk.event.query()]
             for tk in done:
                 inflight.remove(tk)
+                th = time.perf_counter()
                 tk.event.synchronize()
-                costs = tk.cost.cpu().numpy()
-                ends = tk.end.cpu().numpy() if self.record is not None else None
+                costs = tk.cost.numpy()  # pinned host copies, complete with the event
+                ends = tk.end.numpy()
+                timed("results", th)
+                th = time.perf_counter()
                 for s in tk.scratch:
                     s.close()
+                timed("close_scratch", th)
                 now = time.perf_counter()
                 in_window = t_meas <= now <= t_end
                 if in_window:
@@ -217,12 +254,15 @@ class ReadUntilServer:
                     if in_window:
                         stats.decisions += 1
                         stats.decision_latency.append(now - arr)
+                        stats.decision_target.append(rd.target)
                         stats.kept += verdict == "keep"
                         stats.rejected += verdict == "reject"
                         stats.decided_on_target += rd.on
                         stats.correct += (verdict == "keep") == rd.on
                     if rd.handle is not None:
+                        th = time.perf_counter()
                         rd.handle.close()
+                        timed("stream_close", th)
                         rd.handle = None
                     chan_read[c] = self._new_read(now)
                     heapq.heappush(arrivals, (now + P, c))
@@ -241,7 +281,9 @@ class ReadUntilServer:
                 rd = chan_read[c]
                 if self.mode == "extend" and rd.handle is None:
                     try:
+                        th = time.perf_counter()
                         rd.handle = sd.Stream(self.targets[rd.target].ref)
+                        timed("stream_open", th)
                     except sd.SdtwError as e:
                         if e.code != "EBUDGET":
                             raise
@@ -249,10 +291,20 @@ class ReadUntilServer:
                         keep_waiting.append((arr, c))
                         continue
                 groups.setdefault(rd.target, []).append((arr, c))
-            waiting = keep_waiting
+            # continuous batching: a target's ready chunks go out together on
+            # one of its HIP streams that has no batch in flight; while all
+            # are busy they wait and join the next batch
+            submitted = False
             for ti, items in groups.items():
-                self._submit(ti, items, chan_read, inflight, dev)
-            if not groups:
+                if self._free_slot(ti, inflight) is None:
+                    keep_waiting.extend(items)
+                else:
+                    th = time.perf_counter()
+                    self._submit(ti, items, chan_read, inflight, dev)
+                    timed("submit " + self.targets[ti].name, th)
+                    submitted = True
+            waiting = keep_waiting
+            if not submitted:
                 nxt = arrivals[0][0] if arrivals else now + 0.002
                 time.sleep(max(0.0, min(nxt - time.perf_counter(), 0.0005 if inflight else 0.002)))
         harvest(block=True)
@@ -283,7 +335,24 @@ class ReadUntilServer:
             "admission_waits": stats.admission_waits,
             "max_waiting_chunks": stats.max_queue,
             "tau": {t.name: round(t.tau, 4) for t in self.targets},
+            "host_loop_ms": {k: {"total": round(v[0] * 1e3, 1), "max": round(v[1] * 1e3, 2),
+                                 "calls": v[2]} for k, v in host.items()},
+            "per_target": {
+                t.name: {"decisions": int((np.asarray(stats.decision_target) == ti).sum()),
+                         "decision_latency_p50_ms": pct(lat[np.asarray(stats.decision_target)
+                                                            == ti], 50),
+                         "decision_latency_p99_ms": pct(lat[np.asarray(stats.decision_target)
+                                                            == ti], 99)}
+                for ti, t in enumerate(self.targets)},
         }
+
+    def _free_slot(self, ti, inflight):
+        """Index of one of target ti's HIP streams with no batch in flight."""
+        busy = {tk.slot for tk in inflight if tk.target == ti}
+        for k in range(len(self.targets[ti].streams)):
+            if k not in busy:
+                return k
+        return None
 
     def _submit(self, ti, items, chan_read, inflight, dev):
         """Normalise and extend the ready chunks of one target in one launch."""
@@ -294,7 +363,9 @@ class ReadUntilServer:
         first = [(a, c) for a, c in items if chan_read[c].chunks_done == 0]
         cont = [(a, c) for a, c in items if chan_read[c].chunks_done > 0]
         entries, code_parts, lens, scratch = [], [], [], []
-        with torch.cuda.stream(t.stream):
+        slot = self._free_slot(ti, inflight)
+        hs = t.streams[slot]
+        with torch.cuda.stream(hs):
             for group, fresh in ((first, True), (cont, False)):
                 if not group:
                     continue
@@ -304,19 +375,23 @@ class ReadUntilServer:
                     rd = chan_read[c]
                     a = 0 if lo == 0 else rd.chunks_done * E
                     segs.append(rd.raw[a:(rd.chunks_done + 1) * E])
-                raw = torch.from_numpy(np.concatenate(segs).astype(np.float32)).to(dev)
+                # pinned staging and asynchronous copies: the host loop never
+                # waits for earlier work queued on the stream
                 offs_np = np.zeros(len(segs) + 1, np.int64)
                 np.cumsum([x.size for x in segs], out=offs_np[1:])
-                offs = torch.from_numpy(offs_np).to(dev)
+                raw = torch.from_numpy(np.concatenate(segs).astype(np.float32)).pin_memory()
+                offs = torch.from_numpy(offs_np).pin_memory()
+                raw = raw.to(dev, non_blocking=True)
+                offs = offs.to(dev, non_blocking=True)
                 if fresh:
                     # the read's statistics are those of its first chunk
-                    _, codes, _, st = sd.prepare_queries_ex(raw, offs, cfg.scale, stream=t.stream)
+                    _, codes, _, st = sd.prepare_queries_ex(raw, offs, cfg.scale, stream=hs)
                     for k, (_, c) in enumerate(group):
                         chan_read[c].stats = st[k:k + 1]
                 else:
                     st_in = torch.cat([chan_read[c].stats for _, c in group])
                     _, codes, _, _ = sd.prepare_queries_ex(raw, offs, cfg.scale, st_in,
-                                                           stream=t.stream)
+                                                           stream=hs)
                 code_parts.append(codes)
                 lens += [x.size for x in segs]
                 entries += [(c, chan_read[c], arr) for arr, c in group]
@@ -336,15 +411,22 @@ class ReadUntilServer:
                                 raise
                             time.sleep(0.001)
                 handles = scratch
-            cost, end = sd.stream_extend(handles, codes, offs_np, stream=t.stream)
+            cost, end = sd.stream_extend(handles, codes, offs_np, stream=hs)
+            # results to pinned host memory on the same stream: the event then
+            # marks them readable and harvesting never issues a copy (a copy
+            # to pageable memory could wait for other streams' work)
+            cost_h = torch.empty(cost.shape, dtype=cost.dtype, pin_memory=True)
+            end_h = torch.empty(end.shape, dtype=end.dtype, pin_memory=True)
+            cost_h.copy_(cost, non_blocking=True)
+            end_h.copy_(end, non_blocking=True)
             ev = torch.cuda.Event()
-            ev.record(t.stream)
+            ev.record(hs)
         out = []
         for c, rd, arr in entries:
             rd.chunks_done += 1
             rd.rows = rd.chunks_done * E
             out.append((c, rd, arr, rd.rows))
-        inflight.append(_Tick(ev, ti, out, cost, end, time.perf_counter(),
+        inflight.append(_Tick(ev, ti, slot, out, cost_h, end_h, time.perf_counter(),
                               float(sum(lens)) * t.ref.n, scratch))
 
 

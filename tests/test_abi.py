@@ -69,7 +69,8 @@ def test_argument_validation(lib):
     assert lib.sdtw_plan_set_config(None, 16, 2, 1, 4) == 1
     assert lib.sdtw_plan_autotune(None, None, p, p, p, 0, None) == 1
     assert lib.sdtw_plan_use_tuned(None, None, None) == 1
-    assert lib.sdtw_stream_set_bands(3) == 1
+    assert lib.sdtw_stream_set_config(0, 3) == 1
+    assert lib.sdtw_stream_set_config(8, 0) == 1
     assert lib.sdtw_free_reference(None) == 1
     assert lib.sdtw_plan_destroy(None) == 1
     assert "null" in _err(lib)

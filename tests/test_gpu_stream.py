@@ -105,36 +105,38 @@ PLANS = [[400, 400, 400], [70, 30, 300], [1, 64, 65, 200], [250], [65, 65, 65, 6
 
 
 @pytest.mark.parametrize("dt", ["i16", "f32"])
-@pytest.mark.parametrize("bands", [0, 1, 2, 4])
-def test_extend_equals_from_scratch(dev, prepared, dt, bands):
+@pytest.mark.parametrize("strip,bands", [(0, 0), (16, 1), (16, 2), (16, 4), (32, 1), (32, 2),
+                                         (32, 4)])
+def test_extend_equals_from_scratch(dev, prepared, dt, strip, bands):
     w, z, codes = prepared
     reads = chunked_reads(w, PLANS)
-    sd.set_stream_bands(bands)
+    sd.set_stream_config(strip, bands)
     try:
         run_rounds(dev, codes if dt == "i16" else z, reads, sd.I16 if dt == "i16" else sd.F32)
     finally:
-        sd.set_stream_bands(0)
+        sd.set_stream_config(0, 0)
 
 
-@pytest.mark.parametrize("bands", [1, 4])
-def test_extend_diagonal_at_chunk_and_band_boundaries(dev, bands):
+@pytest.mark.parametrize("strip,bands", [(16, 1), (16, 4), (32, 4)])
+def test_extend_diagonal_at_chunk_and_band_boundaries(dev, strip, bands):
     # a read that is an exact substring of the reference, cut into chunks so
     # that its zero-cost diagonal crosses the first chunk boundary exactly at
     # a tile boundary (column 2T) and, with four bands, the boundary between
     # bands 0 and 1 of the third chunk (2016 rows, bands of 504) at column 3T
-    T = 64 * 16
-    rng = np.random.default_rng(17 + bands)
-    ref = rng.permutation(np.arange(-30000, 30000, 9))[:6 * T].astype(np.int16)
+    T = 64 * (strip or 16)
+    rng = np.random.default_rng(17 + bands + strip)
+    ref = rng.permutation(np.arange(-30000, 30000, 4))[:6 * T].astype(np.int16)
     s = 2 * T - 300
-    x = ref[s:s + 300 + 520 + 2016].copy()
-    assert s + 300 + 520 + 504 == 3 * T
-    reads = [(None, None, x, np.array([0, 300, 300 + 520, x.size]))]
-    sd.set_stream_bands(bands)
+    c2 = T - 504
+    x = ref[s:s + 300 + c2 + 2016].copy()
+    assert s + 300 + c2 + 504 == 3 * T
+    reads = [(None, None, x, np.array([0, 300, 300 + c2, x.size]))]
+    sd.set_stream_config(strip, bands)
     try:
         got = run_rounds(dev, ref, reads, sd.I16)
     finally:
-        sd.set_stream_bands(0)
-    assert [(e, c) for (_, _, e, c) in got] == [(s + 299, 0.0), (s + 819, 0.0),
+        sd.set_stream_config(0, 0)
+    assert [(e, c) for (_, _, e, c) in got] == [(s + 299, 0.0), (s + 299 + c2, 0.0),
                                                 (s + x.size - 1, 0.0)]
 
 
