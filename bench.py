@@ -44,6 +44,32 @@ CUS, SIMDS_PER_CU, CLOCK_GHZ = 256, 4, 2.4
 SIMD_CYCLES_PER_64_CELLS = {"i16": 4 + 4, "f32": 2 + 4 + 2}
 
 
+# HBM bytes per launch of the alignment kernel, from the rocprofv3 FETCH_SIZE
+# and WRITE_SIZE passes summarised in
+# profiles/counters_k_align_skew_i16_w32_b1_4096x250.md (each scaled by what
+# the counter reads for a plain copy of known size), keyed by workload and
+# launch shape, valid only while the kernel source is the one measured
+# (sha256 of csrc/align.hip); otherwise `traffic` is null.
+MEASURED_TRAFFIC = {
+    ("4096 reads M=250 vs 29,903-base genome", "i16", 32, 1, 1): {
+        "fetch_bytes": 4793859, "write_bytes": 367104,
+        "align_hip_sha256": "46d84c1cb2c5deb2e553b5047cb76c71669985e8874fe141c793841158cac53b"},
+}
+
+
+def measured_traffic(workload: str, dtype: str, cfg: dict):
+    import hashlib
+    key = (workload, dtype, cfg["strip"], cfg["chains"], cfg["bands"])
+    m = MEASURED_TRAFFIC.get(key)
+    if m is None:
+        return None
+    src = os.path.join(ROOT, "paper_2211_07340_amd", "csrc", "align.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != m["align_hip_sha256"]:
+            return None
+    return m["fetch_bytes"] + m["write_bytes"]
+
+
 def valu_peak_tcups(dtype: str) -> float:
     return CUS * SIMDS_PER_CU * CLOCK_GHZ * 1e9 * 64 / SIMD_CYCLES_PER_64_CELLS[dtype] / 1e12
 
@@ -167,7 +193,8 @@ def main():
         "roofline": {"bound": "alu", "kernel": "sdtw_align_batch",
                      "achieved": round(kern_tcups, 3), "peak": round(peak, 3),
                      "unit": "TCUPS", "frac": round(kern_tcups / peak, 4),
-                     "kernel_ms": round(kern_ms, 4), "traffic": None},
+                     "kernel_ms": round(kern_ms, 4),
+                     "traffic": measured_traffic(w.name, args.dtype, pcfg)},
     }
 
     if not args.no_extras:
@@ -248,8 +275,7 @@ def serving(torch, dev, seconds: float, warmup: float, channels: int, recompute_
     """Streaming Read Until: incremental extension, then recompute from scratch."""
     from paper_2211_07340_amd import server as srv
     targets = serving_targets(torch, dev, large=large)
-    cfg = srv.ServerConfig(channels=channels, row_budget_bytes=64 << 30,
-                           stream_strip=int(os.environ.get("SDTW_SERVE_STRIP", "0")))
+    cfg = srv.ServerConfig(channels=channels, row_budget_bytes=64 << 30)
     inc = srv.ReadUntilServer(targets, cfg, mode="extend")
     inc.calibrate()
     out = {"workload": f"{channels} channels, 400-event chunks every 0.1 s, reads to "

@@ -55,7 +55,8 @@ class ServerConfig:
     row_budget_bytes: int | None = None
     seed: int = 4004
     streams_per_target: int = 2        # HIP streams per target: launches of later ticks overlap
-    stream_strip: int = 0              # sdtw_stream_set_config strip (0: the library's choice)
+    stream_strip: int = 32             # sdtw_stream_set_config strip (0: the library's choice);
+                                       # 32 halves the tiles of a long reference per chunk
     prewarm_rows: bool = True          # open (and close) rows for every channel before serving
 
 
