@@ -301,9 +301,9 @@ def cpu_baseline(w, reads, args):
     r = codes if args.dtype == "i16" else z
     if args.cpu_sample:
         n = args.cpu_sample
-    else:  # about 10 s of work at ~0.25 GCUPS per core
+    else:  # 1e10 cells per core: about 10-15 s at the oracle's ~0.7 GCUPS per core
         per_read = reads.lengths.astype(np.float64) * r.size
-        n = int(np.searchsorted(np.cumsum(per_read), 2.5e9 * cores)) + 1
+        n = int(np.searchsorted(np.cumsum(per_read), 1e10 * cores)) + 1
         n = max(1, min(reads.nq, n))
     idx = np.arange(n)
     threads = min(cores, n)
