@@ -18,6 +18,9 @@ What it computes (each function cites the passage it follows):
   (section 2.3, Eq. 1 and its boundary conditions; evaluated column by column
   with an (M+1) cost array as Algorithm 2 of section 4.3 describes).
 * ``batch``         -- the same over a CSR batch of reads with POSIX threads.
+* ``best_two``      -- the best end and the best end outside a window around
+  it, on a last row (the two mapped positions a MAPQ-like decision compares;
+  section 5.2 computes a mapping quality from the positions and scores).
 
 The C source is ``sdtw_oracle.c``; ``build()`` compiles it with gcc.  The
 brute-force warping-path enumerator and the full-matrix recurrence used to pin
@@ -229,3 +232,26 @@ def prepare_queries(values: np.ndarray, offsets: np.ndarray, scale: float = 64.0
         z[a:b] = znorm(v[a:b])
     codes, nsat = quantize(z, scale)
     return z, codes, nsat
+
+
+def best_two(row: np.ndarray, window: int):
+    """Best and runner-up ends of a last row gamma(M, .) (0-based columns).
+
+    best = the first j with the minimum value (the strict-less scan of
+    Algorithms 1 and 2); second = the first j with the minimum value among
+    the columns with |j - best| > window.  Returns (best value, best j,
+    second value, second j); second is (inf, -1) when no column lies outside
+    the window.  Values are compared as given (int64 or float).
+    """
+    row = np.asarray(row)
+    if row.size == 0 or window < 0:
+        raise ValueError("empty row or negative window")
+    jb = int(np.argmin(row))  # numpy returns the first index of the minimum
+    j = np.arange(row.size)
+    out = np.abs(j - jb) > window
+    if not out.any():
+        return row[jb], jb, float("inf"), -1
+    # among the outside columns only: the first index attaining their minimum
+    m = row[out].min()
+    js = int(np.nonzero(out & (row == m))[0][0])
+    return row[jb], jb, m, js

@@ -385,3 +385,31 @@ def test_literal_algorithm2_counterexample():
     # the reading recorded for the garbled neighbour indices of Algorithm 2
     assert _literal_algorithm2([0, 10], [0, 10]) == (10, 0)
     assert brute.enumerate_paths([0, 10], [0, 10]) == (0, 1)
+
+
+# ---- best and runner-up ends (decision stage) -------------------------------
+
+def test_best_two_hand_examples():
+    row = np.array([5, 1, 3, 1, 0, 2])
+    assert oracle.best_two(row, 0) == (0, 4, 1, 1)   # runner-up: first of the tied 1s
+    assert oracle.best_two(row, 2) == (0, 4, 1, 1)   # j in {0, 1} remain
+    assert oracle.best_two(row, 3) == (0, 4, 5, 0)   # only j = 0 remains
+    assert oracle.best_two(row, 4) == (0, 4, float("inf"), -1)
+    # ties for the best: the first index wins, the other tie is the runner-up
+    assert oracle.best_two(np.array([2, 7, 2, 9]), 1) == (2, 0, 2, 2)
+    assert oracle.best_two(np.array([2, 7, 2, 9]), 2) == (2, 0, 9, 3)
+
+
+def test_best_two_against_sorted_scan():
+    # independent formulation: sort (value, j) lexicographically; the best is
+    # the first pair, the runner-up the first later pair outside the window
+    rng = np.random.default_rng(31)
+    for _ in range(300):
+        n = int(rng.integers(1, 40))
+        row = rng.integers(0, 6, size=n)
+        w = int(rng.integers(0, 8))
+        pairs = sorted((int(v), j) for j, v in enumerate(row))
+        b = pairs[0]
+        rest = [p for p in pairs[1:] if abs(p[1] - b[1]) > w]
+        want = (b[0], b[1]) + ((rest[0][0], rest[0][1]) if rest else (float("inf"), -1))
+        assert oracle.best_two(row, w) == want, (row, w)
