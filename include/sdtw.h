@@ -318,6 +318,25 @@ int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk
                        void* stream);
 
 /*
+ * Best and runner-up ends of the resident rows of `ns` streams on one
+ * reference: the two mapped positions and scores a mapping quality is
+ * computed from (section 5.2).  best = the first column with the row's
+ * minimum (the end the last sdtw_stream_extend returned); second = the first
+ * column with the minimum among the columns farther than `window` from best.
+ *   window           >= 0 columns.
+ *   best_cost_dev, second_cost_dev   out [ns]: int32 (SDTW_I16) or float32
+ *                    (SDTW_F32), in stream order.
+ *   best_end_dev, second_end_dev     out int32 [ns], 0-based columns.
+ * When no column lies outside the window, second is INT32_MAX (int16 path)
+ * or +inf, at column -1.  Enqueued on `stream`; order it after the extends
+ * that wrote the rows (same stream).  Closing a stream waits for this call.
+ * SDTW_ESTATE if a stream has no rows yet.
+ */
+int sdtw_stream_best_two(const sdtw_stream* streams, int32_t ns, int32_t window,
+                         void* best_cost_dev, int32_t* best_end_dev, void* second_cost_dev,
+                         int32_t* second_end_dev, void* stream);
+
+/*
  * Launch shape of later sdtw_stream_extend calls in this process (one chain
  * per lane):
  *   strip  columns per lane, 16 or 32; 0 (default) = 16.

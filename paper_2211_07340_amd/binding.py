@@ -59,6 +59,7 @@ def load_library():
         "sdtw_align_one": ([p, p, i32, p, p, p], C.c_int),
         "sdtw_prepare_queries_ex": ([p, p, i32, dbl, p, p, p, p, p, p], C.c_int),
         "sdtw_stream_set_config": ([C.c_int, C.c_int], C.c_int),
+        "sdtw_stream_best_two": ([p, i32, i32, p, p, p, p, p], C.c_int),
         "sdtw_set_row_budget": ([i64], C.c_int),
         "sdtw_row_budget_info": ([C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)], C.c_int),
         "sdtw_stream_open": ([p, C.POINTER(p)], C.c_int),
@@ -321,6 +322,25 @@ def align_one(ref: Reference, q, cost=None, end=None, stream=None):
 def set_row_budget(nbytes: int):
     """Byte budget of resident rows on the current device."""
     _check(load_library().sdtw_set_row_budget(int(nbytes)))
+
+
+def stream_best_two(streams, window: int, stream=None):
+    """sdtw_stream_best_two: (best_cost, best_end, second_cost, second_end)
+    device tensors for the streams' resident rows."""
+    torch = _torch()
+    ns = len(streams)
+    if ns == 0:
+        raise ValueError("no streams")
+    dt = streams[0].ref.dtype
+    dev = torch.device("cuda", torch.cuda.current_device())
+    cdt = torch.int32 if dt == I16 else torch.float32
+    bc, sc = torch.empty(ns, dtype=cdt, device=dev), torch.empty(ns, dtype=cdt, device=dev)
+    be, se = (torch.empty(ns, dtype=torch.int32, device=dev),
+              torch.empty(ns, dtype=torch.int32, device=dev))
+    arr = (C.c_void_p * ns)(*[s.handle for s in streams])
+    _check(load_library().sdtw_stream_best_two(arr, ns, int(window), _dev(bc), _dev(be),
+                                               _dev(sc), _dev(se), _stream(stream)))
+    return bc, be, sc, se
 
 
 def set_stream_config(strip: int = 0, bands: int = 0):

@@ -183,6 +183,33 @@ static int ensure_slot(DescSlot& sl, int32_t n) {
   return SDTW_OK;
 }
 
+// A descriptor slot for a call of n items: one whose previous call has
+// completed, else a new one (up to kMaxDescSlots), else the round-robin
+// victim after its call completes.  The caller holds ring.mu.
+static int acquire_slot(DescRing& ring, int32_t n, DescSlot** out, const char* who) {
+  DescSlot* pick = nullptr;
+  for (auto& c : ring.slot) {
+    if (!c->last || !c->last->ev || hipEventQuery(c->last->ev) == hipSuccess) {
+      pick = c.get();
+      break;
+    }
+  }
+  if (!pick && (int)ring.slot.size() < kMaxDescSlots) {
+    ring.slot.push_back(std::make_unique<DescSlot>());
+    pick = ring.slot.back().get();
+  }
+  if (!pick) {
+    pick = ring.slot[(size_t)ring.next].get();
+    ring.next = (ring.next + 1) % kMaxDescSlots;
+    int rc = check_hip(hipEventSynchronize(pick->last->ev), who);
+    if (rc) return rc;
+  }
+  int rc = ensure_slot(*pick, n);
+  if (rc) return rc;
+  *out = pick;
+  return SDTW_OK;
+}
+
 }  // namespace sdtw
 
 using namespace sdtw;
@@ -879,25 +906,9 @@ int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk
   DescRing& ring = g_ring[dev >= 0 && dev < kMaxDevices ? dev : 0];
   std::lock_guard<std::mutex> g(ring.mu);
   DescSlot* pick = nullptr;
-  for (auto& c : ring.slot) {
-    if (!c->last || !c->last->ev || hipEventQuery(c->last->ev) == hipSuccess) {
-      pick = c.get();
-      break;
-    }
-  }
-  if (!pick && (int)ring.slot.size() < kMaxDescSlots) {
-    ring.slot.push_back(std::make_unique<DescSlot>());
-    pick = ring.slot.back().get();
-  }
-  if (!pick) {
-    pick = ring.slot[(size_t)ring.next].get();
-    ring.next = (ring.next + 1) % kMaxDescSlots;
-    int rc = check_hip(hipEventSynchronize(pick->last->ev), "sdtw_stream_extend: slot wait");
-    if (rc) return rc;
-  }
-  DescSlot& sl = *pick;
-  int rc = ensure_slot(sl, ns);
+  int rc = acquire_slot(ring, ns, &pick, "sdtw_stream_extend");
   if (rc) return rc;
+  DescSlot& sl = *pick;
   for (int32_t t = 0; t < ns; ++t) {
     const int32_t i = order[(size_t)t];
     StreamItem& it = sl.host[t];
@@ -941,13 +952,63 @@ int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk
     a.max_m = (int32_t)len(order[(size_t)nbig]);
     rc = check_hip(launch_align_plain(dtype, kStrip, a, st, true), "sdtw_stream_extend: launch");
   }
-  if (!rc) rc = check_hip(hipEventRecord(tok->ev, st), "sdtw_stream_extend: record");
+  // the slot is busy until this point of the stream, whatever was enqueued
+  const int rc_ev = check_hip(hipEventRecord(tok->ev, st), "sdtw_stream_extend: record");
+  if (!rc_ev) sl.last = tok;
+  if (!rc) rc = rc_ev;
   if (rc) return rc;
-  sl.last = tok;
   for (int32_t i = 0; i < ns; ++i) {
     streams[i]->rows += (int32_t)len(i);
     streams[i]->last = tok;
   }
+  return SDTW_OK;
+}
+
+int sdtw_stream_best_two(const sdtw_stream* streams, int32_t ns, int32_t window,
+                         void* best_cost_dev, int32_t* best_end_dev, void* second_cost_dev,
+                         int32_t* second_end_dev, void* stream) {
+  SDTW_REQUIRE(streams && best_cost_dev && best_end_dev && second_cost_dev && second_end_dev,
+               "sdtw_stream_best_two: null pointer");
+  SDTW_REQUIRE(ns >= 1, "sdtw_stream_best_two: ns=%d < 1", ns);
+  SDTW_REQUIRE(window >= 0, "sdtw_stream_best_two: negative window");
+  SDTW_REQUIRE(streams[0], "sdtw_stream_best_two: stream 0 is null");
+  const sdtw_ref ref = streams[0]->ref;
+  for (int32_t i = 0; i < ns; ++i) {
+    SDTW_REQUIRE(streams[i], "sdtw_stream_best_two: stream %d is null", i);
+    SDTW_REQUIRE(streams[i]->ref == ref, "sdtw_stream_best_two: stream %d uses another reference",
+                 i);
+    if (streams[i]->rows == 0)
+      return set_error(SDTW_ESTATE, "sdtw_stream_best_two: stream %d has no rows yet", i);
+  }
+  const int dev = ref->device;
+  DescRing& ring = g_ring[dev >= 0 && dev < kMaxDevices ? dev : 0];
+  std::lock_guard<std::mutex> g(ring.mu);
+  DescSlot* pick = nullptr;
+  int rc = acquire_slot(ring, ns, &pick, "sdtw_stream_best_two");
+  if (rc) return rc;
+  DescSlot& sl = *pick;
+  for (int32_t i = 0; i < ns; ++i) {
+    StreamItem& it = sl.host[i];
+    it = StreamItem{};
+    it.acc = streams[i]->row;
+    it.out = i;
+  }
+  auto tok = std::make_shared<CallToken>();
+  tok->ev = event_get();
+  if (!tok->ev) return set_error(SDTW_EDEVICE, "sdtw_stream_best_two: event creation failed");
+  hipStream_t st = (hipStream_t)stream;
+  rc = check_hip(hipMemcpyAsync(sl.dev, sl.host, sizeof(StreamItem) * (size_t)ns,
+                                hipMemcpyHostToDevice, st),
+                 "sdtw_stream_best_two: descriptors");
+  if (!rc)
+    rc = check_hip(launch_best_two(ref->dtype, sl.dev, ns, ref->n, window, best_cost_dev,
+                                   best_end_dev, second_cost_dev, second_end_dev, st),
+                   "sdtw_stream_best_two: launch");
+  const int rc_ev = check_hip(hipEventRecord(tok->ev, st), "sdtw_stream_best_two: record");
+  if (!rc_ev) sl.last = tok;
+  if (!rc) rc = rc_ev;
+  if (rc) return rc;
+  for (int32_t i = 0; i < ns; ++i) streams[i]->last = tok;  // close waits for the read
   return SDTW_OK;
 }
 

@@ -121,6 +121,13 @@ hipError_t launch_align_skew(int dtype, int strip, int chains, int bands, int bl
 hipError_t launch_align_plain(int dtype, int strip, const AlignArgs& a, hipStream_t st,
                               bool stream = false);
 size_t plain_lds_bytes(int dtype, int strip, int max_m);
+
+// ---- launchers (scores.hip) -------------------------------------------------
+// Best and runner-up ends of the resident rows items[i].acc (n columns), out
+// to index items[i].out; one workgroup per item.
+hipError_t launch_best_two(int dtype, const StreamItem* items, int32_t ns, int64_t n,
+                           int32_t window, void* best_cost, int32_t* best_end,
+                           void* second_cost, int32_t* second_end, hipStream_t st);
 int max_lds_bytes();
 
 }  // namespace sdtw

@@ -70,6 +70,7 @@ def test_argument_validation(lib):
     assert lib.sdtw_plan_autotune(None, None, p, p, p, 0, None) == 1
     assert lib.sdtw_plan_use_tuned(None, None, None) == 1
     assert lib.sdtw_stream_set_config(0, 3) == 1
+    assert lib.sdtw_stream_best_two(None, 1, 0, p, p, p, p, None) == 1
     assert lib.sdtw_stream_set_config(8, 0) == 1
     assert lib.sdtw_free_reference(None) == 1
     assert lib.sdtw_plan_destroy(None) == 1

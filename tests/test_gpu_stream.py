@@ -140,6 +140,41 @@ def test_extend_diagonal_at_chunk_and_band_boundaries(dev, strip, bands):
                                                 (s + x.size - 1, 0.0)]
 
 
+@pytest.mark.parametrize("dt", ["i16", "f32"])
+def test_best_two_matches_oracle(dev, prepared, dt):
+    # best and runner-up ends of resident rows after ragged extensions, for
+    # windows from 0 to beyond the row (no runner-up)
+    w, z, codes = prepared
+    ref_np = codes if dt == "i16" else z
+    reads = chunked_reads(w, PLANS[:5], seed=21)
+    ref = sd.Reference(torch.from_numpy(ref_np).to(dev))
+    streams = [sd.Stream(ref) for _ in reads]
+    vals = [(r[2] if dt == "i16" else r[1]) for r in reads]
+    q, offs = synth.csr(vals)
+    q = q.astype(np.int16 if dt == "i16" else np.float32)
+    sd.stream_extend(streams, torch.from_numpy(q).to(dev), offs)
+    for window in (0, 3, 250, 40000, ref_np.size):
+        bc, be, sc, se = [t.cpu().numpy() for t in sd.stream_best_two(streams, window)]
+        torch.cuda.synchronize()
+        for i, v in enumerate(vals):
+            if dt == "i16":
+                _, _, row = oracle.sdtw_i64(v, ref_np, lastrow=True)
+                want = oracle.best_two(row, window)
+                got = (int(bc[i]), int(be[i]),
+                       float("inf") if se[i] < 0 else int(sc[i]), int(se[i]))
+            else:
+                _, _, row = oracle.sdtw_f32(v, ref_np, lastrow=True)
+                want = oracle.best_two(row, window)
+                want = (np.float32(want[0]), want[1], np.float32(want[2]), want[3])
+                got = (np.float32(bc[i]), int(be[i]), np.float32(sc[i]), int(se[i]))
+            assert got == tuple(want), (i, window)
+            if se[i] < 0:
+                assert sc[i] == (np.iinfo(np.int32).max if dt == "i16" else np.inf)
+    for st in streams:
+        st.close()
+    ref.close()
+
+
 def test_extend_ragged_reference(dev):
     rng = np.random.default_rng(4)
     ref = rng.integers(-3000, 3000, size=3001).astype(np.int16)
