@@ -199,6 +199,7 @@ def main():
 
     if not args.no_extras:
         out["extras"] = extras(sd, torch, dev, w, reads, zref, cref, args, stream)
+        out["extras"]["hip_graph"] = graph_step(sd, torch, step, cost, end, args.steps)
 
     if args.serve_seconds > 0:
         out["serving"] = serving(torch, dev, args.serve_seconds, args.serve_warmup,
@@ -208,6 +209,33 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, reads, args)
     print(json.dumps(out), flush=True)
+
+
+def graph_step(sd, torch, step, cost, end, steps):
+    """The same step captured once in a HIP graph and replayed: time per
+    replay, and whether every replay's outputs equal the eager step's."""
+    step()
+    torch.cuda.synchronize()
+    want = (cost.clone(), end.clone())
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    g.replay()
+    torch.cuda.synchronize()
+    same = bool(torch.equal(cost, want[0]) and torch.equal(end, want[1]))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    same = same and bool(torch.equal(cost, want[0]) and torch.equal(end, want[1]))
+    return {"ms_per_step": round(ms, 4), "replays": steps + 1, "equal_to_eager": same}
 
 
 def extras(sd, torch, dev, w, reads, zref, cref, args, stream):
@@ -221,6 +249,7 @@ def extras(sd, torch, dev, w, reads, zref, cref, args, stream):
     z, codes, _ = sd.prepare_queries(raw, offs_dev, 64.0)
     q = z if dt == sd.F32 else codes
     plan = sd.Plan(reads.offsets, dt)
+    sd.autotune(ref, plan, q)
     cost, end = sd.align_batch(ref, plan, q)
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -232,7 +261,8 @@ def extras(sd, torch, dev, w, reads, zref, cref, args, stream):
     ms = a.elapsed_time(b) / 5
     cells = float(reads.lengths.sum()) * ref.n
     res[other] = {"kernel_ms": round(ms, 4), "gcups": round(cells / ms / 1e6, 1),
-                  "frac_valu_peak": round(cells / ms / 1e9 / valu_peak_tcups(other), 4)}
+                  "frac_valu_peak": round(cells / ms / 1e9 / valu_peak_tcups(other), 4),
+                  **plan.config}
     # one read per launch with the single-wave kernel, on the main dtype
     dt0 = sd.I16 if args.dtype == "i16" else sd.F32
     ref0 = sd.Reference(cref if dt0 == sd.I16 else zref)

@@ -93,6 +93,16 @@ static int current_device() {
   return d;
 }
 
+// Kernels run on the current device; objects of another device would be
+// reached through peer addresses, so every call that launches checks.
+static int require_device(int dev, const char* who) {
+  const int cur = current_device();
+  if (cur != dev)
+    return set_error(SDTW_EINVAL, "%s: objects live on device %d, current device is %d", who, dev,
+                     cur);
+  return SDTW_OK;
+}
+
 static int cu_count() {
   int dev = current_device(), v = 0;
   if (dev < 0 || hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -560,6 +570,9 @@ int sdtw_align_batch(sdtw_ref ref, sdtw_plan plan, const void* q_dev, void* cost
   SDTW_REQUIRE(q_dev && cost_dev && end_dev, "sdtw_align_batch: null device pointer");
   SDTW_REQUIRE(ref->dtype == plan->dtype, "sdtw_align_batch: reference dtype %d != plan dtype %d",
                ref->dtype, plan->dtype);
+  SDTW_REQUIRE(ref->device == plan->device, "sdtw_align_batch: reference and plan on devices %d, %d",
+               ref->device, plan->device);
+  if (int rc = require_device(ref->device, "sdtw_align_batch")) return rc;
   return align_batch_impl(ref, plan, q_dev, cost_dev, end_dev, (hipStream_t)stream, ref->n);
 }
 
@@ -610,6 +623,7 @@ int sdtw_align_one(sdtw_ref ref, const void* q_dev, int32_t M, void* cost_dev, i
   SDTW_REQUIRE(q_dev && cost_dev && end_dev, "sdtw_align_one: null device pointer");
   SDTW_REQUIRE(M >= 1 && M <= SDTW_MAX_QUERY, "sdtw_align_one: M=%d outside [1, %d]", M,
                SDTW_MAX_QUERY);
+  if (int rc = require_device(ref->device, "sdtw_align_one")) return rc;
   AlignArgs a{};
   a.ref = ref->data;
   a.n = ref->n;
@@ -661,6 +675,10 @@ int sdtw_plan_autotune(sdtw_ref ref, sdtw_plan plan, const void* q_dev, void* co
                "sdtw_plan_autotune: reference dtype %d != plan dtype %d", ref->dtype,
                plan->dtype);
   SDTW_REQUIRE(max_columns >= 0, "sdtw_plan_autotune: negative max_columns");
+  SDTW_REQUIRE(ref->device == plan->device,
+               "sdtw_plan_autotune: reference and plan on devices %d, %d", ref->device,
+               plan->device);
+  if (int rc = require_device(ref->device, "sdtw_plan_autotune")) return rc;
   hipStream_t st = (hipStream_t)stream;
   const int64_t n = max_columns ? std::min<int64_t>(ref->n, max_columns) : ref->n;
   // candidates: every strip / chains / bands the kernel is built for with
@@ -756,6 +774,7 @@ int sdtw_row_budget_info(int64_t* budget, int64_t* in_use, int64_t* cached) {
 
 int sdtw_stream_open(sdtw_ref ref, sdtw_stream* out) {
   SDTW_REQUIRE(ref && out, "sdtw_stream_open: null pointer");
+  if (int rc = require_device(ref->device, "sdtw_stream_open")) return rc;
   RowPool* pl = pool_for(ref->device);
   SDTW_REQUIRE(pl, "sdtw_stream_open: bad device");
   const size_t bytes = sizeof(uint32_t) * (size_t)ref->n_pad;
@@ -833,6 +852,7 @@ int sdtw_stream_close(sdtw_stream s) {
 
 int sdtw_stream_copy_row(sdtw_stream s, void* dst_dev, void* stream) {
   SDTW_REQUIRE(s && dst_dev, "sdtw_stream_copy_row: null pointer");
+  if (int rc = require_device(s->device, "sdtw_stream_copy_row")) return rc;
   if (s->rows == 0)
     return set_error(SDTW_ESTATE, "sdtw_stream_copy_row: the stream has no rows yet");
   return check_hip(hipMemcpyAsync(dst_dev, s->row, sizeof(uint32_t) * (size_t)s->ref->n,
@@ -859,6 +879,7 @@ int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk
   SDTW_REQUIRE(streams[0], "sdtw_stream_extend: stream 0 is null");
   const sdtw_ref ref = streams[0]->ref;
   const int dtype = ref->dtype;
+  if (int rc = require_device(ref->device, "sdtw_stream_extend")) return rc;
   const int32_t row_cap = dtype == SDTW_I16 ? 32767 : INT32_MAX;
   std::set<const sdtw_stream_s*> seen;
   std::vector<int32_t> order((size_t)ns);
@@ -973,6 +994,7 @@ int sdtw_stream_best_two(const sdtw_stream* streams, int32_t ns, int32_t window,
   SDTW_REQUIRE(window >= 0, "sdtw_stream_best_two: negative window");
   SDTW_REQUIRE(streams[0], "sdtw_stream_best_two: stream 0 is null");
   const sdtw_ref ref = streams[0]->ref;
+  if (int rc = require_device(ref->device, "sdtw_stream_best_two")) return rc;
   for (int32_t i = 0; i < ns; ++i) {
     SDTW_REQUIRE(streams[i], "sdtw_stream_best_two: stream %d is null", i);
     SDTW_REQUIRE(streams[i]->ref == ref, "sdtw_stream_best_two: stream %d uses another reference",
