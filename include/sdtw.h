@@ -192,9 +192,10 @@ int sdtw_plan_info(sdtw_plan plan, int32_t* nq, int* dtype, int32_t* max_m);
  *           4 (0 = keep); strip / chains must be a multiple of 4.  Reads
  *           with M >= 64 * chains + 1 use that many; shorter reads fall back
  *           to fewer chains, and reads with M <= 64 to the one-wave kernel.
- *   bands   waves per read: 1, 2 or 4 (0 = keep the plan's where they fit the
- *           other settings, else 1); more than 1 needs strip 16 with at most
- *           2 chains or strip 32 with 1 chain.  A read's rows are cut into
+ *   bands   waves per read: 1 to 4 (0 = keep the plan's where they fit the
+ *           other settings, else 1); 2 or 4 need strip 16 with at most 2
+ *           chains or strip 32 with 1 chain, 3 needs strip 16 or 32 with 1
+ *           chain.  A read's rows are cut into
  *           up to `bands` row bands of at least 64 * chains + 1 rows each
  *           (Eq. 1: a row depends on the rows above only through the
  *           previous row), one wave per band, pipelined over the
@@ -209,7 +210,7 @@ int sdtw_plan_get_config(sdtw_plan plan, int* strip, int* chains, int* bands,
 
 /*
  * Autotune the plan's kernel configuration on this batch: run every
- * candidate (strip 16 or 32, 1 or 2 chains, 1, 2 or 4 bands where valid,
+ * candidate (strip 16 or 32, 1 or 2 chains, 1 to 4 bands where valid,
  * each at the waves per CU its LDS allows and at half that) once to warm up
  * and once timed with HIP events on `stream`, keep the fastest on the plan
  * and remember it for sdtw_plan_use_tuned (keyed by device, dtype, reference
@@ -340,8 +341,8 @@ int sdtw_stream_best_two(const sdtw_stream* streams, int32_t ns, int32_t window,
  * Launch shape of later sdtw_stream_extend calls in this process (one chain
  * per lane):
  *   strip  columns per lane, 16 or 32; 0 (default) = 16.
- *   bands  waves per chunk (the row bands of sdtw_plan_set_config), 1, 2 or
- *          4; 0 (default) = 4 for at most one chunk per compute unit, 2 for
+ *   bands  waves per chunk (the row bands of sdtw_plan_set_config), 1 to 4;
+ *          0 (default) = 4 for at most one chunk per compute unit, 2 for
  *          fewer than four, else 1 (a chunk of M rows uses at most M / 65).
  * Results never depend on it.  EINVAL for other values.
  */

@@ -728,7 +728,9 @@ hipError_t launch_skew_f(int strip, int chains, int bands, int blocks, const Ali
     case (16 * 8 + 1) * 8 + 4: return launch_skew_s<F, 16, 1, 4>(blocks, a, st, stream);
     case (16 * 8 + 2) * 8 + 2: return launch_skew_s<F, 16, 2, 2>(blocks, a, st, stream);
     case (16 * 8 + 2) * 8 + 4: return launch_skew_s<F, 16, 2, 4>(blocks, a, st, stream);
+    case (16 * 8 + 1) * 8 + 3: return launch_skew_s<F, 16, 1, 3>(blocks, a, st, stream);
     case (32 * 8 + 1) * 8 + 2: return launch_skew_s<F, 32, 1, 2>(blocks, a, st, stream);
+    case (32 * 8 + 1) * 8 + 3: return launch_skew_s<F, 32, 1, 3>(blocks, a, st, stream);
     case (32 * 8 + 1) * 8 + 4: return launch_skew_s<F, 32, 1, 4>(blocks, a, st, stream);
   }
   return hipErrorInvalidValue;

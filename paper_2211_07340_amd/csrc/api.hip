@@ -509,8 +509,8 @@ int sdtw_plan_set_config(sdtw_plan plan, int strip, int chains, int bands, int w
                strip);
   SDTW_REQUIRE(chains == 0 || chains == 1 || chains == 2 || chains == 4,
                "sdtw_plan_set_config: chains %d not in {1,2,4}", chains);
-  SDTW_REQUIRE(bands == 0 || bands == 1 || bands == 2 || bands == 4,
-               "sdtw_plan_set_config: bands %d not in {1,2,4}", bands);
+  SDTW_REQUIRE(bands >= 0 && bands <= 4, "sdtw_plan_set_config: bands %d not in {1,2,3,4}",
+               bands);
   SDTW_REQUIRE(waves_per_cu >= 0 && waves_per_cu <= 32,
                "sdtw_plan_set_config: waves_per_cu %d outside [0, 32]", waves_per_cu);
   const int s2 = strip ? strip : plan->strip;
@@ -687,7 +687,7 @@ int sdtw_plan_autotune(sdtw_ref ref, sdtw_plan plan, const void* q_dev, void* co
   std::vector<TuneVal> cand;
   for (int strip : {16, 32})
     for (int chains : {1, 2})
-      for (int bands : {1, 2, 4}) {
+      for (int bands : {1, 2, 3, 4}) {
         if (!valid_skew_config(strip, chains, bands)) continue;
         if (bands > 1 && plan->max_m < bands * skew_min_m(chains)) continue;
         const int band_rows = std::max(skew_band_rows(plan->max_m, chains, bands),
@@ -863,8 +863,8 @@ int sdtw_stream_copy_row(sdtw_stream s, void* dst_dev, void* stream) {
 int sdtw_stream_set_config(int strip, int bands) {
   SDTW_REQUIRE(strip == 0 || strip == 16 || strip == 32,
                "sdtw_stream_set_config: strip %d not in {0,16,32}", strip);
-  SDTW_REQUIRE(bands == 0 || bands == 1 || bands == 2 || bands == 4,
-               "sdtw_stream_set_config: bands %d not in {0,1,2,4}", bands);
+  SDTW_REQUIRE(bands >= 0 && bands <= 4, "sdtw_stream_set_config: bands %d not in {0,1,2,3,4}",
+               bands);
   g_stream_strip.store(strip);
   g_stream_bands.store(bands);
   return SDTW_OK;

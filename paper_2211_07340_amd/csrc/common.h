@@ -34,10 +34,12 @@ inline bool valid_strip_chains(int strip, int chains) {
 }
 
 // Row bands per workgroup (waves per read): 1 for every (strip, chains)
-// above; 2 or 4 with strip 16 and 1 or 2 chains, or strip 32 and 1 chain.
+// above; 2 or 4 with strip 16 and 1 or 2 chains; 2, 3 or 4 with strip 16 or
+// 32 and 1 chain.
 inline bool valid_skew_config(int strip, int chains, int bands) {
   if (!valid_strip_chains(strip, chains)) return false;
   if (bands == 1) return true;
+  if (bands == 3) return chains == 1 && (strip == 16 || strip == 32);
   if (bands != 2 && bands != 4) return false;
   return (strip == 16 && chains <= 2) || (strip == 32 && chains == 1);
 }

@@ -135,7 +135,7 @@ def _ragged_case(seed, Ms, N, lo=-3000, hi=3000):
 
 @pytest.mark.parametrize("strip,chains,bands,waves", [
     (16, 1, 2, 2), (16, 1, 2, 8), (16, 1, 4, 4), (16, 1, 4, 16), (16, 2, 2, 4), (16, 2, 4, 8),
-    (32, 1, 2, 4), (32, 1, 4, 8)])
+    (32, 1, 2, 4), (32, 1, 4, 8), (16, 1, 3, 3), (16, 1, 3, 12), (32, 1, 3, 6)])
 def test_band_schedule_invariance(dev, strip, chains, bands, waves):
     # row bands (several waves per read): reads whose band count ranges from
     # 1 to 4, band heights at the minimum and ragged, several tiles and a
@@ -152,7 +152,8 @@ def test_band_schedule_invariance(dev, strip, chains, bands, waves):
 
 
 @pytest.mark.parametrize("strip,chains,bands", [(16, 1, 2), (16, 1, 4), (16, 2, 2), (16, 2, 4),
-                                                (32, 1, 2), (32, 1, 4)])
+                                                (32, 1, 2), (32, 1, 4), (16, 1, 3),
+                                                (32, 1, 3)])
 def test_band_boundary_diagonal_on_exact_substrings(dev, strip, chains, bands):
     # each read is an exact substring of the reference whose zero-cost
     # diagonal crosses from band g - 1 into band g exactly at a tile

@@ -105,8 +105,8 @@ PLANS = [[400, 400, 400], [70, 30, 300], [1, 64, 65, 200], [250], [65, 65, 65, 6
 
 
 @pytest.mark.parametrize("dt", ["i16", "f32"])
-@pytest.mark.parametrize("strip,bands", [(0, 0), (16, 1), (16, 2), (16, 4), (32, 1), (32, 2),
-                                         (32, 4)])
+@pytest.mark.parametrize("strip,bands", [(0, 0), (16, 1), (16, 2), (16, 3), (16, 4), (32, 1),
+                                         (32, 2), (32, 3), (32, 4)])
 def test_extend_equals_from_scratch(dev, prepared, dt, strip, bands):
     w, z, codes = prepared
     reads = chunked_reads(w, PLANS)
