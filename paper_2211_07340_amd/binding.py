@@ -58,7 +58,7 @@ def load_library():
         "sdtw_align_batch": ([p, p, p, p, p, p], C.c_int),
         "sdtw_align_one": ([p, p, i32, p, p, p], C.c_int),
         "sdtw_prepare_queries_ex": ([p, p, i32, dbl, p, p, p, p, p, p], C.c_int),
-        "sdtw_stream_set_config": ([C.c_int, C.c_int], C.c_int),
+        "sdtw_stream_set_config": ([p, C.c_int, C.c_int], C.c_int),
         "sdtw_stream_best_two": ([p, i32, i32, p, p, p, p, p], C.c_int),
         "sdtw_set_row_budget": ([i64], C.c_int),
         "sdtw_row_budget_info": ([C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)], C.c_int),
@@ -343,9 +343,11 @@ def stream_best_two(streams, window: int, stream=None):
     return bc, be, sc, se
 
 
-def set_stream_config(strip: int = 0, bands: int = 0):
-    """Launch shape of later stream_extend calls (0 = automatic)."""
-    _check(load_library().sdtw_stream_set_config(int(strip), int(bands)))
+def set_stream_config(strip: int = 0, bands: int = 0, ref: Reference | None = None):
+    """Launch shape of later stream_extend calls on streams of ``ref`` (None:
+    the process default); 0 = automatic."""
+    _check(load_library().sdtw_stream_set_config(ref.handle if ref is not None else None,
+                                                 int(strip), int(bands)))
 
 
 def row_budget_info():

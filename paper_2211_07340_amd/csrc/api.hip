@@ -24,6 +24,8 @@ struct sdtw_ref_s {
   int64_t n_pad;   // device layout length
   uint32_t* data;  // u32 biased int16 or float bits
   std::atomic<int> open_streams;
+  std::atomic<int> stream_strip{0};  // sdtw_stream_set_config for this reference (0: automatic)
+  std::atomic<int> stream_bands{0};
 };
 
 namespace sdtw {
@@ -860,13 +862,18 @@ int sdtw_stream_copy_row(sdtw_stream s, void* dst_dev, void* stream) {
                    "sdtw_stream_copy_row");
 }
 
-int sdtw_stream_set_config(int strip, int bands) {
+int sdtw_stream_set_config(sdtw_ref ref, int strip, int bands) {
   SDTW_REQUIRE(strip == 0 || strip == 16 || strip == 32,
                "sdtw_stream_set_config: strip %d not in {0,16,32}", strip);
   SDTW_REQUIRE(bands >= 0 && bands <= 4, "sdtw_stream_set_config: bands %d not in {0,1,2,3,4}",
                bands);
-  g_stream_strip.store(strip);
-  g_stream_bands.store(bands);
+  if (ref) {
+    ref->stream_strip.store(strip);
+    ref->stream_bands.store(bands);
+  } else {
+    g_stream_strip.store(strip);
+    g_stream_bands.store(bands);
+  }
   return SDTW_OK;
 }
 
@@ -905,14 +912,17 @@ int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk
   // One chain per lane.  Automatic shape: more waves per chunk the fewer
   // chunks there are (a chunk's latency shrinks with its bands while the
   // device is not full), one per chunk from four chunks per compute unit on;
-  // strip 16, whose workgroups need a third of strip 32's LDS, so that calls
-  // in flight on several HIP streams share the compute units.
+  // strip 32 for references of 2^20 columns and more (half the tiles per
+  // chunk), else 16, whose workgroups need a third of strip 32's LDS, so that
+  // short-reference calls find room beside long-reference ones.
   constexpr int kChains = 1;
   const int cus = std::max(cu_count(), 1);
-  int bands = g_stream_bands.load();
+  int bands = ref->stream_bands.load();
+  if (bands == 0) bands = g_stream_bands.load();
   if (bands == 0) bands = ns <= cus ? 4 : (ns < 4 * cus ? 2 : 1);
-  int kStrip = g_stream_strip.load();
-  if (kStrip == 0) kStrip = 16;
+  int kStrip = ref->stream_strip.load();
+  if (kStrip == 0) kStrip = g_stream_strip.load();
+  if (kStrip == 0) kStrip = ref->n >= (int64_t(1) << 20) ? 32 : 16;
   int32_t nbig = 0, max_band = 0;
   while (nbig < ns && len(order[(size_t)nbig]) >= skew_min_m(kChains)) {
     max_band = std::max(max_band, skew_band_rows((int32_t)len(order[(size_t)nbig]), kChains, bands));

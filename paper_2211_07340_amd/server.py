@@ -55,8 +55,8 @@ class ServerConfig:
     row_budget_bytes: int | None = None
     seed: int = 4004
     streams_per_target: int = 2        # HIP streams per target: launches of later ticks overlap
-    stream_strip: int = 32             # sdtw_stream_set_config strip (0: the library's choice);
-                                       # 32 halves the tiles of a long reference per chunk
+    stream_strip: int = 0              # sdtw_stream_set_config strip per target (0: the
+                                       # library's choice by reference length)
     prewarm_rows: bool = True          # open (and close) rows for every channel before serving
 
 
@@ -199,7 +199,8 @@ class ReadUntilServer:
         torch = self.torch
         cfg = self.cfg
         dev = torch.device("cuda")
-        sd.set_stream_config(cfg.stream_strip, 0)
+        for t in self.targets:
+            sd.set_stream_config(cfg.stream_strip, 0, ref=t.ref)
         if cfg.prewarm_rows and self.mode == "extend":
             self.prewarm()
         P = cfg.chunk_period_s

@@ -69,9 +69,9 @@ def test_argument_validation(lib):
     assert lib.sdtw_plan_set_config(None, 16, 2, 1, 4) == 1
     assert lib.sdtw_plan_autotune(None, None, p, p, p, 0, None) == 1
     assert lib.sdtw_plan_use_tuned(None, None, None) == 1
-    assert lib.sdtw_stream_set_config(0, 3) == 1
+    assert lib.sdtw_stream_set_config(None, 0, 5) == 1
     assert lib.sdtw_stream_best_two(None, 1, 0, p, p, p, p, None) == 1
-    assert lib.sdtw_stream_set_config(8, 0) == 1
+    assert lib.sdtw_stream_set_config(None, 8, 0) == 1
     assert lib.sdtw_free_reference(None) == 1
     assert lib.sdtw_plan_destroy(None) == 1
     assert "null" in _err(lib)
