@@ -281,6 +281,13 @@ int sdtw_set_row_budget(int64_t bytes);
 int sdtw_row_budget_info(int64_t* budget, int64_t* in_use, int64_t* cached);
 
 /*
+ * Free the rows closed streams left cached on the current device (they are
+ * kept for reuse by later sdtw_stream_open calls of the same size and do not
+ * count against the budget).  Open streams are not touched.
+ */
+int sdtw_row_pool_trim(void);
+
+/*
  * Open a stream on `ref` (its dtype applies).  SDTW_EBUDGET when the row
  * would exceed the budget (nothing allocated; retry after closing others),
  * SDTW_ENOMEM when the device allocation fails.  The reference cannot be

@@ -59,6 +59,7 @@ def load_library():
         "sdtw_align_one": ([p, p, i32, p, p, p], C.c_int),
         "sdtw_prepare_queries_ex": ([p, p, i32, dbl, p, p, p, p, p, p], C.c_int),
         "sdtw_stream_set_config": ([p, C.c_int, C.c_int], C.c_int),
+        "sdtw_row_pool_trim": ([], C.c_int),
         "sdtw_stream_best_two": ([p, i32, i32, p, p, p, p, p], C.c_int),
         "sdtw_set_row_budget": ([i64], C.c_int),
         "sdtw_row_budget_info": ([C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)], C.c_int),
@@ -348,6 +349,11 @@ def set_stream_config(strip: int = 0, bands: int = 0, ref: Reference | None = No
     the process default); 0 = automatic."""
     _check(load_library().sdtw_stream_set_config(ref.handle if ref is not None else None,
                                                  int(strip), int(bands)))
+
+
+def row_pool_trim():
+    """Free the cached rows of closed streams on the current device."""
+    _check(load_library().sdtw_row_pool_trim())
 
 
 def row_budget_info():

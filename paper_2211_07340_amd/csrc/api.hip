@@ -764,6 +764,23 @@ int sdtw_set_row_budget(int64_t bytes) {
   return SDTW_OK;
 }
 
+int sdtw_row_pool_trim(void) {
+  const int dev = current_device();
+  RowPool* pl = pool_for(dev);
+  SDTW_REQUIRE(pl, "sdtw_row_pool_trim: no current device");
+  std::lock_guard<std::mutex> g(pl->mu);
+  hipError_t first = hipSuccess;
+  for (auto& kv : pl->free_rows) {
+    for (void* row : kv.second) {
+      const hipError_t e = hipFree(row);
+      if (first == hipSuccess) first = e;
+      pl->cached -= (int64_t)kv.first;
+    }
+  }
+  pl->free_rows.clear();
+  return check_hip(first, "sdtw_row_pool_trim");
+}
+
 int sdtw_row_budget_info(int64_t* budget, int64_t* in_use, int64_t* cached) {
   RowPool* pl = pool_for(current_device());
   SDTW_REQUIRE(pl, "sdtw_row_budget_info: no current device");

@@ -253,6 +253,9 @@ def test_budget_and_state_errors(dev, prepared):
         assert ei.value.code == "EINVAL"
         for s in (a, c, o):
             s.close()
+        assert sd.row_budget_info()[1] == 0 and sd.row_budget_info()[2] > 0
+        sd.row_pool_trim()
+        assert sd.row_budget_info()[2] == 0  # cached rows freed
     finally:
         sd.set_row_budget(budget0)
     other.close()
