@@ -85,6 +85,8 @@ def parse():
     ap.add_argument("--chains", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--bands", type=int, default=0, help="waves per read (row bands): 1, 2, 4")
+    ap.add_argument("--band-rows", type=int, default=-1,
+                    help="target rows per band (0: as many bands as fit)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the plan's default launch shape instead of autotuning it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -129,8 +131,8 @@ def main():
     offs_dev = torch.from_numpy(reads.offsets).to(dev)
     plan = sd.Plan(reads.offsets, dt)
     tune_ms = None
-    if args.strip or args.chains or args.waves or args.bands:
-        plan.set_config(args.strip, args.chains, args.waves, args.bands)
+    if args.strip or args.chains or args.waves or args.bands or args.band_rows >= 0:
+        plan.set_config(args.strip, args.chains, args.waves, args.bands, args.band_rows)
     elif not args.no_autotune:
         # launch shape picked by the library's autotuner on this batch (on the
         # first 2^17 reference columns), outside the timed region

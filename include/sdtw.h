@@ -202,16 +202,24 @@ int sdtw_plan_info(sdtw_plan plan, int32_t* nq, int* dtype, int32_t* max_m);
  *           reference tiles.
  *   waves_per_cu  resident waves per compute unit for the persistent grid,
  *           1..32 (0 = keep); a multiple of bands.
+ *   band_rows  target rows per band: each read gets about M / band_rows
+ *           bands (rounded to nearest, at least 1, at most `bands` and at
+ *           most M / (64 * chains + 1)), so that reads of different lengths
+ *           finish together; 0 = as many bands as fit; -1 = keep.  Otherwise
+ *           >= 65.
  * EINVAL for values outside these sets.
  */
-int sdtw_plan_set_config(sdtw_plan plan, int strip, int chains, int bands, int waves_per_cu);
+int sdtw_plan_set_config(sdtw_plan plan, int strip, int chains, int bands, int waves_per_cu,
+                         int32_t band_rows);
 int sdtw_plan_get_config(sdtw_plan plan, int* strip, int* chains, int* bands,
-                         int* waves_per_cu);
+                         int* waves_per_cu, int32_t* band_rows);
 
 /*
  * Autotune the plan's kernel configuration on this batch: run every
  * candidate (strip 16 or 32, 1 or 2 chains, 1 to 4 bands where valid,
- * each at the waves per CU its LDS allows and at half that) once to warm up
+ * with 3 or 4 bands also band_rows targets of a half and a third of the
+ * median read, each at the waves per CU its LDS allows and at half that)
+ * once to warm up
  * and once timed with HIP events on `stream`, keep the fastest on the plan
  * and remember it for sdtw_plan_use_tuned (keyed by device, dtype, reference
  * length, number of reads, longest read and total rows).

@@ -49,9 +49,10 @@ def load_library():
         "sdtw_free_reference": ([p], C.c_int),
         "sdtw_plan_create": ([p, i32, C.c_int, C.POINTER(p)], C.c_int),
         "sdtw_plan_info": ([p, C.POINTER(i32), C.POINTER(C.c_int), C.POINTER(i32)], C.c_int),
-        "sdtw_plan_set_config": ([p, C.c_int, C.c_int, C.c_int, C.c_int], C.c_int),
+        "sdtw_plan_set_config": ([p, C.c_int, C.c_int, C.c_int, C.c_int, i32], C.c_int),
         "sdtw_plan_get_config": ([p, C.POINTER(C.c_int), C.POINTER(C.c_int),
-                                  C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
+                                  C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                  C.POINTER(i32)], C.c_int),
         "sdtw_plan_destroy": ([p], C.c_int),
         "sdtw_plan_autotune": ([p, p, p, p, p, i64, p], C.c_int),
         "sdtw_plan_use_tuned": ([p, p, C.POINTER(C.c_int)], C.c_int),
@@ -239,19 +240,19 @@ class Plan:
         return self._h
 
     def set_config(self, strip: int = 0, chains: int = 0, waves_per_cu: int = 0,
-                   bands: int = 0):
-        """sdtw_plan_set_config; 0 keeps a setting."""
+                   bands: int = 0, band_rows: int = -1):
+        """sdtw_plan_set_config; 0 (band_rows: -1) keeps a setting."""
         _check(load_library().sdtw_plan_set_config(self.handle, strip, chains, bands,
-                                                   waves_per_cu))
+                                                   waves_per_cu, band_rows))
 
     @property
     def config(self):
-        """dict(strip, chains, bands, waves_per_cu)"""
-        s, k, b, w = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        """dict(strip, chains, bands, waves_per_cu, band_rows)"""
+        s, k, b, w, r = C.c_int(), C.c_int(), C.c_int(), C.c_int(), C.c_int32()
         _check(load_library().sdtw_plan_get_config(self.handle, C.byref(s), C.byref(k),
-                                                   C.byref(b), C.byref(w)))
+                                                   C.byref(b), C.byref(w), C.byref(r)))
         return {"strip": s.value, "chains": k.value, "bands": b.value,
-                "waves_per_cu": w.value}
+                "waves_per_cu": w.value, "band_rows": r.value}
 
     def close(self):
         if self._h is not None:

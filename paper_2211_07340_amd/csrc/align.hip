@@ -224,7 +224,9 @@ __device__ __forceinline__ void load_strip(uint32_t (&dst)[W], const uint32_t* _
 // period p = G - 2g, so a slot is written (during the writer's switch steps
 // of its period t + 1) one barrier before it is read (during the reader's
 // switch steps of its period t) and rewritten only after its last read.
-// Pe = min(P, M / (64K + 1)); waves g >= Pe idle through the barriers.
+// Pe = min(P, M / (64K + 1)), or fewer when a target band height is given
+// (reads of different lengths then get bands of about the same height and
+// finish together); waves g >= Pe idle through the barriers.
 //
 // LDS layout of the query and the left-boundary column of a band, one 8-byte
 // entry per k in [0, M_g + 64K):
@@ -323,10 +325,7 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
                                                    : args.single_m);
     }
     int32_t Pe = 1;
-    if constexpr (P > 1) {
-      Pe = M / (S + 1);
-      Pe = Pe < 1 ? 1 : (Pe > P ? P : Pe);
-    }
+    if constexpr (P > 1) Pe = skew_read_bands(M, K, P, args.band_target);
     const bool active = wave < Pe;
     const bool last = wave == Pe - 1;
     const int32_t r0 = (wave * M) / Pe;

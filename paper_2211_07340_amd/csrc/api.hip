@@ -58,6 +58,7 @@ struct sdtw_plan_s {
   int strip;                      // columns per lane
   int chains;                     // most chains per lane (K) the long reads use
   int bands;                      // waves per read (row bands) of the skew kernel
+  int32_t band_rows;              // target rows per band (0: as many bands as fit)
   int waves_per_cu;               // persistent grid density (bands x workgroups per CU)
   int cus;                        // compute units of the device
 };
@@ -367,7 +368,7 @@ int sdtw_free_reference(sdtw_ref ref) {
 // run by the skew kernel with `chains` chains per lane and `bands` waves per
 // read (chains == 0: the synchronised single-wave kernel).
 struct LaunchGroup {
-  int32_t first, count, max_m, chains, bands, max_band;
+  int32_t first, count, max_m, chains, bands, max_band, band_target;
 };
 
 static std::vector<LaunchGroup> launch_groups(const sdtw_plan_s* p) {
@@ -377,16 +378,18 @@ static std::vector<LaunchGroup> launch_groups(const sdtw_plan_s* p) {
   for (int k = p->chains; k >= 1; k /= 2) {
     if (!valid_strip_chains(p->strip, k)) continue;
     const int bands = valid_skew_config(p->strip, k, p->bands) ? p->bands : 1;
+    const int32_t target = bands > 1 ? p->band_rows : 0;
     const int32_t lo = skew_min_m(k);
     const int32_t start = pos;
     int32_t max_band = 0;
     while (pos < n && p->sorted_m[pos] >= lo) {
-      max_band = std::max(max_band, skew_band_rows(p->sorted_m[pos], k, bands));
+      max_band = std::max(max_band, skew_band_rows(p->sorted_m[pos], k, bands, target));
       ++pos;
     }
-    if (pos > start) g.push_back({start, pos - start, p->sorted_m[start], k, bands, max_band});
+    if (pos > start)
+      g.push_back({start, pos - start, p->sorted_m[start], k, bands, max_band, target});
   }
-  if (pos < n) g.push_back({pos, n - pos, p->sorted_m[pos], 0, 1, 0});
+  if (pos < n) g.push_back({pos, n - pos, p->sorted_m[pos], 0, 1, 0, 0});
   return g;
 }
 
@@ -439,6 +442,7 @@ static void choose_config(sdtw_plan_s* p) {
     p->chains = 2;
     p->bands = 1;
   }
+  p->band_rows = 0;
   p->waves_per_cu = skew_waves_per_cu(p->strip, p->chains, p->bands,
                                       std::max(skew_band_rows(p->max_m, p->chains, p->bands),
                                                skew_min_m(p->chains)),
@@ -505,8 +509,12 @@ int sdtw_plan_info(sdtw_plan plan, int32_t* nq, int* dtype, int32_t* max_m) {
   return SDTW_OK;
 }
 
-int sdtw_plan_set_config(sdtw_plan plan, int strip, int chains, int bands, int waves_per_cu) {
+int sdtw_plan_set_config(sdtw_plan plan, int strip, int chains, int bands, int waves_per_cu,
+                         int32_t band_rows) {
   SDTW_REQUIRE(plan, "sdtw_plan_set_config: null plan");
+  SDTW_REQUIRE(band_rows == -1 || band_rows == 0 || band_rows >= skew_min_m(1),
+               "sdtw_plan_set_config: band_rows %d is not -1, 0 or >= %d", band_rows,
+               skew_min_m(1));
   SDTW_REQUIRE(strip == 0 || valid_strip(strip), "sdtw_plan_set_config: strip %d not in {8,16,32}",
                strip);
   SDTW_REQUIRE(chains == 0 || chains == 1 || chains == 2 || chains == 4,
@@ -534,15 +542,18 @@ int sdtw_plan_set_config(sdtw_plan plan, int strip, int chains, int bands, int w
   plan->chains = k2;
   plan->bands = b2;
   plan->waves_per_cu = w2;
+  if (band_rows >= 0) plan->band_rows = band_rows;
   return SDTW_OK;
 }
 
-int sdtw_plan_get_config(sdtw_plan plan, int* strip, int* chains, int* bands, int* waves_per_cu) {
+int sdtw_plan_get_config(sdtw_plan plan, int* strip, int* chains, int* bands, int* waves_per_cu,
+                         int32_t* band_rows) {
   SDTW_REQUIRE(plan, "sdtw_plan_get_config: null plan");
   if (strip) *strip = plan->strip;
   if (chains) *chains = plan->chains;
   if (bands) *bands = plan->bands;
   if (waves_per_cu) *waves_per_cu = plan->waves_per_cu;
+  if (band_rows) *band_rows = plan->band_rows;
   return SDTW_OK;
 }
 
@@ -602,6 +613,7 @@ static int align_batch_impl(sdtw_ref ref, sdtw_plan plan, const void* q_dev, voi
     a.nwork = g.count;
     a.max_m = g.max_m;
     a.max_band = g.max_band;
+    a.band_target = g.band_target;
     int rc;
     if (g.chains) {
       const int groups_per_cu = std::max(plan->waves_per_cu / g.bands, 1);
@@ -658,6 +670,7 @@ struct TuneKey {
 };
 struct TuneVal {
   int strip, chains, bands, waves_per_cu;
+  int32_t band_rows;
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tuned;  // best configuration per batch shape and reference length
@@ -686,24 +699,35 @@ int sdtw_plan_autotune(sdtw_ref ref, sdtw_plan plan, const void* q_dev, void* co
   // candidates: every strip / chains / bands the kernel is built for with
   // strip >= 16 and at most 2 chains, each at the resident waves per CU its
   // LDS allows and at half that
+  // and, with 3 or 4 bands, targets of a half and a third of the median read
+  // (equal band heights for reads of different lengths)
   std::vector<TuneVal> cand;
+  const int32_t median_m = plan->sorted_m[plan->sorted_m.size() / 2];
   for (int strip : {16, 32})
     for (int chains : {1, 2})
       for (int bands : {1, 2, 3, 4}) {
         if (!valid_skew_config(strip, chains, bands)) continue;
         if (bands > 1 && plan->max_m < bands * skew_min_m(chains)) continue;
-        const int band_rows = std::max(skew_band_rows(plan->max_m, chains, bands),
-                                       skew_min_m(chains));
-        const int w = skew_waves_per_cu(strip, chains, bands, band_rows, false);
-        cand.push_back({strip, chains, bands, w});
-        if (w / 2 >= bands && (w / 2) % bands == 0) cand.push_back({strip, chains, bands, w / 2});
+        std::vector<int32_t> targets = {0};
+        if (bands > 2)
+          for (int32_t t : {(median_m + 1) / 2, (median_m + 2) / 3})
+            if (t >= skew_min_m(chains)) targets.push_back(t);
+        for (int32_t target : targets) {
+          const int band_rows = std::max(skew_band_rows(plan->max_m, chains, bands, target),
+                                         skew_min_m(chains));
+          const int w = skew_waves_per_cu(strip, chains, bands, band_rows, false);
+          cand.push_back({strip, chains, bands, w, target});
+          if (w / 2 >= bands && (w / 2) % bands == 0)
+            cand.push_back({strip, chains, bands, w / 2, target});
+        }
       }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
     return set_error(SDTW_EDEVICE, "sdtw_plan_autotune: event creation failed");
   }
-  const TuneVal keep = {plan->strip, plan->chains, plan->bands, plan->waves_per_cu};
+  const TuneVal keep = {plan->strip, plan->chains, plan->bands, plan->waves_per_cu,
+                        plan->band_rows};
   TuneVal best = keep;
   float best_ms = 0.f;
   int rc = SDTW_OK;
@@ -712,6 +736,7 @@ int sdtw_plan_autotune(sdtw_ref ref, sdtw_plan plan, const void* q_dev, void* co
     plan->chains = c.chains;
     plan->bands = c.bands;
     plan->waves_per_cu = c.waves_per_cu;
+    plan->band_rows = c.band_rows;
     rc = align_batch_impl(ref, plan, q_dev, cost_dev, end_dev, st, n);  // warm-up
     if (!rc) rc = check_hip(hipEventRecord(e0, st), "sdtw_plan_autotune: record");
     if (!rc) rc = align_batch_impl(ref, plan, q_dev, cost_dev, end_dev, st, n);
@@ -731,6 +756,7 @@ int sdtw_plan_autotune(sdtw_ref ref, sdtw_plan plan, const void* q_dev, void* co
   plan->chains = best.chains;
   plan->bands = best.bands;
   plan->waves_per_cu = best.waves_per_cu;
+  plan->band_rows = best.band_rows;
   if (rc) return rc;
   std::lock_guard<std::mutex> g(g_tune_mu);
   g_tuned[tune_key(plan, ref->n)] = best;
@@ -747,6 +773,7 @@ int sdtw_plan_use_tuned(sdtw_ref ref, sdtw_plan plan, int* found) {
     plan->chains = it->second.chains;
     plan->bands = it->second.bands;
     plan->waves_per_cu = it->second.waves_per_cu;
+    plan->band_rows = it->second.band_rows;
   }
   return SDTW_OK;
 }

@@ -44,14 +44,24 @@ inline bool valid_skew_config(int strip, int chains, int bands) {
   return (strip == 16 && chains <= 2) || (strip == 32 && chains == 1);
 }
 
-// Bands a read of M rows is cut into: as many as allowed, each >= 64K + 1 rows.
-inline int32_t skew_read_bands(int32_t m, int chains, int bands) {
-  int32_t pe = m / skew_min_m(chains);
-  return pe < 1 ? 1 : (pe > bands ? bands : pe);
+// Bands a read of M rows is cut into: as many as allowed (at most `bands`,
+// each >= 64K + 1 rows) or, with a target > 0, about M / target of them
+// (rounded to nearest, at least 1), so that reads of different lengths get
+// bands of about the same height and finish together.
+__host__ __device__ inline int32_t skew_read_bands(int32_t m, int chains, int bands,
+                                                   int32_t target = 0) {
+  int32_t pe = m / (64 * chains + 1);
+  pe = pe < 1 ? 1 : (pe > bands ? bands : pe);
+  if (target > 0) {
+    int32_t t = (m + target / 2) / target;
+    t = t < 1 ? 1 : t;
+    pe = t < pe ? t : pe;
+  }
+  return pe;
 }
 // Rows of the tallest band of a read of M rows.
-inline int32_t skew_band_rows(int32_t m, int chains, int bands) {
-  const int32_t pe = skew_read_bands(m, chains, bands);
+inline int32_t skew_band_rows(int32_t m, int chains, int bands, int32_t target = 0) {
+  const int32_t pe = skew_read_bands(m, chains, bands, target);
   return (m + pe - 1) / pe;
 }
 
@@ -103,6 +113,7 @@ struct AlignArgs {
   int32_t nwork;         // entries in the work list
   int32_t max_m;         // longest read in the work list (LDS sizing)
   int32_t max_band;      // skew kernel: rows of the tallest band of any item (LDS sizing)
+  int32_t band_target;   // skew kernel: target rows per band (0: as many bands as fit)
   int32_t lds_bytes;     // skew kernel: LDS to reserve per workgroup if more than it needs
                          // (caps the workgroups a compute unit takes, spreading a short
                          // work list over every compute unit)

@@ -66,7 +66,7 @@ def test_argument_validation(lib):
     assert lib.sdtw_prepare_reference(p, 3, p, 6, 64.0, p, p, p, None) == 1  # L < k
     assert lib.sdtw_prepare_reference(p, 100, p, 6, -1.0, p, p, p, None) == 1
     assert lib.sdtw_prepare_queries(p, p, 0, 64.0, p, p, p, None) == 1
-    assert lib.sdtw_plan_set_config(None, 16, 2, 1, 4) == 1
+    assert lib.sdtw_plan_set_config(None, 16, 2, 1, 4, -1) == 1
     assert lib.sdtw_plan_autotune(None, None, p, p, p, 0, None) == 1
     assert lib.sdtw_plan_use_tuned(None, None, None) == 1
     assert lib.sdtw_stream_set_config(None, 0, 5) == 1

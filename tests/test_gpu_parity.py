@@ -42,11 +42,12 @@ def small_ref():
     return w, z, codes, qz, qc
 
 
-def gpu_batch(dev, ref_np, q_np, offs, dtype, strip=0, waves=0, chains=0, bands=0):
+def gpu_batch(dev, ref_np, q_np, offs, dtype, strip=0, waves=0, chains=0, bands=0,
+              band_rows=-1):
     ref = sd.Reference(torch.from_numpy(np.ascontiguousarray(ref_np)).to(dev))
     plan = sd.Plan(offs, dtype)
-    if strip or waves or chains or bands:
-        plan.set_config(strip, chains, waves, bands)
+    if strip or waves or chains or bands or band_rows >= 0:
+        plan.set_config(strip, chains, waves, bands, band_rows)
     cost, end = sd.align_batch(ref, plan, torch.from_numpy(np.ascontiguousarray(q_np)).to(dev))
     torch.cuda.synchronize()
     out = cost.cpu().numpy(), end.cpu().numpy()
@@ -149,6 +150,18 @@ def test_band_schedule_invariance(dev, strip, chains, bands, waves):
     zq, zoffs = synth.csr([rng.normal(size=m).astype(np.float32) for m in Ms[:12]])
     check_f32(gpu_batch(dev, zref, zq.astype(np.float32), zoffs, sd.F32, strip, waves, chains,
                         bands), zq.astype(np.float32), zoffs, zref)
+
+
+@pytest.mark.parametrize("strip,bands,band_rows", [(16, 4, 100), (32, 4, 125), (32, 3, 70),
+                                                   (16, 2, 300)])
+def test_band_row_targets(dev, strip, bands, band_rows):
+    # a target band height gives reads of different lengths different band
+    # counts (1 to `bands`) in one launch
+    Ms = [65, 100, 130, 150, 199, 260, 300, 333, 400, 450, 500, 777, 1500]
+    ref, q, offs = _ragged_case(strip + bands + band_rows, Ms, 4100)
+    note(f"band rows strip={strip} bands={bands} target={band_rows}")
+    check_i16(gpu_batch(dev, ref, q, offs, sd.I16, strip, 4 * bands, 1, bands, band_rows),
+              q, offs, ref)
 
 
 @pytest.mark.parametrize("strip,chains,bands", [(16, 1, 2), (16, 1, 4), (16, 2, 2), (16, 2, 4),
@@ -331,6 +344,7 @@ def test_autotune_keeps_results_and_is_remembered(dev, small_ref):
     cfg = sd.autotune(ref, plan, q, max_columns=4096)
     assert cfg["strip"] in (16, 32) and cfg["chains"] in (1, 2) and cfg["bands"] in (1, 2, 4)
     assert cfg["waves_per_cu"] % cfg["bands"] == 0
+    assert cfg["band_rows"] == 0 or cfg["band_rows"] >= 65
     cost, end = sd.align_batch(ref, plan, q)
     torch.cuda.synchronize()
     check_i16((cost.cpu().numpy(), end.cpu().numpy()), qc, offs, codes)
