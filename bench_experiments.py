@@ -14,7 +14,12 @@ scale    Accuracy against the fixed-point scaling factor (section 6): for
          the int16 path equals the float32 path's, and the number of values
          that saturate int16, on the 4,096-read workload (50% on-target).
 
-Usage: python bench_experiments.py latency|scale [--max-genome BASES]
+serving  The Read Until server (workload 4) against the channel count and the
+         row budget: reads/s, decision latency per target, admission waits,
+         for the 29,903-base target alone and for both targets (50/50), and
+         with a budget that holds only part of the large target's rows.
+
+Usage: python bench_experiments.py latency|scale|serving [--max-genome BASES]
 """
 from __future__ import annotations
 
@@ -142,13 +147,41 @@ def scale(args):
     fref.close()
 
 
+def serving(args):
+    os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")  # one hardware queue per HIP stream
+    import torch
+
+    import bench
+    from paper_2211_07340_amd import server as srv
+    dev = torch.device("cuda:0")
+    small = bench.serving_targets(torch, dev, large=False)
+    both = bench.serving_targets(torch, dev, large=True)
+    runs = [("29,903-base only", small, ch, 64 << 30) for ch in (512, 1024, 2048)]
+    runs += [("both targets", both, ch, 64 << 30) for ch in (64, 128, 256, 512)]
+    runs += [("both targets", both, 256, 4 << 30)]  # about 100 large-target rows
+    for name, targets, ch, budget in runs:
+        cfg = srv.ServerConfig(channels=ch, row_budget_bytes=budget)
+        server = srv.ReadUntilServer(targets, cfg, mode="extend")
+        server.calibrate()
+        r = server.run(8.0, 3.0)
+        print(json.dumps({"experiment": "serving", "targets": name, "channels": ch,
+                          "row_budget_gib": budget >> 30,
+                          **{k: r[k] for k in ("reads_per_s", "chunks_per_s", "gcups",
+                                               "decision_latency_p50_ms",
+                                               "decision_latency_p99_ms", "admission_waits",
+                                               "max_waiting_chunks", "decision_accuracy")},
+                          "per_target": r["per_target"]}), flush=True)
+    for t in small + both:
+        t.ref.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("experiment", choices=["latency", "scale"])
+    ap.add_argument("experiment", choices=["latency", "scale", "serving"])
     ap.add_argument("--max-genome", type=int, default=10_000_000)
     args = ap.parse_args()
     t0 = time.perf_counter()
-    latency(args) if args.experiment == "latency" else scale(args)
+    {"latency": latency, "scale": scale, "serving": serving}[args.experiment](args)
     print(json.dumps({"done": args.experiment, "seconds": round(time.perf_counter() - t0, 1)}),
           flush=True)
 
