@@ -36,8 +36,10 @@ sys.path.insert(0, ROOT)
 # this many hardware queues round-robin (4 by default), and two streams on one
 # queue run in order, so a short-reference batch could wait behind a
 # long-reference one.  Eight queues give every stream its own.  Read at HIP
-# initialisation, so set before torch touches the device.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+# initialisation, so set before torch touches the device (and over any
+# smaller value the environment holds).
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
 CUS, SIMDS_PER_CU, CLOCK_GHZ = 256, 4, 2.4
 # SIMD cycles per 64 cells (one wave-wide row of a strip column)

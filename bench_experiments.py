@@ -33,6 +33,7 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+import bench  # noqa: E402  (sets the hardware queue count before HIP starts)
 
 
 def _events(torch):
@@ -148,10 +149,8 @@ def scale(args):
 
 
 def serving(args):
-    os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")  # one hardware queue per HIP stream
     import torch
 
-    import bench
     from paper_2211_07340_amd import server as srv
     dev = torch.device("cuda:0")
     small = bench.serving_targets(torch, dev, large=False)

@@ -22,7 +22,8 @@ This module simulates the channels and runs the decisions through the C ABI:
   soon as one of the target's HIP streams has no batch in flight; chunks
   that arrive meanwhile wait and join the next batch.  Targets have their
   own streams, so short-reference work never waits behind long-reference
-  work;
+  work (give the process at least as many hardware queues as streams,
+  GPU_MAX_HW_QUEUES, or streams share queues and run in order);
 * decision rule (a reading; the paper only says that position and score
   feed the selection criteria): s = cost / (scale * rows), the mean
   per-event distance in z-units; keep if s <= tau, reject if rows >=
