@@ -15,7 +15,7 @@
  *
  * which is the (score, position) pair that Algorithms 1 and 2 return
  * (sections 2.3 and 4.3); the start position / warp path is not computed,
- * as in section 4.3 ("cost matrix memory optimization").
+ * as in section 4.3 (only two cost columns are kept).
  *
  * Number formats.  SDTW_I16: int16 inputs (the fixed-point scaling of
  * section 4.1 / section 4.3), exact 32-bit accumulation, int32 costs in
