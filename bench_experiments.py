@@ -18,8 +18,19 @@ serving  The Read Until server (workload 4) against the channel count and the
          row budget: reads/s, decision latency per target, admission waits,
          for the 29,903-base target alone and for both targets (50/50), and
          with a budget that holds only part of the large target's rows.
+decision The two decision rules of the server (per-event cost threshold and
+         the mapping-quality score from best and runner-up ends, section 5.2)
+         on both targets at 512 channels, with off-target reads that are
+         i.i.d. noise and, harder, pore signal of a 1,000,000-base background
+         genome: accuracy, on-target reads kept, off-target reads rejected,
+         mean events read before the decision, reads/s and latency.
+best_two The runner-up search alone (sdtw_stream_best_two) over 1 to 256
+         resident rows of the 5,000,000-base target (9,999,990 columns):
+         device time and the rate at which it reads the rows (4 bytes per
+         column per row, the bound being HBM at 8 TB/s).
 
-Usage: python bench_experiments.py latency|scale|serving [--max-genome BASES]
+Usage: python bench_experiments.py latency|scale|serving|decision|best_two
+                                   [--max-genome BASES]
 """
 from __future__ import annotations
 
@@ -174,13 +185,80 @@ def serving(args):
         t.ref.close()
 
 
+def decision(args):
+    import torch
+
+    import synth
+    from paper_2211_07340_amd import server as srv
+    dev = torch.device("cuda:0")
+    table = synth.make_level_table()
+    background = synth.make_genome(1_000_000, 1_000_003)
+    for off in args.off.split(","):
+        specs = []
+        for i, (name, L) in enumerate((("29,903-base", synth.SMALL_GENOME),
+                                       ("5,000,000-base", synth.LARGE_GENOME))):
+            genome = synth.make_genome(L, L)
+            rd = synth.simulate_reads(genome, table, np.full(512, 2000), 0.5, 4400 + i,
+                                      off_genome=background if off == "genomic" else None)
+            raws = [rd.values[rd.offsets[r]:rd.offsets[r + 1]] for r in range(512)]
+            specs.append((name, genome, table, raws, rd.on_target))
+        targets = srv.make_targets(specs, dev)
+        for rule in ("cost", "mapq"):
+            cfg = srv.ServerConfig(channels=512, row_budget_bytes=64 << 30, decision=rule)
+            server = srv.ReadUntilServer(targets, cfg, mode="extend")
+            server.calibrate()
+            r = server.run(8.0, 3.0)
+            print(json.dumps({"experiment": "decision rule", "off_target_reads": off,
+                              "rule": rule,
+                              **{k: r[k] for k in ("reads_per_s", "decision_accuracy",
+                                                   "on_target_kept", "off_target_rejected",
+                                                   "mean_events_at_decision", "tau", "q_min",
+                                                   "decision_latency_p50_ms",
+                                                   "decision_latency_p99_ms")},
+                              "per_target": r["per_target"]}), flush=True)
+        for t in targets:
+            t.ref.close()
+
+
+def best_two(args):
+    import torch
+
+    import synth
+    import paper_2211_07340_amd as sd
+    dev = torch.device("cuda:0")
+    table = synth.make_level_table()
+    genome = synth.make_genome(synth.LARGE_GENOME, synth.LARGE_GENOME)
+    _, cref, _ = sd.prepare_reference(torch.from_numpy(genome).to(dev),
+                                      torch.from_numpy(table).to(dev), synth.K, 64.0)
+    ref = sd.Reference(cref)
+    rd = synth.simulate_reads(genome, table, np.full(256, 400), 0.5, 515)
+    _, q, _ = sd.prepare_queries(torch.from_numpy(rd.values).to(dev),
+                                 torch.from_numpy(rd.offsets).to(dev), 64.0)
+    streams = [sd.Stream(ref) for _ in range(256)]
+    sd.stream_extend(streams, q, rd.offsets)
+    torch.cuda.synchronize()
+    for ns in (1, 8, 64, 256):
+        ms = _time_ms(torch, lambda: sd.stream_best_two(streams[:ns], 2000), 10)
+        gbs = ns * 4.0 * ref.n / (ms * 1e-3) / 1e9
+        print(json.dumps({"experiment": "best_two", "rows": ns, "columns": ref.n,
+                          "ms": round(ms, 4), "row_read_gb_per_s": round(gbs, 1),
+                          "hbm_fraction": round(gbs / 8000.0, 3)}), flush=True)
+    for st in streams:
+        st.close()
+    ref.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("experiment", choices=["latency", "scale", "serving"])
+    ap.add_argument("experiment",
+                    choices=["latency", "scale", "serving", "decision", "best_two"])
     ap.add_argument("--max-genome", type=int, default=10_000_000)
+    ap.add_argument("--off", default="noise,genomic",
+                    help="decision: off-target read kinds to run, in order")
     args = ap.parse_args()
     t0 = time.perf_counter()
-    {"latency": latency, "scale": scale, "serving": serving}[args.experiment](args)
+    {"latency": latency, "scale": scale, "serving": serving,
+     "decision": decision, "best_two": best_two}[args.experiment](args)
     print(json.dumps({"done": args.experiment, "seconds": round(time.perf_counter() - t0, 1)}),
           flush=True)
 

@@ -346,7 +346,11 @@ int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk
  * When no column lies outside the window, second is INT32_MAX (int16 path)
  * or +inf, at column -1.  Enqueued on `stream`; order it after the extends
  * that wrote the rows (same stream).  Closing a stream waits for this call.
- * SDTW_ESTATE if a stream has no rows yet.
+ * SDTW_ESTATE if a stream has no rows yet; EINVAL if ns times
+ * ceil(n / 16384) exceeds INT32_MAX.  Uses library-owned device scratch of
+ * 8 bytes per 16,384 columns per row: 8 MiB per call in flight, allocated
+ * by the first such call; a call that needs more reallocates, which waits
+ * for all work on the device.
  */
 int sdtw_stream_best_two(const sdtw_stream* streams, int32_t ns, int32_t window,
                          void* best_cost_dev, int32_t* best_end_dev, void* second_cost_dev,

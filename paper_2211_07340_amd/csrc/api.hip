@@ -163,6 +163,8 @@ struct DescSlot {
   StreamItem* host = nullptr;
   StreamItem* dev = nullptr;  // cap items, then one int32 work counter
   int32_t cap = 0;
+  uint64_t* part = nullptr;  // sdtw_stream_best_two: per-segment minima
+  int64_t part_cap = 0;
   std::shared_ptr<CallToken> last;
 };
 // A call takes a slot whose previous call has completed, adding slots (up to
@@ -193,6 +195,24 @@ static int ensure_slot(DescSlot& sl, int32_t n) {
                    "sdtw_stream_extend: device descriptors");
   if (rc) return rc;
   sl.cap = cap;
+  return SDTW_OK;
+}
+
+// Segment minima of sdtw_stream_best_two.  The first allocation already
+// holds 2^20 keys (8 MiB: e.g. 1,024 rows of 16 M columns), so that serving
+// loops do not regrow it: hipFree of the old buffer would wait for all work
+// on the device, including long launches on other HIP streams.
+constexpr int64_t kMinPartKeys = int64_t(1) << 20;
+static int ensure_part(DescSlot& sl, int64_t n) {
+  if (sl.part_cap >= n) return SDTW_OK;
+  const int64_t cap = std::max<int64_t>(std::max<int64_t>(n, 2 * sl.part_cap), kMinPartKeys);
+  if (sl.part) (void)hipFree(sl.part);
+  sl.part = nullptr;
+  sl.part_cap = 0;
+  int rc = check_hip(hipMalloc((void**)&sl.part, sizeof(uint64_t) * (size_t)cap),
+                     "sdtw_stream_best_two: segment minima");
+  if (rc) return rc;
+  sl.part_cap = cap;
   return SDTW_OK;
 }
 
@@ -1063,6 +1083,12 @@ int sdtw_stream_best_two(const sdtw_stream* streams, int32_t ns, int32_t window,
   int rc = acquire_slot(ring, ns, &pick, "sdtw_stream_best_two");
   if (rc) return rc;
   DescSlot& sl = *pick;
+  const int64_t nseg = best_two_segments(ref->n);
+  SDTW_REQUIRE((int64_t)ns * nseg <= (int64_t)INT32_MAX,
+               "sdtw_stream_best_two: %d rows of %lld columns exceed one launch", ns,
+               (long long)ref->n);
+  rc = ensure_part(sl, (int64_t)ns * nseg);
+  if (rc) return rc;
   for (int32_t i = 0; i < ns; ++i) {
     StreamItem& it = sl.host[i];
     it = StreamItem{};
@@ -1077,7 +1103,7 @@ int sdtw_stream_best_two(const sdtw_stream* streams, int32_t ns, int32_t window,
                                 hipMemcpyHostToDevice, st),
                  "sdtw_stream_best_two: descriptors");
   if (!rc)
-    rc = check_hip(launch_best_two(ref->dtype, sl.dev, ns, ref->n, window, best_cost_dev,
+    rc = check_hip(launch_best_two(ref->dtype, sl.dev, ns, ref->n, window, sl.part, best_cost_dev,
                                    best_end_dev, second_cost_dev, second_end_dev, st),
                    "sdtw_stream_best_two: launch");
   const int rc_ev = check_hip(hipEventRecord(tok->ev, st), "sdtw_stream_best_two: record");

@@ -137,9 +137,12 @@ size_t plain_lds_bytes(int dtype, int strip, int max_m);
 
 // ---- launchers (scores.hip) -------------------------------------------------
 // Best and runner-up ends of the resident rows items[i].acc (n columns), out
-// to index items[i].out; one workgroup per item.
+// to index items[i].out.  `part` holds ns * best_two_segments(n) keys of
+// scratch (per-segment minima), written and read on `st`.
+constexpr int64_t kBestTwoSegment = 16384;  // columns per workgroup of the first pass
+int64_t best_two_segments(int64_t n);
 hipError_t launch_best_two(int dtype, const StreamItem* items, int32_t ns, int64_t n,
-                           int32_t window, void* best_cost, int32_t* best_end,
+                           int32_t window, uint64_t* part, void* best_cost, int32_t* best_end,
                            void* second_cost, int32_t* second_end, hipStream_t st);
 int max_lds_bytes();
 

@@ -24,12 +24,22 @@ This module simulates the channels and runs the decisions through the C ABI:
   own streams, so short-reference work never waits behind long-reference
   work (give the process at least as many hardware queues as streams,
   GPU_MAX_HW_QUEUES, or streams share queues and run in order);
-* decision rule (a reading; the paper only says that position and score
-  feed the selection criteria): s = cost / (scale * rows), the mean
-  per-event distance in z-units; keep if s <= tau, reject if rows >=
-  ``max_events`` or (rows >= ``min_reject_events`` and s >= tau), else
-  continue.  tau is set per target as the midpoint of the median s of
-  on-target and off-target reads on a calibration batch with its own seed.
+* decision rules (readings; section 5.2 only says that a mapping quality
+  is computed from the mapped positions and scores and that the selection
+  criteria act on it):
+  ``decision="cost"``: s = cost / (scale * rows), the mean per-event
+  distance in z-units; keep if s <= tau, reject if rows >= ``max_events``
+  or (rows >= ``min_reject_events`` and s > tau), else continue.
+  ``decision="mapq"``: after each extension the library also returns the
+  runner-up end farther than ``mapq_window`` columns from the best
+  (sdtw_stream_best_two); q = ``mapq(best, second)``, a 0..60 score that
+  grows with the relative gap between the two costs (a read that fits one
+  locus much better than anywhere else is confidently placed); keep if
+  q >= q_min, reject if rows >= ``max_events`` or (rows >=
+  ``min_reject_events`` and q < q_min), else continue.
+  tau and q_min are set per target as the midpoint of the medians of s (or
+  q) of on-target and off-target reads' first chunks on a calibration set
+  with its own seed.
 
 ``mode="recompute"`` aligns every chunk's whole prefix from scratch instead
 (a fresh stream extended by the full prefix), for comparison.
@@ -59,6 +69,8 @@ class ServerConfig:
     stream_strip: int = 0              # sdtw_stream_set_config strip per target (0: the
                                        # library's choice by reference length)
     prewarm_rows: bool = True          # open (and close) rows for every channel before serving
+    decision: str = "cost"             # "cost" or "mapq" (see the module doc)
+    mapq_window: int = 2000            # columns around the best end excluded for the runner-up
 
 
 @dataclass
@@ -68,8 +80,10 @@ class Target:
     ref: sd.Reference                  # int16 reference (prepared on the device)
     reads: list                        # raw pA event arrays (float32), >= max_events each
     on_target: np.ndarray              # bool per pool read
-    tau: float = float("nan")          # decision threshold (z-units per event)
-    streams: list = field(default_factory=list)  # torch.cuda.Streams for this target's work
+    tau: float = float("nan")          # cost threshold (z-units per event)
+    q_min: float = float("nan")        # mapping-quality threshold (0..60)
+    streams: list = field(default_factory=list)  # HIP streams of this target's work (set
+                                                 # by the server that serves it)
 
 
 @dataclass
@@ -93,6 +107,8 @@ class _Tick:
     entries: list                      # (channel, read, arrival, rows after)
     cost: object                       # pinned host copies of the results
     end: object
+    second: object                     # pinned runner-up costs and ends ("mapq"), else None
+    second_end: object
     t_submit: float
     cells: float
     scratch: list                      # recompute mode: fresh streams to close
@@ -104,7 +120,9 @@ class ServerStats:
     kept: int = 0
     rejected: int = 0
     decided_on_target: int = 0
+    kept_on_target: int = 0
     correct: int = 0
+    decision_events: list = field(default_factory=list)
     chunks: int = 0
     cells: float = 0.0
     chunk_latency: list = field(default_factory=list)
@@ -116,6 +134,39 @@ class ServerStats:
 
 def _median(x):
     return float(np.median(np.asarray(x))) if len(x) else float("nan")
+
+
+_STREAMS: dict = {}  # device index -> HIP streams of this process, reused by every server
+
+
+def _server_streams(torch, first: int, count: int) -> list:
+    """Streams first .. first+count-1 of a per-device list that only grows.
+    Servers and targets created later reuse them: a HIP stream created after
+    GPU_MAX_HW_QUEUES others shares a hardware queue with an older one, and
+    the work of streams on one queue runs in order, so fresh streams for
+    every new server would serialise batches that should overlap."""
+    pool = _STREAMS.setdefault(torch.cuda.current_device(), [])
+    while len(pool) < first + count:
+        pool.append(torch.cuda.Stream())
+    return pool[first:first + count]
+
+
+MAPQ_MAX = 60
+
+
+def mapq(best, second):
+    """Mapping-quality-like score from the best and runner-up alignment
+    costs (non-negative; runner-up >= best): round(60 (second - best) /
+    second), 0 when both are 0 (every locus fits perfectly: no information),
+    60 when there is no runner-up (second = inf or the int32 maximum).
+    Scale-free: the same for int16 codes and float32 values of one read."""
+    b = np.asarray(best, dtype=np.float64)
+    s = np.asarray(second, dtype=np.float64)
+    none = ~np.isfinite(s) | (s >= np.iinfo(np.int32).max)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        g = np.where(s > 0, (s - b) / np.where(s > 0, s, 1.0), 0.0)
+    q = np.floor(MAPQ_MAX * np.clip(g, 0.0, 1.0) + 0.5)
+    return np.where(none, MAPQ_MAX, q).astype(np.int64)
 
 
 class ReadUntilServer:
@@ -130,38 +181,55 @@ class ReadUntilServer:
         self.cfg = cfg or ServerConfig()
         if mode not in ("extend", "recompute"):
             raise ValueError("mode must be 'extend' or 'recompute'")
+        if self.cfg.decision not in ("cost", "mapq"):
+            raise ValueError("decision must be 'cost' or 'mapq'")
         self.mode = mode
         self.rng = np.random.default_rng(self.cfg.seed)
-        for t in self.targets:
-            while len(t.streams) < max(1, self.cfg.streams_per_target):
-                t.streams.append(torch.cuda.Stream())
+        k = max(1, self.cfg.streams_per_target)
+        for i, t in enumerate(self.targets):
+            t.streams = _server_streams(torch, i * k, k)
         if self.cfg.row_budget_bytes is not None:
             sd.set_row_budget(self.cfg.row_budget_bytes)
 
     # ------------------------------------------------------------------
-    def calibrate(self, n_each: int = 128, seed: int = 77):
-        """Set each target's tau from reads of its pool with another seed."""
+    def calibrate(self, n_each: int = 128, seed: int = 77, group: int = 32):
+        """Set each target's tau and q_min from the first chunks of reads of
+        its pool drawn with another seed (aligned as one-chunk streams,
+        ``group`` at a time, so the rows stay within a small budget)."""
         torch = self.torch
         rng = np.random.default_rng(seed)
         M = self.cfg.chunk_events
+        dev = torch.device("cuda")
         for t in self.targets:
             on_idx = np.nonzero(t.on_target)[0]
             off_idx = np.nonzero(~t.on_target)[0]
             pick = np.concatenate([rng.choice(on_idx, min(n_each, on_idx.size), replace=False),
                                    rng.choice(off_idx, min(n_each, off_idx.size), replace=False)])
-            raw = np.concatenate([t.reads[i][:M] for i in pick]).astype(np.float32)
-            offs = np.arange(pick.size + 1, dtype=np.int64) * M
-            dev = torch.device("cuda")
-            _, codes, _ = sd.prepare_queries(torch.from_numpy(raw).to(dev),
-                                             torch.from_numpy(offs).to(dev), self.cfg.scale)
-            plan = sd.Plan(offs, sd.I16)
-            cost, _ = sd.align_batch(t.ref, plan, codes)
-            torch.cuda.synchronize()
-            s = cost.cpu().numpy().astype(np.float64) / (self.cfg.scale * M)
+            cost, second = [], []
+            for g0 in range(0, pick.size, group):
+                sub = pick[g0:g0 + group]
+                raw = np.concatenate([t.reads[i][:M] for i in sub]).astype(np.float32)
+                offs = np.arange(sub.size + 1, dtype=np.int64) * M
+                _, codes, _ = sd.prepare_queries(torch.from_numpy(raw).to(dev),
+                                                 torch.from_numpy(offs).to(dev), self.cfg.scale)
+                streams = [sd.Stream(t.ref) for _ in sub]
+                try:
+                    c, _ = sd.stream_extend(streams, codes, offs)
+                    _, _, c2, _ = sd.stream_best_two(streams, self.cfg.mapq_window)
+                    cost.append(c.cpu().numpy())
+                    second.append(c2.cpu().numpy())
+                finally:
+                    torch.cuda.synchronize()
+                    for st in streams:
+                        st.close()
+            cost = np.concatenate(cost).astype(np.float64)
+            second = np.concatenate(second).astype(np.float64)
             on = t.on_target[pick]
+            s = cost / (self.cfg.scale * M)
+            q = mapq(cost, second)
             t.tau = 0.5 * (_median(s[on]) + _median(s[~on]))
-            plan.close()
-        return {t.name: t.tau for t in self.targets}
+            t.q_min = 0.5 * (_median(q[on]) + _median(q[~on]))
+        return {t.name: {"tau": t.tau, "q_min": t.q_min} for t in self.targets}
 
     # ------------------------------------------------------------------
     def _new_read(self, now: float) -> _Read:
@@ -170,12 +238,16 @@ class ReadUntilServer:
         pi = int(self.rng.integers(0, len(t.reads)))
         return _Read(ti, pi, t.reads[pi], now, bool(t.on_target[pi]))
 
-    def _decide(self, rd: _Read, cost: float):
-        s = cost / (self.cfg.scale * rd.rows)
-        tau = self.targets[rd.target].tau
-        if s <= tau:
+    def _decide(self, rd: _Read, cost: float, second: float | None = None):
+        """"keep", "reject" or None (sequence another chunk)."""
+        t = self.targets[rd.target]
+        if self.cfg.decision == "mapq":
+            good = bool(mapq(cost, second) >= t.q_min)
+        else:
+            good = cost / (self.cfg.scale * rd.rows) <= t.tau
+        if good:
             return "keep"
-        if rd.rows >= self.cfg.max_events or (rd.rows >= self.cfg.min_reject_events and s >= tau):
+        if rd.rows >= self.cfg.max_events or rd.rows >= self.cfg.min_reject_events:
             return "reject"
         return None
 
@@ -234,6 +306,8 @@ class ReadUntilServer:
                 tk.event.synchronize()
                 costs = tk.cost.numpy()  # pinned host copies, complete with the event
                 ends = tk.end.numpy()
+                seconds = None if tk.second is None else tk.second.numpy()
+                second_ends = None if tk.second_end is None else tk.second_end.numpy()
                 timed("results", th)
                 th = time.perf_counter()
                 for s in tk.scratch:
@@ -247,10 +321,12 @@ class ReadUntilServer:
                     if in_window:
                         stats.chunks += 1
                         stats.chunk_latency.append(now - arr)
+                    c2 = None if seconds is None else float(seconds[k])
                     if self.record is not None:
                         self.record.append((rd.target, rd.pool_idx, rows, int(costs[k]),
-                                            int(ends[k])))
-                    verdict = self._decide(rd, float(costs[k]))
+                                            int(ends[k]), None if c2 is None else int(c2),
+                                            None if second_ends is None else int(second_ends[k])))
+                    verdict = self._decide(rd, float(costs[k]), c2)
                     if verdict is None:  # the read's next chunk
                         heapq.heappush(arrivals, (rd.start + (rd.chunks_done + 1) * P, c))
                         continue
@@ -261,6 +337,8 @@ class ReadUntilServer:
                         stats.kept += verdict == "keep"
                         stats.rejected += verdict == "reject"
                         stats.decided_on_target += rd.on
+                        stats.kept_on_target += rd.on and verdict == "keep"
+                        stats.decision_events.append(rd.rows)
                         stats.correct += (verdict == "keep") == rd.on
                     if rd.handle is not None:
                         th = time.perf_counter()
@@ -328,7 +406,14 @@ class ReadUntilServer:
             "decisions": stats.decisions,
             "kept": stats.kept,
             "rejected": stats.rejected,
+            "decision": cfg.decision,
             "decision_accuracy": round(stats.correct / max(stats.decisions, 1), 4),
+            "on_target_kept": round(stats.kept_on_target / max(stats.decided_on_target, 1), 4),
+            "off_target_rejected": round(
+                (stats.rejected - (stats.decided_on_target - stats.kept_on_target))
+                / max(stats.decisions - stats.decided_on_target, 1), 4),
+            "mean_events_at_decision": round(float(np.mean(stats.decision_events)), 1)
+            if stats.decision_events else None,
             "chunks_per_s": round(stats.chunks / duration_s, 1),
             "gcups": round(stats.cells / duration_s / 1e9, 1),
             "decision_latency_p50_ms": pct(lat, 50),
@@ -338,6 +423,7 @@ class ReadUntilServer:
             "admission_waits": stats.admission_waits,
             "max_waiting_chunks": stats.max_queue,
             "tau": {t.name: round(t.tau, 4) for t in self.targets},
+            "q_min": {t.name: round(t.q_min, 2) for t in self.targets},
             "host_loop_ms": {k: {"total": round(v[0] * 1e3, 1), "max": round(v[1] * 1e3, 2),
                                  "calls": v[2]} for k, v in host.items()},
             "per_target": {
@@ -415,13 +501,19 @@ class ReadUntilServer:
                             time.sleep(0.001)
                 handles = scratch
             cost, end = sd.stream_extend(handles, codes, offs_np, stream=hs)
+            pinned = [cost, end]
+            if cfg.decision == "mapq":
+                _, _, c2, e2 = sd.stream_best_two(handles, cfg.mapq_window, stream=hs)
+                pinned += [c2, e2]
             # results to pinned host memory on the same stream: the event then
             # marks them readable and harvesting never issues a copy (a copy
             # to pageable memory could wait for other streams' work)
-            cost_h = torch.empty(cost.shape, dtype=cost.dtype, pin_memory=True)
-            end_h = torch.empty(end.shape, dtype=end.dtype, pin_memory=True)
-            cost_h.copy_(cost, non_blocking=True)
-            end_h.copy_(end, non_blocking=True)
+            host = []
+            for x in pinned:
+                h = torch.empty(x.shape, dtype=x.dtype, pin_memory=True)
+                h.copy_(x, non_blocking=True)
+                host.append(h)
+            host += [None] * (4 - len(host))
             ev = torch.cuda.Event()
             ev.record(hs)
         out = []
@@ -429,7 +521,8 @@ class ReadUntilServer:
             rd.chunks_done += 1
             rd.rows = rd.chunks_done * E
             out.append((c, rd, arr, rd.rows))
-        inflight.append(_Tick(ev, ti, slot, out, cost_h, end_h, time.perf_counter(),
+        inflight.append(_Tick(ev, ti, slot, out, host[0], host[1], host[2], host[3],
+                              time.perf_counter(),
                               float(sum(lens)) * t.ref.n, scratch))
 
 

@@ -12,7 +12,9 @@ would hand to the method, in raw units.
   strand and a start, walks the strand's bases 5'->3' and emits the pore
   model's level of each successive 6-mer 1, 2 or 3 times (uniform), each
   emission with additive N(0, 0.3 x 12 pA) noise.  An off-target read is
-  i.i.d. N(90, 12) pA.  Lengths follow the workload.
+  i.i.d. N(90, 12) pA, or (``off_genome``) the same pore simulation run on
+  another genome, the harder case of reads from a background organism.
+  Lengths follow the workload.
 
 The sizes mirror the paper's workloads (Table 2: the 29,903-base SARS-CoV-2
 genome and 250-event queries, section 4.1), which stand in for the missing
@@ -80,10 +82,31 @@ class Reads:
         return self.offsets.size - 1
 
 
+def _genomic_events(genome: np.ndarray, table: np.ndarray, M: int, k: int,
+                    noise_sd: float, rng) -> tuple[np.ndarray, int, int, int]:
+    """M events of a random strand and start of ``genome``: (events, strand,
+    start, k-mers emitted - 1)."""
+    nk = genome.size - k + 1
+    s = int(rng.integers(0, 2))
+    p = int(rng.integers(0, nk - M + 1))  # M k-mers always fit
+    reps = rng.integers(1, 4, size=M)
+    strand_bases = genome if s == 0 else (3 - genome[::-1]).astype(np.uint8)
+    levels = _pore_current(strand_bases[p:p + M + k - 1], table, k)
+    ev = np.repeat(levels, reps)[:M]
+    ev = ev + rng.normal(0.0, noise_sd, size=M)
+    used = int(np.searchsorted(np.cumsum(reps), M))
+    return ev.astype(np.float32), s, p, used
+
+
 def simulate_reads(genome: np.ndarray, table: np.ndarray, lengths,
                    frac_on: float, seed: int, k: int = K,
-                   noise_sd: float = NOISE_SD_PA) -> Reads:
-    """Raw event streams for reads of the given lengths (see module doc)."""
+                   noise_sd: float = NOISE_SD_PA,
+                   off_genome: np.ndarray | None = None) -> Reads:
+    """Raw event streams for reads of the given lengths (see module doc).
+
+    ``off_genome``: off-target reads are drawn from this other genome the
+    way on-target reads are drawn from ``genome`` (pore signal of a random
+    strand and start), instead of i.i.d. N(90, 12) pA values."""
     rng = np.random.default_rng(seed)
     lengths = np.asarray(lengths, dtype=np.int64)
     nq = lengths.size
@@ -94,25 +117,19 @@ def simulate_reads(genome: np.ndarray, table: np.ndarray, lengths,
     strand = np.full(nq, -1, dtype=np.int8)
     start = np.full(nq, -1, dtype=np.int64)
     end_true = np.full(nq, -1, dtype=np.int64)
-    L = genome.size
-    rev = (3 - genome[::-1]).astype(np.uint8)  # complement strand read 5'->3'
-    nk = L - k + 1
+    nk = genome.size - k + 1
+    nk_off = -1 if off_genome is None else off_genome.size - k + 1
     for r in range(nq):
         M = int(lengths[r])
         a, b = int(offsets[r]), int(offsets[r + 1])
         if on[r] and nk >= M:
-            s = int(rng.integers(0, 2))
-            p = int(rng.integers(0, nk - M + 1))  # M k-mers always fit
-            reps = rng.integers(1, 4, size=M)
-            strand_bases = genome if s == 0 else rev
-            levels = _pore_current(strand_bases[p:p + M + k - 1], table, k)
-            ev = np.repeat(levels, reps)[:M]
-            ev = ev + rng.normal(0.0, noise_sd, size=M)
-            values[a:b] = ev.astype(np.float32)
+            values[a:b], s, p, used = _genomic_events(genome, table, M, k, noise_sd, rng)
             strand[r] = s
             start[r] = p
-            used = int(np.searchsorted(np.cumsum(reps), M))  # k-mers emitted - 1
             end_true[r] = s * nk + p + used
+        elif nk_off >= M:
+            on[r] = False
+            values[a:b] = _genomic_events(off_genome, table, M, k, noise_sd, rng)[0]
         else:
             on[r] = False
             values[a:b] = rng.normal(LEVEL_MEAN_PA, LEVEL_SD_PA, size=M).astype(np.float32)

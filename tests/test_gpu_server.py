@@ -5,7 +5,10 @@ Two targets are served at once, as in the serving workload: the 29,903-base
 genome and a 600,000-base one (1.2 M columns, past the 2^20 columns from
 which streams switch to strip 32), so that chunks of both launch shapes
 share the device.  A seeded sample of up to 32 served results per target is
-checked against the oracle.
+checked against the oracle.  Under the mapping-quality rule the server also
+serves the runner-up end of every resident row; a sample of those is checked
+against the oracle's last row (fewer on the large target, whose rows cost
+the oracle seconds each).
 """
 import numpy as np
 import pytest
@@ -19,7 +22,14 @@ torch = pytest.importorskip("torch")
 sd = pytest.importorskip("paper_2211_07340_amd")
 
 
-def test_served_results_match_oracle():
+def _prefix_codes(raw, rows):
+    mean, sdv = oracle.zstats(raw[:400])
+    q, _ = oracle.quantize(oracle.zapply(raw[:rows], mean, sdv), 64.0)
+    return q
+
+
+@pytest.mark.parametrize("decision", ["cost", "mapq"])
+def test_served_results_match_oracle(decision):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2211_07340_amd import server as srv
@@ -38,24 +48,31 @@ def test_served_results_match_oracle():
         codes_of.append(codes)
         raws_of.append(raws)
     rec = []
-    server = srv.ReadUntilServer(targets, srv.ServerConfig(channels=32), record=rec)
+    cfg = srv.ServerConfig(channels=32, decision=decision, mapq_window=700)
+    server = srv.ReadUntilServer(targets, cfg, record=rec)
     server.calibrate(n_each=16)
     res = server.run(3.0, 0.5)
+    print(decision, {k: res[k] for k in ("decisions", "decision_accuracy", "q_min", "tau")},
+          flush=True)
     assert res["decisions"] > 20 and res["decision_accuracy"] > 0.9, res
     rng = np.random.default_rng(0)
     for t in range(2):
         mine = [r for r in rec if r[0] == t]
         assert mine, f"nothing served for target {t}"
         pick = [mine[i] for i in rng.choice(len(mine), min(32, len(mine)), replace=False)]
-        qs = []
-        for _, pi, rows, _, _ in pick:
-            raw = raws_of[t][pi]
-            mean, sdv = oracle.zstats(raw[:400])
-            q, _ = oracle.quantize(oracle.zapply(raw[:rows], mean, sdv), 64.0)
-            qs.append(q)
+        qs = [_prefix_codes(raws_of[t][r[1]], r[2]) for r in pick]
         q, offs = synth.csr(qs)
         want_c, want_e, _ = oracle.batch(oracle.I64, q.astype(np.int16), offs, codes_of[t])
-        got = [(c, e) for (_, _, _, c, e) in pick]
+        got = [(r[3], r[4]) for r in pick]
         assert got == list(zip(want_c.astype(np.int64).tolist(), want_e.tolist())), t
+        if decision != "mapq":
+            assert all(r[5] is None for r in pick)
+            continue
+        for r, x in list(zip(pick, qs))[:8 if t == 0 else 2]:
+            _, _, row = oracle.sdtw_i64(x, codes_of[t], lastrow=True)
+            b, jb, s2, j2 = oracle.best_two(row, 700)
+            assert (r[3], r[4]) == (int(b), jb)
+            want = (np.iinfo(np.int32).max, -1) if j2 < 0 else (int(s2), j2)
+            assert (r[5], r[6]) == want, (t, r)
     for t in targets:
         t.ref.close()

@@ -175,6 +175,34 @@ def test_best_two_matches_oracle(dev, prepared, dt):
     ref.close()
 
 
+@pytest.mark.parametrize("dt", ["i16", "f32"])
+def test_best_two_segment_edges(dev, dt):
+    # a one-event read makes the last row |x - y_j| exactly, so the row can
+    # be planted: minima on both sides of the first-pass segment edges
+    # (16,384 columns), ties across an edge, and windows that end exactly on
+    # a planted column or one past it
+    n = 3 * 16384 + 77
+    ref_np = np.full(n, 100, np.int16)
+    for c, v in ((16383, 5), (16384, 5), (16390, 6), (32767, 7), (32768, 7), (40000, 8),
+                 (0, 9), (n - 1, 10)):
+        ref_np[c] = v
+    x = np.zeros(1, np.int16)
+    if dt == "f32":
+        ref_np, x = ref_np.astype(np.float32), x.astype(np.float32)
+    ref = sd.Reference(torch.from_numpy(ref_np).to(dev))
+    st = sd.Stream(ref)
+    sd.stream_extend([st], torch.from_numpy(x).to(dev), np.array([0, 1], np.int64))
+    row = np.abs(ref_np.astype(np.int64))
+    for window in (0, 1, 6, 7, 16382, 16383, 16384, 16385, 23616, 23617, 32844, 32845, n):
+        bc, be, sc, se = [t.cpu().numpy() for t in sd.stream_best_two([st], window)]
+        want = oracle.best_two(row, window)
+        got = (int(bc[0]), int(be[0]), float("inf") if se[0] < 0 else int(sc[0]), int(se[0]))
+        assert got == (int(want[0]), want[1], want[2] if want[3] < 0 else int(want[2]),
+                       want[3]), window
+    st.close()
+    ref.close()
+
+
 def test_extend_ragged_reference(dev):
     rng = np.random.default_rng(4)
     ref = rng.integers(-3000, 3000, size=3001).astype(np.int16)
