@@ -6,9 +6,10 @@ latency  Single-query sDTW latency against reference length (the paper's
          10^7 bases.  Reported per length: the one-wave synchronised kernel
          launched for the read alone (sdtw_align_one), the batched engine
          with the read as a one-read batch at its fastest launch shape
-         (bands of rows over up to four waves), and the paper's accelerator
-         cycle model, N + 249 cycles at 100 MHz for 250 processing elements
-         (section 4.3), as context.
+         (bands of rows over up to four waves), the whole-device row scan
+         (sdtw_align_one_wide) at its automatic and at each tile width, and
+         the paper's accelerator cycle model, N + 249 cycles at 100 MHz for
+         250 processing elements (section 4.3), as context.
 scale    Accuracy against the fixed-point scaling factor (section 6): for
          scales 2, 4, ..., 256, the percentage of reads whose end position on
          the int16 path equals the float32 path's, and the number of values
@@ -96,11 +97,17 @@ def latency(args):
             ms = _time_ms(torch, lambda: sd.align_batch(ref, plan, q), reps)
             if best is None or ms < best[0]:
                 best = (ms, strip, bands)
+        wide = {}
+        for cols in (8, 16, 32, 64, 0):
+            wide[cols] = _time_ms(torch, lambda: sd.align_one_wide(ref, q, cols=cols), reps)
         c1, e1 = sd.align_one(ref, q)
         plan.set_config(strip=best[1], chains=1, bands=best[2], waves_per_cu=4 * best[2])
         c2, e2 = sd.align_batch(ref, plan, q)
+        c3, e3 = sd.align_one_wide(ref, q)
         torch.cuda.synchronize()
         assert (int(c1.item()), int(e1.item())) == (int(c2.item()), int(e2.item()))
+        assert (int(c1.item()), int(e1.item())) == (int(c3.item()), int(e3.item()))
+        wbest = min((v, k) for k, v in wide.items() if k)
         cells = 250.0 * N
         fpga_ms = (N + 249) / 100e6 * 1e3
         print(json.dumps({
@@ -109,6 +116,9 @@ def latency(args):
             "one_wave_ms": round(one, 4), "one_wave_gcups": round(cells / one / 1e6, 2),
             "banded_ms": round(best[0], 4), "banded_gcups": round(cells / best[0] / 1e6, 2),
             "banded_shape": {"strip": best[1], "bands": best[2]},
+            "row_scan_ms": round(wide[0], 4), "row_scan_gcups": round(cells / wide[0] / 1e6, 2),
+            "row_scan_best_ms": round(wbest[0], 4), "row_scan_best_cols": wbest[1],
+            "row_scan_ms_by_cols": {str(k): round(v, 4) for k, v in wide.items() if k},
             "paper_accelerator_model_ms": round(fpga_ms, 4),
             "end": int(e1.item())}), flush=True)
         plan.close()

@@ -266,6 +266,28 @@ int sdtw_align_batch(sdtw_ref ref, sdtw_plan plan, const void* q_dev,
 int sdtw_align_one(sdtw_ref ref, const void* q_dev, int32_t M, void* cost_dev,
                    int32_t* end_dev, void* stream);
 
+/*
+ * One read spread over every compute unit (int16 references only): each of
+ * the M rows of Eq. 1 is computed as a prefix scan over the N columns (a row
+ * of the recurrence is a composition of maps x -> min(a, x + d), section 4.3
+ * computes the same cells as an oblique wavefront), with tiles of 256 x
+ * `cols` columns that pass their boundary values to the right through
+ * device-memory flags.  Results equal sdtw_align_one's bit for bit; the
+ * latency no longer grows with N / (columns of one workgroup).
+ *   q_dev  M int16 values; 1 <= M <= SDTW_MAX_QUERY.
+ *   cols   columns per thread, 8, 16, 32 or 64; 0 = the fewest that cut the
+ *          reference into at most 64 tiles, else into at most 256, else 64
+ *          (the fastest choice measured for each reference length).
+ *   cost_dev  out int32[1]; end_dev out int32[1] (0-based column).
+ * Only kernels are enqueued.  Uses library-owned device scratch of 8 bytes
+ * per tile per row (8 MiB per call in flight unless more is needed).  If a
+ * tile waits for its left neighbour for about a second (a defect; never in
+ * normal operation) every wait ends and cost and end are -1.
+ * EINVAL for a float32 reference.
+ */
+int sdtw_align_one_wide(sdtw_ref ref, const void* q_dev, int32_t M, int cols, void* cost_dev,
+                        int32_t* end_dev, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Streaming extension (Read Until: section 2.2 rejection before most of a   */
 /* read is sequenced; section 4.1 reads arrive as the sequencer produces     */

@@ -58,6 +58,7 @@ def load_library():
         "sdtw_plan_use_tuned": ([p, p, C.POINTER(C.c_int)], C.c_int),
         "sdtw_align_batch": ([p, p, p, p, p, p], C.c_int),
         "sdtw_align_one": ([p, p, i32, p, p, p], C.c_int),
+        "sdtw_align_one_wide": ([p, p, i32, C.c_int, p, p, p], C.c_int),
         "sdtw_prepare_queries_ex": ([p, p, i32, dbl, p, p, p, p, p, p], C.c_int),
         "sdtw_stream_set_config": ([p, C.c_int, C.c_int], C.c_int),
         "sdtw_row_pool_trim": ([], C.c_int),
@@ -314,6 +315,16 @@ def align_one(ref: Reference, q, cost=None, end=None, stream=None):
     cost, end = _outputs(1, ref.dtype, q.device, cost, end)
     _check(load_library().sdtw_align_one(ref.handle, _dev(q, qdt, "q"), q.numel(), _dev(cost),
                                          _dev(end, torch.int32, "end"), _stream(stream)))
+    return cost, end
+
+
+def align_one_wide(ref: Reference, q, cols: int = 0, cost=None, end=None, stream=None):
+    """sdtw_align_one_wide (one int16 read over every compute unit)."""
+    torch = _torch()
+    cost, end = _outputs(1, ref.dtype, q.device, cost, end)
+    _check(load_library().sdtw_align_one_wide(ref.handle, _dev(q, torch.int16, "q"), q.numel(),
+                                              int(cols), _dev(cost),
+                                              _dev(end, torch.int32, "end"), _stream(stream)))
     return cost, end
 
 

@@ -673,6 +673,40 @@ int sdtw_align_one(sdtw_ref ref, const void* q_dev, int32_t M, void* cost_dev, i
                    "sdtw_align_one: launch");
 }
 
+int sdtw_align_one_wide(sdtw_ref ref, const void* q_dev, int32_t M, int cols, void* cost_dev,
+                        int32_t* end_dev, void* stream) {
+  SDTW_REQUIRE(ref, "sdtw_align_one_wide: null reference");
+  SDTW_REQUIRE(q_dev && cost_dev && end_dev, "sdtw_align_one_wide: null device pointer");
+  SDTW_REQUIRE(ref->dtype == SDTW_I16, "sdtw_align_one_wide: int16 references only");
+  SDTW_REQUIRE(M >= 1 && M <= SDTW_MAX_QUERY, "sdtw_align_one_wide: M=%d outside [1, %d]", M,
+               SDTW_MAX_QUERY);
+  SDTW_REQUIRE(cols == 0 || cols == 8 || cols == 16 || cols == 32 || cols == 64,
+               "sdtw_align_one_wide: cols=%d not in {0, 8, 16, 32, 64}", cols);
+  if (int rc = require_device(ref->device, "sdtw_align_one_wide")) return rc;
+  if (cols == 0) cols = wide_pick_cols(ref->n, ref->device);
+  SDTW_REQUIRE(wide_tiles(ref->n, cols) <= (int64_t)INT32_MAX,
+               "sdtw_align_one_wide: reference too long for %d columns per thread", cols);
+  const int dev = ref->device;
+  DescRing& ring = g_ring[dev >= 0 && dev < kMaxDevices ? dev : 0];
+  std::lock_guard<std::mutex> g(ring.mu);
+  DescSlot* pick = nullptr;
+  int rc = acquire_slot(ring, 1, &pick, "sdtw_align_one_wide");
+  if (rc) return rc;
+  DescSlot& sl = *pick;
+  rc = ensure_part(sl, wide_scratch_words(ref->n, M, cols));
+  if (rc) return rc;
+  auto tok = std::make_shared<CallToken>();
+  tok->ev = event_get();
+  if (!tok->ev) return set_error(SDTW_EDEVICE, "sdtw_align_one_wide: event creation failed");
+  hipStream_t st = (hipStream_t)stream;
+  rc = check_hip(launch_align_wide(ref->data, ref->n, (const int16_t*)q_dev, M, cols, sl.part,
+                                   (int32_t*)cost_dev, end_dev, st),
+                 "sdtw_align_one_wide: launch");
+  const int rc_ev = check_hip(hipEventRecord(tok->ev, st), "sdtw_align_one_wide: record");
+  if (!rc_ev) sl.last = tok;
+  return rc ? rc : rc_ev;
+}
+
 // ---------------------------------------------------------------------------
 // autotuning
 // ---------------------------------------------------------------------------

@@ -146,4 +146,16 @@ hipError_t launch_best_two(int dtype, const StreamItem* items, int32_t ns, int64
                            void* second_cost, int32_t* second_end, hipStream_t st);
 int max_lds_bytes();
 
+// ---- launchers (wide.hip) ---------------------------------------------------
+// One int16 query over every compute unit: row scans with look-back between
+// tiles of 256 * cols columns (cols in {8, 16, 32, 64}).  `scratch` holds
+// wide_scratch_words(n, m, cols) 64-bit words, used only by this launch
+// (cleared by it, in order on `st`).
+int64_t wide_tiles(int64_t n, int cols);
+int64_t wide_scratch_words(int64_t n, int32_t m, int cols);
+int wide_pick_cols(int64_t n, int device);  // columns per thread for sdtw_align_one_wide(cols=0)
+hipError_t launch_align_wide(const uint32_t* ref, int64_t n, const int16_t* q, int32_t m,
+                             int cols, uint64_t* scratch, int32_t* cost, int32_t* end,
+                             hipStream_t st);
+
 }  // namespace sdtw

@@ -60,6 +60,8 @@ def test_argument_validation(lib):
     p = C.c_void_p(1)
     assert lib.sdtw_align_batch(None, None, p, p, p, None) == 1
     assert lib.sdtw_align_one(None, p, 5, p, p, None) == 1
+    assert lib.sdtw_align_one_wide(None, p, 5, 0, p, p, None) == 1
+    assert lib.sdtw_align_one_wide(p, None, 5, 0, p, p, None) == 1
     assert lib.sdtw_load_reference(None, 10, 1, 0, None, C.byref(C.c_void_p())) == 1
     assert lib.sdtw_load_reference(p, 0, 1, 0, None, C.byref(C.c_void_p())) == 1
     assert lib.sdtw_load_reference(p, 10, 9, 0, None, C.byref(C.c_void_p())) == 1
