@@ -1,0 +1,160 @@
+"""CPU model of the whole-device single-query scheme (sdtw_align_one_wide),
+checked against the oracle: each row as a scan of maps x -> min(a, x + d)
+over column tiles, per-thread strips, a two-level look-back (tiles within a
+group, then group maps) over flags that appear in random orders, and the
+saturated sums of the look-back.  Small tiles, groups and windows stand in
+for the kernel's 256 x C columns, 64-tile groups and 64-lane windows, so
+that every path is taken on small inputs.  No GPU.
+"""
+import numpy as np
+import pytest
+
+import oracle
+
+INF = 1 << 31
+IDN = (INF, 0)
+
+
+def comp(f, g, cap=None):
+    """f, then g; with cap, the summed distances saturate there."""
+    d = f[1] + g[1]
+    return (min(g[0], f[0] + g[1]), d if cap is None else min(d, cap))
+
+
+def look_back(t, agg, inc, gag, GT, GW, rng, cap):
+    """x entering tile t, or None while a flag it needs is missing."""
+    def seen(p):  # an inc flag may be published but not yet visible
+        return p in inc and (p == 0 or rng.random() < 0.6)
+    if t == 0:
+        return INF
+    first = t - t % GT
+    closer = t - first == GT - 1
+    acc = IDN
+    if t > first:
+        lanes = [t - 1 - k for k in range(GT) if t - 1 - k >= first]
+        kn = next((k for k, p in enumerate(lanes) if seen(p)), None)
+        k = len(lanes) if (closer or kn is None) else kn
+        if any(lanes[j] not in agg for j in range(k)):
+            return None
+        win = IDN
+        for j in reversed(range(k)):
+            win = comp(win, agg[lanes[j]], cap)
+        if closer:
+            gag[t // GT] = comp(win, agg[t], cap)
+        if kn is not None:
+            part = IDN
+            for j in reversed(range(kn)):
+                part = comp(part, agg[lanes[j]], cap)
+            return min(part[0], inc[lanes[kn]] + part[1])
+        acc = win
+    elif closer:
+        gag[t // GT] = agg[t]
+    gbase, gacc = t // GT - 1, IDN
+    while True:
+        lanes = [gbase - k for k in range(GW)]
+        k, edge = None, False
+        for j, g in enumerate(lanes):
+            if g < 0:
+                k, edge = j, True
+                break
+            if seen(g * GT + GT - 1):
+                k = j
+                break
+        kk = GW if k is None else k
+        if any(lanes[j] not in gag for j in range(kk)):
+            return None
+        win = IDN
+        for j in reversed(range(kk)):
+            win = comp(win, gag[lanes[j]], cap)
+        gacc = comp(win, gacc, cap)
+        if k is not None:
+            v = INF if edge else inc[lanes[k] * GT + GT - 1]
+            xg = min(gacc[0], v + gacc[1])
+            return min(acc[0], xg + acc[1])
+        gbase -= GW
+
+
+def row_scan_sdtw(q, ref, C, TH, GT, GW, seed, cap=1 << 30):
+    rng = np.random.default_rng(seed)
+    x_all = q.astype(np.int64) + 32768
+    y = ref.astype(np.int64) + 32768
+    n, T = y.size, C * TH
+    ntiles = (n + T - 1) // T
+    ycols = np.zeros(ntiles * T, np.int64)
+    ycols[:n] = y
+    prev = np.zeros((ntiles, T), np.int64)   # gamma(0, j) = 0
+    xprev = np.zeros(ntiles, np.int64)        # gamma(i-1, first column - 1)
+    for x in x_all:
+        d = np.abs(int(x) - ycols.reshape(ntiles, T))
+        left = np.concatenate([xprev[:, None], prev[:, :-1]], axis=1)
+        a = d + np.minimum(left, prev)
+        agg, inc, gag, before = {}, {}, {}, {}
+        for t in range(ntiles):
+            maps = []
+            for th in range(TH):
+                m = IDN
+                for c in range(th * C, th * C + C):
+                    m = comp(m, (int(a[t, c]), int(d[t, c])))
+                maps.append(m)
+            acc, ex = IDN, []
+            for m in maps:
+                ex.append(acc)
+                acc = comp(acc, m)
+            agg[t], before[t] = acc, ex
+        xin, pending = {}, list(rng.permutation(ntiles))
+        while pending:
+            t = int(pending.pop(0))
+            v = look_back(t, agg, inc, gag, GT, GW, rng, cap)
+            if v is None:
+                pending.append(t)
+                continue
+            xin[t] = v
+            inc[t] = min(agg[t][0], v + agg[t][1])
+        for t in range(ntiles):
+            for th in range(TH):
+                carry = min(before[t][th][0], xin[t] + before[t][th][1])
+                for c in range(th * C, th * C + C):
+                    carry = min(int(a[t, c]), carry + int(d[t, c]))
+                    prev[t, c] = carry
+            xprev[t] = xin[t]
+    last = prev.reshape(-1)[:n]
+    j = int(np.argmin(last))
+    return int(last[j]), j
+
+
+@pytest.mark.parametrize("case", range(40))
+def test_model_matches_oracle(case):
+    rng = np.random.default_rng(case)
+    n, m = int(rng.integers(1, 260)), int(rng.integers(1, 7))
+    C, TH = int(rng.choice([1, 2, 3])), int(rng.choice([1, 2, 4]))
+    GT, GW = int(rng.choice([1, 2, 3, 4])), int(rng.choice([1, 2, 3]))
+    lo = int(rng.choice([2, 30, 32768]))
+    ref = rng.integers(-lo, lo, size=n).astype(np.int16)
+    q = rng.integers(-lo, lo, size=m).astype(np.int16)
+    assert row_scan_sdtw(q, ref, C, TH, GT, GW, case) == oracle.sdtw_i64(q, ref)
+
+
+def test_saturated_sums_do_not_change_results():
+    # a cap far below the summed distances, still above every cost
+    rng = np.random.default_rng(99)
+    ref = rng.integers(-30, 30, size=200).astype(np.int16)
+    q = rng.integers(-30, 30, size=5).astype(np.int16)
+    want = oracle.sdtw_i64(q, ref)
+    assert row_scan_sdtw(q, ref, 2, 2, 2, 2, 5, cap=1024) == want
+
+
+def test_planted_mistake_is_caught():
+    # composing a window nearest-first instead of farthest-first is wrong
+    global comp
+    ok = comp
+    try:
+        comp = lambda f, g, cap=None: ok(g, f, cap)  # noqa: E731
+        rng = np.random.default_rng(4)
+        bad = 0
+        for s in range(10):
+            ref = rng.integers(-30, 30, size=60).astype(np.int16)
+            q = rng.integers(-30, 30, size=4).astype(np.int16)
+            bad += row_scan_sdtw(q, ref, 2, 2, 2, 2, s) != oracle.sdtw_i64(q, ref)
+        assert bad > 0
+    finally:
+        comp = ok
