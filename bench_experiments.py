@@ -25,13 +25,18 @@ decision The two decision rules of the server (per-event cost threshold and
          i.i.d. noise and, harder, pore signal of a 1,000,000-base background
          genome: accuracy, on-target reads kept, off-target reads rejected,
          mean events read before the decision, reads/s and latency.
+wide     The whole-device single-query scan alone (sdtw_align_one_wide) on
+         one genome length (--genome, default 5,000,000 bases) at one width
+         (--cols, default automatic): device time per call, median of
+         --reps calls (HIP events), for a kernel trace of exactly that case.
 best_two The runner-up search alone (sdtw_stream_best_two) over 1 to 256
          resident rows of the 5,000,000-base target (9,999,990 columns):
          device time and the rate at which it reads the rows (4 bytes per
          column per row, the bound being HBM at 8 TB/s).
 
-Usage: python bench_experiments.py latency|scale|serving|decision|best_two
-                                   [--max-genome BASES]
+Usage: python bench_experiments.py latency|scale|serving|decision|best_two|wide
+                                   [--max-genome BASES] [--genome BASES] [--cols C]
+                                   [--reps R]
 """
 from __future__ import annotations
 
@@ -230,6 +235,31 @@ def decision(args):
             t.ref.close()
 
 
+def wide(args):
+    import torch
+
+    import synth
+    import paper_2211_07340_amd as sd
+    dev = torch.device("cuda:0")
+    table = synth.make_level_table()
+    L = args.genome
+    genome = synth.make_genome(L, L)
+    rd = synth.simulate_reads(genome, table, [250], 1.0, 7000 + L % 997)
+    _, cref, _ = sd.prepare_reference(torch.from_numpy(genome).to(dev),
+                                      torch.from_numpy(table).to(dev), synth.K, 64.0)
+    ref = sd.Reference(cref)
+    _, q, _ = sd.prepare_queries(torch.from_numpy(rd.values).to(dev),
+                                 torch.from_numpy(rd.offsets).to(dev), 64.0)
+    ms = _time_ms(torch, lambda: sd.align_one_wide(ref, q, cols=args.cols), args.reps)
+    c, e = sd.align_one_wide(ref, q, cols=args.cols)
+    torch.cuda.synchronize()
+    print(json.dumps({"experiment": "wide", "genome_bases": L, "reference_values": ref.n,
+                      "query_events": 250, "cols": args.cols, "reps": args.reps,
+                      "ms_median": round(ms, 4), "gcups": round(250.0 * ref.n / ms / 1e6, 1),
+                      "cost": int(c.item()), "end": int(e.item())}), flush=True)
+    ref.close()
+
+
 def best_two(args):
     import torch
 
@@ -261,14 +291,17 @@ def best_two(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("experiment",
-                    choices=["latency", "scale", "serving", "decision", "best_two"])
+                    choices=["latency", "scale", "serving", "decision", "best_two", "wide"])
     ap.add_argument("--max-genome", type=int, default=10_000_000)
+    ap.add_argument("--genome", type=int, default=5_000_000, help="wide: genome bases")
+    ap.add_argument("--cols", type=int, default=0, help="wide: columns per thread (0: auto)")
+    ap.add_argument("--reps", type=int, default=20, help="wide: timed calls")
     ap.add_argument("--off", default="noise,genomic",
                     help="decision: off-target read kinds to run, in order")
     args = ap.parse_args()
     t0 = time.perf_counter()
     {"latency": latency, "scale": scale, "serving": serving,
-     "decision": decision, "best_two": best_two}[args.experiment](args)
+     "decision": decision, "best_two": best_two, "wide": wide}[args.experiment](args)
     print(json.dumps({"done": args.experiment, "seconds": round(time.perf_counter() - t0, 1)}),
           flush=True)
 

@@ -68,8 +68,32 @@ __device__ __forceinline__ Map compose_sat(Map f, Map g) {
   return r;
 }
 
+// |x - y| + acc, and a_j = |x - y_j| + min(gamma(i-1, j-1), gamma(i-1, j)).
+// Plain code lets the compiler keep each cell's distance and a_j from the
+// first sweep for the second (fewer instructions, a shorter row); the
+// LowReg forms are asm, so the second sweep recomputes them and a thread
+// needs about 2C registers instead of 3-4C, which fits more tiles on the
+// device at once (worth it only when the tiles would otherwise run in more
+// rounds).
+template <bool LowReg>
 __device__ __forceinline__ uint32_t sad(uint32_t x, uint32_t y, uint32_t acc) {
-  return (x > y ? x - y : y - x) + acc;  // one v_sad_u32
+  if constexpr (LowReg) {
+    uint32_t r;
+    asm volatile("v_sad_u32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(y), "v"(acc));
+    return r;
+  } else {
+    return (x > y ? x - y : y - x) + acc;
+  }
+}
+template <bool LowReg>
+__device__ __forceinline__ uint32_t cell_a(uint32_t x, uint32_t y, uint32_t diag, uint32_t up) {
+  if constexpr (LowReg) {
+    uint32_t m;
+    asm volatile("v_min_u32 %0, %1, %2" : "=v"(m) : "v"(diag), "v"(up));
+    return sad<true>(x, y, m);
+  } else {
+    return sad<false>(x, y, min(diag, up));
+  }
 }
 
 // A flag word carries its payload (a map or a value) with its status in one
@@ -234,7 +258,7 @@ __device__ uint32_t look_back(int32_t tile, int32_t ntiles, int32_t i, int32_t m
   }
 }
 
-template <int C>
+template <int C, bool LowReg>
 __global__ __launch_bounds__(kWideThreads) void k_align_wide(
     const uint32_t* __restrict__ ref, int64_t n, int32_t ntiles, const int16_t* __restrict__ q,
     int32_t m, uint64_t* __restrict__ flags, uint64_t* __restrict__ tile_key,
@@ -270,9 +294,9 @@ __global__ __launch_bounds__(kWideThreads) void k_align_wide(
       uint32_t left = left0;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        const uint32_t a = sad(x, y[c], min(left, prev[c]));
-        mine.a = min(a, sad(x, y[c], mine.a));
-        mine.d = sad(x, y[c], mine.d);
+        const uint32_t a = cell_a<LowReg>(x, y[c], left, prev[c]);
+        mine.a = min(a, sad<LowReg>(x, y[c], mine.a));
+        mine.d = sad<LowReg>(x, y[c], mine.d);
         left = prev[c];
       }
     }
@@ -298,9 +322,9 @@ __global__ __launch_bounds__(kWideThreads) void k_align_wide(
       uint32_t left = left0;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        const uint32_t a = sad(x, y[c], min(left, prev[c]));
+        const uint32_t a = cell_a<LowReg>(x, y[c], left, prev[c]);
         left = prev[c];
-        carry = min(a, sad(x, y[c], carry));
+        carry = min(a, sad<LowReg>(x, y[c], carry));
         prev[c] = carry;
       }
     }
@@ -366,7 +390,17 @@ __global__ __launch_bounds__(kWideThreads) void k_wide_final(const uint64_t* __r
   }
 }
 
-template <int C>
+// Tiles of one launch that are resident at once on the current device.
+int resident_tiles(const void* fn) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kWideThreads, 0) != hipSuccess)
+    return 0;
+  return per_cu * cus;
+}
+
+template <int C, bool LowReg>
 hipError_t launch_c(const uint32_t* ref, int64_t n, const int16_t* q, int32_t m,
                     uint64_t* scratch, int32_t* cost, int32_t* end, hipStream_t st) {
   const int64_t T = (int64_t)kWideThreads * C;
@@ -378,8 +412,8 @@ hipError_t launch_c(const uint32_t* ref, int64_t n, const int16_t* q, int32_t m,
   uint32_t* ctrl = (uint32_t*)(tile_key + ntiles);
   hipLaunchKernelGGL(k_wide_clear, dim3((unsigned)((nflags + 255) / 256)), dim3(256), 0, st,
                      flags, nflags, ctrl);
-  hipLaunchKernelGGL(k_align_wide<C>, dim3((unsigned)ntiles), dim3(kWideThreads), 0, st, ref, n,
-                     ntiles, q, m, flags, tile_key, ctrl);
+  hipLaunchKernelGGL((k_align_wide<C, LowReg>), dim3((unsigned)ntiles), dim3(kWideThreads), 0,
+                     st, ref, n, ntiles, q, m, flags, tile_key, ctrl);
   hipLaunchKernelGGL(k_wide_final, dim3(1), dim3(kWideThreads), 0, st, tile_key, ntiles, ctrl,
                      cost, end);
   return hipGetLastError();
@@ -389,17 +423,18 @@ hipError_t launch_c(const uint32_t* ref, int64_t n, const int16_t* q, int32_t m,
 
 int wide_pick_cols(int64_t n, int device) {
   // Narrow tiles keep each thread's two sweeps of a row short, but every
-  // tile adds flag traffic and a reference of more tiles than fit on the
-  // device at once runs in rounds.  Measured on MI355X (250 rows): the
-  // narrowest width with at most 64 tiles (one look-back window) is fastest
-  // up to a few hundred thousand columns; then the narrowest with at most
-  // 256 tiles; beyond that, 64 columns per thread.
+  // tile adds flag traffic, and tiles beyond those resident at once run in
+  // further rounds.  Measured on MI355X (250 rows): the narrowest width with
+  // at most 64 tiles (one look-back window) is fastest up to a few hundred
+  // thousand columns, then the narrowest with at most 256 tiles; beyond
+  // that, 32 columns per thread (whose low-register form keeps the most
+  // columns resident).
   (void)device;
   const int cols[4] = {8, 16, 32, 64};
   for (int64_t limit : {int64_t(kLookback), int64_t(256)})
     for (int k = 0; k < 4; ++k)
       if (wide_tiles(n, cols[k]) <= limit) return cols[k];
-  return 64;
+  return 32;
 }
 
 int64_t wide_tiles(int64_t n, int cols) { return (n + (int64_t)kWideThreads * cols - 1) /
@@ -416,10 +451,15 @@ hipError_t launch_align_wide(const uint32_t* ref, int64_t n, const int16_t* q, i
                              hipStream_t st) {
   if (n < 1 || m < 1 || wide_tiles(n, cols) > INT_MAX) return hipErrorInvalidValue;
   switch (cols) {
-    case 8: return launch_c<8>(ref, n, q, m, scratch, cost, end, st);
-    case 16: return launch_c<16>(ref, n, q, m, scratch, cost, end, st);
-    case 32: return launch_c<32>(ref, n, q, m, scratch, cost, end, st);
-    case 64: return launch_c<64>(ref, n, q, m, scratch, cost, end, st);
+    case 8: return launch_c<8, false>(ref, n, q, m, scratch, cost, end, st);
+    case 16: return launch_c<16, false>(ref, n, q, m, scratch, cost, end, st);
+    case 32: {
+      // the low-register form when the plain one would run in more rounds
+      if (wide_tiles(n, 32) > resident_tiles((const void*)k_align_wide<32, false>))
+        return launch_c<32, true>(ref, n, q, m, scratch, cost, end, st);
+      return launch_c<32, false>(ref, n, q, m, scratch, cost, end, st);
+    }
+    case 64: return launch_c<64, false>(ref, n, q, m, scratch, cost, end, st);
     default: return hipErrorInvalidValue;
   }
 }

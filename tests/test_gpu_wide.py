@@ -103,6 +103,21 @@ def test_saturated_lookback_long_reference(dev):
         assert run_wide(dev, ref, q, cols) == oracle.sdtw_i64(q, ref)
 
 
+def test_low_register_form_on_long_reference(dev):
+    # more 32-column tiles than the plain form keeps resident (4.2 M columns
+    # on MI355X): the launch takes the low-register form of the kernel
+    rng = np.random.default_rng(31)
+    n = 5_000_000
+    ref = rng.integers(-2000, 2000, size=n).astype(np.int16)
+    q = rng.integers(-2000, 2000, size=12).astype(np.int16)
+    ref[4_400_000:4_400_012] = q  # an exact occurrence near the end
+    want = oracle.sdtw_i64(q, ref)
+    assert want == (0, 4_400_011)
+    for cols in (32, 0):
+        note(f"wide low-register form N={n} cols={cols}")
+        assert run_wide(dev, ref, q, cols) == want
+
+
 def test_back_to_back_calls_share_scratch(dev):
     # the scratch of a finished call is reused: a large call, then smaller
     # ones on another reference, then the large one again
