@@ -8,7 +8,10 @@ would hand to the method, in raw units.
 * ``make_level_table``  -- a stand-in pore model: one expected current per
   6-mer, drawn i.i.d. from N(90, 12) pA (the real R9.4 table is not
   available; section 5.3 data are not available either).
-* ``simulate_reads``    -- raw event streams in pA.  An on-target read picks a
+* ``simulate_raw``      -- raw sample streams in pA (30 adaptor levels, then
+  one level per base, each held for 4-14 samples, N(0, 1.5 pA) sample
+  noise), the input of event detection.
+* ``simulate_reads``    -- event streams in pA.  An on-target read picks a
   strand and a start, walks the strand's bases 5'->3' and emits the pore
   model's level of each successive 6-mer 1, 2 or 3 times (uniform), each
   emission with additive N(0, 0.3 x 12 pA) noise.  An off-target read is
@@ -134,6 +137,64 @@ def simulate_reads(genome: np.ndarray, table: np.ndarray, lengths,
             on[r] = False
             values[a:b] = rng.normal(LEVEL_MEAN_PA, LEVEL_SD_PA, size=M).astype(np.float32)
     return Reads(values, offsets, on, strand, start, end_true)
+
+
+SAMPLE_NOISE_PA = 1.5          # per-sample noise of raw current
+DWELL_SAMPLES = (4, 14)        # samples per base: uniform, mean 9 (4 kHz at 450 b/s)
+ADAPTOR_LEVELS = 30            # adaptor levels before the read's own bases (about 50
+                               # detected events: the detector cuts ~1.7 events per level)
+
+
+@dataclass
+class RawReads:
+    values: np.ndarray      # float32, concatenated raw samples (pA)
+    offsets: np.ndarray     # int64, nreads + 1
+    on_target: np.ndarray   # bool
+    strand: np.ndarray      # int8: 0 forward, 1 reverse, -1 off-target
+    start: np.ndarray       # int64: first k-mer index on the strand (-1 off-target)
+    levels: list            # per read: the expected level of every event (adaptor first)
+
+    @property
+    def nreads(self) -> int:
+        return self.offsets.size - 1
+
+
+def simulate_raw(genome: np.ndarray, table: np.ndarray, nreads: int, bases: int,
+                 frac_on: float, seed: int, k: int = K, adaptor: int = ADAPTOR_LEVELS,
+                 dwell=DWELL_SAMPLES, noise_sd: float = SAMPLE_NOISE_PA,
+                 off_genome: np.ndarray | None = None) -> RawReads:
+    """Raw sample streams, the input of event detection: ``adaptor`` levels
+    drawn from N(90, 12) pA, then one level per base of the read (the pore
+    model's level of each successive k-mer of a random strand and start of
+    ``genome``, or of ``off_genome``, or N(90, 12) pA for off-target reads
+    without one); every level lasts a uniform number of samples in
+    ``dwell`` and every sample carries N(0, noise_sd) pA noise."""
+    rng = np.random.default_rng(seed)
+    on = rng.random(nreads) < frac_on
+    strand = np.full(nreads, -1, dtype=np.int8)
+    start = np.full(nreads, -1, dtype=np.int64)
+    chunks, levels = [], []
+    for r in range(nreads):
+        lv = [rng.normal(LEVEL_MEAN_PA, LEVEL_SD_PA, size=adaptor)]
+        src = genome if on[r] else off_genome
+        if src is not None and src.size - k + 1 >= bases:
+            s = int(rng.integers(0, 2))
+            p = int(rng.integers(0, src.size - k + 1 - bases + 1))
+            strand_bases = src if s == 0 else (3 - src[::-1]).astype(np.uint8)
+            lv.append(_pore_current(strand_bases[p:p + bases + k - 1], table, k))
+            if on[r]:
+                strand[r], start[r] = s, p
+        else:
+            on[r] = False
+            lv.append(rng.normal(LEVEL_MEAN_PA, LEVEL_SD_PA, size=bases))
+        lv = np.concatenate(lv).astype(np.float64)
+        reps = rng.integers(dwell[0], dwell[1] + 1, size=lv.size)
+        x = np.repeat(lv, reps) + rng.normal(0.0, noise_sd, size=int(reps.sum()))
+        chunks.append(x.astype(np.float32))
+        levels.append(lv.astype(np.float32))
+    offsets = np.zeros(nreads + 1, dtype=np.int64)
+    np.cumsum([c.size for c in chunks], out=offsets[1:])
+    return RawReads(np.concatenate(chunks), offsets, on, strand, start, levels)
 
 
 @dataclass
