@@ -126,6 +126,8 @@ def peaks(t_short, t_long) -> list[int]:
 def events(x) -> np.ndarray:
     """Event values (float32) of a whole read (step 3)."""
     v = [float(a) for a in np.asarray(x, np.float32)]
+    if not v:
+        return np.zeros(0, np.float32)  # no samples, no segment
     cuts = [0] + [b for b in boundaries(x) if 0 < b < len(v)] + [len(v)]
     out = []
     for a, b in zip(cuts[:-1], cuts[1:]):

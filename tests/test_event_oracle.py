@@ -97,6 +97,7 @@ def test_partition_and_means_on_noisy_reads():
 
 def test_short_and_empty_reads():
     assert ev.boundaries(np.zeros(0, np.float32)) == []
+    assert ev.events(np.zeros(0, np.float32)).size == 0
     assert ev.events(np.array([4.0], np.float32)).tolist() == [4.0]
     assert ev.query_events(np.arange(5, dtype=np.float32), trim=1, keep=3).size == 0
 
