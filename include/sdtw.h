@@ -137,6 +137,30 @@ int sdtw_prepare_queries_ex(const float* raw_dev, const int64_t* offsets_dev, in
                             double scale, const double* stats_in_dev, double* stats_out_dev,
                             float* z_dev, int16_t* codes_dev, int64_t* nsat_dev, void* stream);
 
+/*
+ * Event detection (section 4.1: raw samples are cut into events before
+ * normalisation; section 5.3: the R9.4 parameters of the f5c / nanopolish
+ * two-window t-test detector).  Per read: t statistics over windows of 3
+ * and 6 samples, a short (threshold 1.4) and a long (threshold 9.0) peak
+ * detector with peak height 0.2 give the event boundaries; an event's value
+ * is the float32 rounding of the float64 mean of its samples.  The first
+ * `trim` events (the adaptor) are dropped and the next `keep` written.
+ *   raw_dev      float32 samples in pA (device), reads concatenated.
+ *   offsets_dev  int64[nreads + 1] (device): read r is
+ *                raw_dev[offsets[r] .. offsets[r+1]).
+ *   trim, keep   trim >= 0, 1 <= keep <= SDTW_MAX_QUERY, trim + keep <= 6144.
+ *   events_dev   out float32[nreads * keep]: row r holds read r's events
+ *                trim .. trim+counts[r]-1, then zeros.
+ *   counts_dev   out int32[nreads]: events written (fewer than keep when
+ *                the read has fewer than trim + keep events).
+ * A read is scanned only until its first trim + keep boundaries are final.
+ * Only a kernel is enqueued.  The query for sdtw_prepare_queries is then
+ * events_dev with offsets r * keep .. r * keep + counts[r].
+ */
+int sdtw_detect_events(const float* raw_dev, const int64_t* offsets_dev, int32_t nreads,
+                       int32_t trim, int32_t keep, float* events_dev, int32_t* counts_dev,
+                       void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Reference handle                                                          */
 /* ------------------------------------------------------------------------ */

@@ -59,6 +59,7 @@ def load_library():
         "sdtw_align_batch": ([p, p, p, p, p, p], C.c_int),
         "sdtw_align_one": ([p, p, i32, p, p, p], C.c_int),
         "sdtw_align_one_wide": ([p, p, i32, C.c_int, p, p, p], C.c_int),
+        "sdtw_detect_events": ([p, p, i32, i32, i32, p, p, p], C.c_int),
         "sdtw_prepare_queries_ex": ([p, p, i32, dbl, p, p, p, p, p, p], C.c_int),
         "sdtw_stream_set_config": ([p, C.c_int, C.c_int], C.c_int),
         "sdtw_row_pool_trim": ([], C.c_int),
@@ -316,6 +317,23 @@ def align_one(ref: Reference, q, cost=None, end=None, stream=None):
     _check(load_library().sdtw_align_one(ref.handle, _dev(q, qdt, "q"), q.numel(), _dev(cost),
                                          _dev(end, torch.int32, "end"), _stream(stream)))
     return cost, end
+
+
+def detect_events(raw, offsets, trim: int = 50, keep: int = 250, stream=None):
+    """sdtw_detect_events: (events float32 [nreads, keep], counts int32
+    [nreads]) device tensors from raw samples (device float32) and int64
+    device offsets."""
+    torch = _torch()
+    nreads = offsets.numel() - 1
+    if nreads < 1:
+        raise ValueError("no reads")
+    ev = torch.empty((nreads, keep), dtype=torch.float32, device=raw.device)
+    cnt = torch.empty(nreads, dtype=torch.int32, device=raw.device)
+    _check(load_library().sdtw_detect_events(_dev(raw, torch.float32, "raw"),
+                                             _dev(offsets, torch.int64, "offsets"), nreads,
+                                             int(trim), int(keep), _dev(ev), _dev(cnt),
+                                             _stream(stream)))
+    return ev, cnt
 
 
 def align_one_wide(ref: Reference, q, cols: int = 0, cost=None, end=None, stream=None):

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsdtw.so")
-SOURCES = ["api.hip", "prep.hip", "align.hip", "scores.hip", "wide.hip"]
+SOURCES = ["api.hip", "prep.hip", "align.hip", "scores.hip", "wide.hip", "events.hip"]
 ARCH = os.environ.get("SDTW_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

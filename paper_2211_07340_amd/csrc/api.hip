@@ -307,6 +307,21 @@ int sdtw_prepare_queries_ex(const float* raw_dev, const int64_t* offsets_dev, in
                    "sdtw_prepare_queries_ex: launch");
 }
 
+int sdtw_detect_events(const float* raw_dev, const int64_t* offsets_dev, int32_t nreads,
+                       int32_t trim, int32_t keep, float* events_dev, int32_t* counts_dev,
+                       void* stream) {
+  SDTW_REQUIRE(raw_dev && offsets_dev && events_dev && counts_dev,
+               "sdtw_detect_events: null pointer");
+  SDTW_REQUIRE(nreads >= 1, "sdtw_detect_events: nreads=%d < 1", nreads);
+  SDTW_REQUIRE(trim >= 0 && keep >= 1 && keep <= SDTW_MAX_QUERY &&
+                   (int64_t)trim + keep <= kMaxEventList,
+               "sdtw_detect_events: trim=%d keep=%d outside trim >= 0, 1 <= keep <= %d, "
+               "trim + keep <= %d", trim, keep, SDTW_MAX_QUERY, kMaxEventList);
+  return check_hip(launch_detect_events(raw_dev, offsets_dev, nreads, trim, keep, events_dev,
+                                        counts_dev, (hipStream_t)stream),
+                   "sdtw_detect_events: launch");
+}
+
 // ---------------------------------------------------------------------------
 // reference
 // ---------------------------------------------------------------------------

@@ -146,6 +146,14 @@ hipError_t launch_best_two(int dtype, const StreamItem* items, int32_t ns, int64
                            void* second_cost, int32_t* second_end, hipStream_t st);
 int max_lds_bytes();
 
+// ---- launchers (events.hip) -------------------------------------------------
+// Event values of each read's raw samples (trim + keep <= kMaxEventList).
+constexpr int32_t kMaxEventList = 6144;
+size_t detect_events_lds_bytes(int32_t trim, int32_t keep);
+hipError_t launch_detect_events(const float* raw, const int64_t* offs, int32_t nreads,
+                                int32_t trim, int32_t keep, float* out, int32_t* counts,
+                                hipStream_t st);
+
 // ---- launchers (wide.hip) ---------------------------------------------------
 // One int16 query over every compute unit: row scans with look-back between
 // tiles of 256 * cols columns (cols in {8, 16, 32, 64}).  `scratch` holds

@@ -1,0 +1,212 @@
+// Event detection on the device: raw samples of each read -> the event values
+// the alignment uses as its query (section 4.1 segments raw samples into
+// events before normalisation; section 5.3 takes its R9.4 parameters from the
+// two-window t-test detector of f5c and nanopolish).
+//
+// The detector, as this library reads it:
+//  1. t statistic at each boundary position i (between samples i-1 and i),
+//     window length w: means m1, m2 and population variances v1, v2 of the w
+//     samples before and the w samples from i;
+//         t_w(i) = |m2 - m1| / max(sqrt((v1 + v2) / w), 1e-30),
+//     0 outside w <= i <= L - w.  float64, sums in index order.
+//  2. Short (w = 3, threshold 1.4) and long (w = 6, threshold 9.0) peak
+//     detectors with peak height 0.2 scan the positions in order (short
+//     first).  Without a candidate a detector follows the running minimum of
+//     t and opens a candidate once t rises more than the peak height above
+//     it; with one it moves the candidate to any higher t, the short
+//     detector's candidate above its threshold masks the long detector up to
+//     candidate + 6 (dropping its candidate), a candidate above threshold
+//     becomes valid once t falls more than the peak height below it, and a
+//     valid candidate is emitted as a boundary once the position is more
+//     than w / 2 past it; the detector restarts from the current t.
+//  3. Events are the segments between consecutive distinct boundaries (0 and
+//     L the outer ends); an event's value is the float32 rounding of the
+//     float64 mean of its samples, summed in index order.
+//  4. The first `trim` events (adaptor) are dropped, the next `keep` kept.
+//
+// One wave per read.  Positions are taken in blocks of 512: all lanes compute
+// both t statistics of the block into LDS, then lane 0 runs the two
+// detectors over it (a sequential state machine) and inserts each emitted
+// boundary into a sorted list that keeps only the trim + keep smallest.
+// Boundaries can be emitted out of order (a candidate stays open while the
+// other detector emits), so the list is final below the smallest open
+// candidate; the read stops as soon as its first trim + keep boundaries are
+// final, which is the first few thousand samples of a read in Read Until.
+// Then every lane sums one event at a time.
+#include <float.h>
+#include <math.h>
+
+#include "common.h"
+
+namespace sdtw {
+namespace {
+
+constexpr int kEvBlock = 512;  // positions per block
+constexpr int kWShort = 3, kWLong = 6;
+constexpr double kTShort = 1.4, kTLong = 9.0, kPeakHeight = 0.2, kDenFloor = 1e-30;
+
+template <int W>
+__device__ __forceinline__ double tstat(const float* __restrict__ x, int64_t L, int64_t i) {
+  if (i < W || i > L - W) return 0.0;
+  double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    s1 += (double)x[i - W + k];
+    s2 += (double)x[i + k];
+  }
+  const double m1 = s1 / (double)W, m2 = s2 / (double)W;
+  double q1 = 0.0, q2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    const double d1 = (double)x[i - W + k] - m1;
+    const double d2 = (double)x[i + k] - m2;
+    q1 += d1 * d1;
+    q2 += d2 * d2;
+  }
+  const double v1 = q1 / (double)W, v2 = q2 / (double)W;
+  const double den = fmax(sqrt((v1 + v2) / (double)W), kDenFloor);
+  return fabs(m2 - m1) / den;
+}
+
+struct Detector {
+  int64_t masked_to, peak_pos;
+  double peak_val;
+  bool valid;
+};
+
+// Insert b into the sorted distinct list bs[0..n) that keeps at most cap
+// entries (the smallest).
+__device__ __forceinline__ void insert_bound(int64_t* bs, int32_t& n, int32_t cap, int64_t b) {
+  if (n == cap && b >= bs[n - 1]) return;
+  int32_t k = n;
+  while (k > 0 && bs[k - 1] > b) --k;
+  if (k > 0 && bs[k - 1] == b) return;
+  const int32_t last = n < cap ? n : cap - 1;  // the largest falls off when full
+  for (int32_t j = last; j > k; --j) bs[j] = bs[j - 1];
+  bs[k] = b;
+  if (n < cap) ++n;
+}
+
+// One detector step at position i with statistic v (lane 0 only).
+__device__ __forceinline__ void step(Detector& d, Detector* other, int w, double threshold,
+                                     int64_t i, double v, int64_t* bs, int32_t& nb,
+                                     int32_t cap) {
+  if (d.masked_to >= i) return;
+  if (d.peak_pos < 0) {
+    if (v < d.peak_val) {
+      d.peak_val = v;
+    } else if (v - d.peak_val > kPeakHeight) {
+      d.peak_val = v;
+      d.peak_pos = i;
+    }
+    return;
+  }
+  if (v > d.peak_val) {
+    d.peak_val = v;
+    d.peak_pos = i;
+  }
+  if (other && d.peak_val > threshold) {  // the short detector masks the long one
+    other->masked_to = d.peak_pos + kWLong;
+    other->peak_pos = -1;
+    other->peak_val = INFINITY;
+    other->valid = false;
+  }
+  if (d.peak_val - v > kPeakHeight && d.peak_val > threshold) d.valid = true;
+  if (d.valid && i - d.peak_pos > w / 2) {
+    insert_bound(bs, nb, cap, d.peak_pos);
+    d.peak_pos = -1;
+    d.peak_val = v;
+    d.valid = false;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_detect_events(const float* __restrict__ raw,
+                                                      const int64_t* __restrict__ offs,
+                                                      int32_t nreads, int32_t trim, int32_t keep,
+                                                      float* __restrict__ out,
+                                                      int32_t* __restrict__ counts) {
+  extern __shared__ double ev_lds[];
+  double* ts = ev_lds;                         // [kEvBlock]
+  double* tl = ev_lds + kEvBlock;              // [kEvBlock]
+  int64_t* bs = (int64_t*)(ev_lds + 2 * kEvBlock);  // [trim + keep]
+  __shared__ int32_t s_nb, s_done;
+  __shared__ int64_t s_end;
+
+  const int32_t r = (int32_t)blockIdx.x;
+  if (r >= nreads) return;
+  const int lane = threadIdx.x;
+  const int64_t a = offs[r];
+  const int64_t L = offs[r + 1] - a;
+  const float* __restrict__ x = raw + a;
+  const int32_t cap = trim + keep;
+
+  Detector ds{-1, -1, INFINITY, false}, dl{-1, -1, INFINITY, false};
+  int32_t nb = 0;
+  if (lane == 0) {
+    s_nb = 0;
+    s_done = 0;
+    s_end = L;
+  }
+  __syncthreads();
+  for (int64_t b0 = 0; b0 < L; b0 += kEvBlock) {
+    const int64_t nblk = L - b0 < kEvBlock ? L - b0 : kEvBlock;
+    for (int64_t j = lane; j < nblk; j += 64) {
+      ts[j] = tstat<kWShort>(x, L, b0 + j);
+      tl[j] = tstat<kWLong>(x, L, b0 + j);
+    }
+    __syncthreads();
+    if (lane == 0) {
+      for (int64_t j = 0; j < nblk; ++j) {
+        step(ds, &dl, kWShort, kTShort, b0 + j, ts[j], bs, nb, cap);
+        step(dl, nullptr, kWLong, kTLong, b0 + j, tl[j], bs, nb, cap);
+      }
+      // below the smallest open candidate no boundary can still appear
+      int64_t cut = b0 + nblk;
+      if (ds.peak_pos >= 0 && ds.peak_pos < cut) cut = ds.peak_pos;
+      if (dl.peak_pos >= 0 && dl.peak_pos < cut) cut = dl.peak_pos;
+      s_nb = nb;
+      if (nb == cap && bs[cap - 1] < cut) {
+        s_done = 1;
+        s_end = -1;  // stopped early: events 0 .. cap-1 are closed
+      }
+    }
+    __syncthreads();
+    if (s_done) break;
+  }
+  nb = s_nb;
+  // events: cut_0 = 0, cut_j = bs[j-1]; the last one ends at L when the read
+  // was scanned to its end
+  const int32_t closed = s_end < 0 ? cap : (L > 0 ? nb + 1 : 0);  // no samples, no event
+  const int32_t hi = closed < cap ? closed : cap;
+  const int32_t n_out = hi > trim ? hi - trim : 0;
+  for (int32_t k = lane; k < keep; k += 64) {
+    float v = 0.0f;
+    if (k < n_out) {
+      const int32_t j = trim + k;
+      const int64_t lo = j == 0 ? 0 : bs[j - 1];
+      const int64_t up = j < nb ? bs[j] : L;
+      double s = 0.0;
+      for (int64_t q = lo; q < up; ++q) s += (double)x[q];
+      v = (float)(s / (double)(up - lo));
+    }
+    out[(int64_t)r * keep + k] = v;
+  }
+  if (lane == 0) counts[r] = n_out;
+}
+
+}  // namespace
+
+size_t detect_events_lds_bytes(int32_t trim, int32_t keep) {
+  return sizeof(double) * 2 * kEvBlock + sizeof(int64_t) * (size_t)(trim + keep);
+}
+
+hipError_t launch_detect_events(const float* raw, const int64_t* offs, int32_t nreads,
+                                int32_t trim, int32_t keep, float* out, int32_t* counts,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_detect_events, dim3((unsigned)nreads), dim3(64),
+                     detect_events_lds_bytes(trim, keep), st, raw, offs, nreads, trim, keep, out,
+                     counts);
+  return hipGetLastError();
+}
+
+}  // namespace sdtw

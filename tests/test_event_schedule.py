@@ -1,0 +1,104 @@
+"""CPU model of the event-detection kernel's control flow (k_detect_events),
+checked against the oracle: positions in blocks of 512, boundaries inserted
+into a sorted list that keeps only the trim + keep smallest, the early stop
+once those are final (below every open candidate), and the event sums from
+the list.  The t statistics are the oracle's; what is tested is that
+stopping early and truncating the list never change the events returned.
+No GPU.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import events as ev
+
+BLOCK = 512
+
+
+def kernel_model(x, trim, keep):
+    ts, tl = ev.tstat(x, 3), ev.tstat(x, 6)
+    L, cap = x.size, trim + keep
+    det = {k: dict(masked_to=-1, peak_pos=-1, peak_val=math.inf, valid=False)
+           for k in ("s", "l")}
+    bs = []
+
+    def insert(b):
+        if len(bs) == cap and b >= bs[-1]:
+            return
+        if b in bs:
+            return
+        bs.append(b)
+        bs.sort()
+        del bs[cap:]
+
+    def step(k, w, thr, i, v):
+        d = det[k]
+        if d["masked_to"] >= i:
+            return
+        if d["peak_pos"] < 0:
+            if v < d["peak_val"]:
+                d["peak_val"] = v
+            elif v - d["peak_val"] > ev.PEAK_HEIGHT:
+                d["peak_val"], d["peak_pos"] = v, i
+            return
+        if v > d["peak_val"]:
+            d["peak_val"], d["peak_pos"] = v, i
+        if k == "s" and d["peak_val"] > thr:
+            det["l"].update(masked_to=d["peak_pos"] + 6, peak_pos=-1, peak_val=math.inf,
+                            valid=False)
+        if d["peak_val"] - v > ev.PEAK_HEIGHT and d["peak_val"] > thr:
+            d["valid"] = True
+        if d["valid"] and i - d["peak_pos"] > w // 2:
+            insert(d["peak_pos"])
+            d.update(peak_pos=-1, peak_val=v, valid=False)
+
+    stopped = False
+    for b0 in range(0, L, BLOCK):
+        end = min(L, b0 + BLOCK)
+        for i in range(b0, end):
+            step("s", 3, ev.T_SHORT, i, ts[i])
+            step("l", 6, ev.T_LONG, i, tl[i])
+        cut = end
+        for k in ("s", "l"):
+            if 0 <= det[k]["peak_pos"] < cut:
+                cut = det[k]["peak_pos"]
+        if len(bs) == cap and bs[-1] < cut:
+            stopped = True
+            break
+    closed = cap if stopped else (len(bs) + 1 if L > 0 else 0)
+    n_out = max(min(closed, cap) - trim, 0)
+    out = []
+    for k in range(n_out):
+        j = trim + k
+        lo = 0 if j == 0 else bs[j - 1]
+        up = bs[j] if j < len(bs) else L
+        s = 0.0
+        for q in range(lo, up):
+            s += float(x[q])
+        out.append(s / (up - lo))
+    return np.asarray(out, np.float64).astype(np.float32), stopped
+
+
+@pytest.mark.parametrize("trim,keep", [(0, 1), (0, 7), (5, 20), (50, 250), (50, 600),
+                                       (400, 30), (0, 4000)])
+def test_model_equals_oracle(trim, keep):
+    g = synth.make_genome(synth.SMALL_GENOME, synth.SMALL_GENOME)
+    raw = synth.simulate_raw(g, synth.make_level_table(), 5, 300, 0.6, trim * 7 + keep)
+    stops = 0
+    for r in range(raw.nreads):
+        x = raw.values[raw.offsets[r]:raw.offsets[r + 1]]
+        got, stopped = kernel_model(x, trim, keep)
+        want = ev.query_events(x, trim, keep)
+        assert np.array_equal(got, want), (r, trim, keep)
+        stops += stopped
+    if trim + keep <= 300:  # reads have ~550 events: most stop early
+        assert stops >= 4
+
+
+def test_reads_shorter_than_windows():
+    for L in (0, 1, 2, 5, 6, 7, 12):
+        x = np.linspace(80, 100, L).astype(np.float32)
+        got, _ = kernel_model(x, 0, 5)
+        assert np.array_equal(got, ev.query_events(x, 0, 5))
