@@ -25,6 +25,12 @@ decision The two decision rules of the server (per-event cost threshold and
          i.i.d. noise and, harder, pore signal of a 1,000,000-base background
          genome: accuracy, on-target reads kept, off-target reads rejected,
          mean events read before the decision, reads/s and latency.
+events   Pre-processing on the device (section 4.1's event detection, prefix
+         trimming and normalisation) against alignment, for 4,096 simulated
+         raw reads (30 adaptor levels, then 320 bases; 50% on-target) and the
+         29,903-base genome: device time per stage (HIP events, median of
+         --reps), raw samples per second, and the share of each stage (the
+         paper's pre-processing takes about 30% of its run time, section 6).
 wide     The whole-device single-query scan alone (sdtw_align_one_wide) on
          one genome length (--genome, default 5,000,000 bases) at one width
          (--cols, default automatic): device time per call, median of
@@ -34,7 +40,7 @@ best_two The runner-up search alone (sdtw_stream_best_two) over 1 to 256
          device time and the rate at which it reads the rows (4 bytes per
          column per row, the bound being HBM at 8 TB/s).
 
-Usage: python bench_experiments.py latency|scale|serving|decision|best_two|wide
+Usage: python bench_experiments.py latency|scale|serving|decision|best_two|wide|events
                                    [--max-genome BASES] [--genome BASES] [--cols C]
                                    [--reps R]
 """
@@ -235,6 +241,47 @@ def decision(args):
             t.ref.close()
 
 
+def events(args):
+    import torch
+
+    import synth
+    import paper_2211_07340_amd as sd
+    dev = torch.device("cuda:0")
+    table = synth.make_level_table()
+    genome = synth.make_genome(synth.SMALL_GENOME, synth.SMALL_GENOME)
+    raw = synth.simulate_raw(genome, table, 4096, 320, 0.5, 4242)
+    x = torch.from_numpy(raw.values).to(dev)
+    xo = torch.from_numpy(raw.offsets).to(dev)
+    _, cref, _ = sd.prepare_reference(torch.from_numpy(genome).to(dev),
+                                      torch.from_numpy(table).to(dev), synth.K, 64.0)
+    ref = sd.Reference(cref)
+    ev, cnt = sd.detect_events(x, xo, 50, 250)
+    torch.cuda.synchronize()
+    assert bool((cnt == 250).all())
+    eo_np = np.arange(4097, dtype=np.int64) * 250
+    eo = torch.from_numpy(eo_np).to(dev)
+    _, q, _ = sd.prepare_queries(ev.reshape(-1), eo, 64.0)
+    plan = sd.Plan(eo_np, sd.I16)
+    sd.autotune(ref, plan, q)
+    reps = args.reps
+    t_ev = _time_ms(torch, lambda: sd.detect_events(x, xo, 50, 250), reps)
+    t_norm = _time_ms(torch, lambda: sd.prepare_queries(ev.reshape(-1), eo, 64.0), reps)
+    t_al = _time_ms(torch, lambda: sd.align_batch(ref, plan, q), reps)
+    total = t_ev + t_norm + t_al
+    print(json.dumps({"experiment": "pre-processing vs alignment", "reads": 4096,
+                      "raw_samples": int(raw.values.size),
+                      "events_per_read": 250, "trim": 50,
+                      "detect_events_ms": round(t_ev, 4), "normalise_ms": round(t_norm, 4),
+                      "align_ms": round(t_al, 4),
+                      "raw_samples_per_s": round(raw.values.size / (t_ev * 1e-3), 1),
+                      "reads_per_s_end_to_end": round(4096 / (total * 1e-3), 1),
+                      "share_detect_events": round(t_ev / total, 4),
+                      "share_normalise": round(t_norm / total, 4),
+                      "share_align": round(t_al / total, 4)}), flush=True)
+    plan.close()
+    ref.close()
+
+
 def wide(args):
     import torch
 
@@ -291,7 +338,8 @@ def best_two(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("experiment",
-                    choices=["latency", "scale", "serving", "decision", "best_two", "wide"])
+                    choices=["latency", "scale", "serving", "decision", "best_two", "wide",
+                             "events"])
     ap.add_argument("--max-genome", type=int, default=10_000_000)
     ap.add_argument("--genome", type=int, default=5_000_000, help="wide: genome bases")
     ap.add_argument("--cols", type=int, default=0, help="wide: columns per thread (0: auto)")
@@ -301,7 +349,8 @@ def main():
     args = ap.parse_args()
     t0 = time.perf_counter()
     {"latency": latency, "scale": scale, "serving": serving,
-     "decision": decision, "best_two": best_two, "wide": wide}[args.experiment](args)
+     "decision": decision, "best_two": best_two, "wide": wide,
+     "events": events}[args.experiment](args)
     print(json.dumps({"done": args.experiment, "seconds": round(time.perf_counter() - t0, 1)}),
           flush=True)
 
