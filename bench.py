@@ -283,7 +283,43 @@ def extras(sd, torch, dev, w, reads, zref, cref, args, stream):
     c1 = float(reads.lengths[:n1].sum()) * ref0.n
     res["plain_one_read_per_launch"] = {"reads": n1, "ms_per_read": round(t * 1e3 / n1, 4),
                                         "gcups": round(c1 / t / 1e9, 2)}
+    if dt0 == sd.I16:
+        # the first read over every compute unit (row scans with look-back)
+        q1 = q0[offs[0]:offs[1]]
+        m1 = int(offs[1] - offs[0])
+        ms1 = _median_event_ms(torch, stream, lambda: sd.align_one_wide(ref0, q1), 20)
+        res["single_query_whole_device"] = {
+            "query_values": m1, "reference_values": ref0.n, "ms": round(ms1, 4),
+            "paper_accelerator_model_ms": round((ref0.n + m1 - 1) / 1e8 * 1e3, 4)}
+    # pre-processing on the device: event detection and trimming of raw reads
+    import synth
+    rr = synth.simulate_raw(w.genome, w.table, 4096, 320, 0.5, 4242)
+    xr = torch.from_numpy(rr.values).to(dev)
+    xo = torch.from_numpy(rr.offsets).to(dev)
+    ms_ev = _median_event_ms(torch, stream, lambda: sd.detect_events(xr, xo, 50, 250), 5)
+    res["event_detection"] = {"raw_reads": rr.nreads, "raw_samples": int(rr.values.size),
+                              "trim": 50, "keep": 250, "ms": round(ms_ev, 4),
+                              "reads_per_s": round(rr.nreads / (ms_ev * 1e-3), 1)}
+    ref0.close()
+    ref.close()
+    plan.close()
     return res
+
+
+def _median_event_ms(torch, stream, fn, reps):
+    """Median device time of fn() (HIP events on the launch stream) after one
+    untimed call."""
+    fn()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        b.synchronize()
+        out.append(a.elapsed_time(b))
+    return float(np.median(out))
 
 
 def serving_targets(torch, dev, pool: int = 512, seed: int = 4400, large: bool = True):
