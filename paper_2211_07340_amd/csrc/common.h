@@ -149,7 +149,6 @@ int max_lds_bytes();
 // ---- launchers (events.hip) -------------------------------------------------
 // Event values of each read's raw samples (trim + keep <= kMaxEventList).
 constexpr int32_t kMaxEventList = 6144;
-size_t detect_events_lds_bytes(int32_t trim, int32_t keep);
 hipError_t launch_detect_events(const float* raw, const int64_t* offs, int32_t nreads,
                                 int32_t trim, int32_t keep, float* out, int32_t* counts,
                                 hipStream_t st);

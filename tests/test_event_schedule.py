@@ -1,5 +1,6 @@
 """CPU model of the event-detection kernel's control flow (k_detect_events),
-checked against the oracle: positions in blocks of 512, boundaries inserted
+checked against the oracle: positions in blocks (512, or 128 when a wave
+serves four reads), boundaries inserted
 into a sorted list that keeps only the trim + keep smallest, the early stop
 once those are final (below every open candidate), and the event sums from
 the list.  The t statistics are the oracle's; what is tested is that
@@ -14,10 +15,7 @@ import pytest
 import synth
 from oracle import events as ev
 
-BLOCK = 512
-
-
-def kernel_model(x, trim, keep):
+def kernel_model(x, trim, keep, BLOCK=512):
     ts, tl = ev.tstat(x, 3), ev.tstat(x, 6)
     L, cap = x.size, trim + keep
     det = {k: dict(masked_to=-1, peak_pos=-1, peak_val=math.inf, valid=False)
@@ -81,15 +79,16 @@ def kernel_model(x, trim, keep):
     return np.asarray(out, np.float64).astype(np.float32), stopped
 
 
+@pytest.mark.parametrize("block", [128, 512])
 @pytest.mark.parametrize("trim,keep", [(0, 1), (0, 7), (5, 20), (50, 250), (50, 600),
                                        (400, 30), (0, 4000)])
-def test_model_equals_oracle(trim, keep):
+def test_model_equals_oracle(trim, keep, block):
     g = synth.make_genome(synth.SMALL_GENOME, synth.SMALL_GENOME)
     raw = synth.simulate_raw(g, synth.make_level_table(), 5, 300, 0.6, trim * 7 + keep)
     stops = 0
     for r in range(raw.nreads):
         x = raw.values[raw.offsets[r]:raw.offsets[r + 1]]
-        got, stopped = kernel_model(x, trim, keep)
+        got, stopped = kernel_model(x, trim, keep, block)
         want = ev.query_events(x, trim, keep)
         assert np.array_equal(got, want), (r, trim, keep)
         stops += stopped

@@ -71,6 +71,23 @@ def test_noise_reads_and_edge_lengths(dev):
         check(values, offsets, e, c, trim, keep)
 
 
+@pytest.mark.parametrize("nreads", [4096, 8192])
+def test_large_batches_share_waves(dev, nreads):
+    # batches large enough that two or four reads share a wave: a sample of
+    # reads in every position within a wave against the oracle
+    g = synth.make_genome(synth.SMALL_GENOME, synth.SMALL_GENOME)
+    raw = synth.simulate_raw(g, synth.make_level_table(), nreads, 60, 0.5, nreads, adaptor=8)
+    note(f"events {nreads} reads, {raw.values.size} samples")
+    e, c = gpu_events(dev, raw.values, raw.offsets, 10, 60)
+    rng = np.random.default_rng(nreads)
+    pick = sorted(set(rng.choice(nreads, 20, replace=False).tolist() + [0, 1, 2, 3, nreads - 1]))
+    for r in pick:
+        want = ev.query_events(raw.values[raw.offsets[r]:raw.offsets[r + 1]], 10, 60)
+        assert c[r] == want.size, r
+        assert np.array_equal(e[r, :c[r]], want), r
+        assert not e[r, c[r]:].any()
+
+
 def test_noise_free_steps(dev):
     rng = np.random.default_rng(9)
     lens = rng.integers(3, 16, size=400)
