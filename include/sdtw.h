@@ -154,7 +154,8 @@ int sdtw_prepare_queries_ex(const float* raw_dev, const int64_t* offsets_dev, in
  *   counts_dev   out int32[nreads]: events written (fewer than keep when
  *                the read has fewer than trim + keep events).
  * A read is scanned only until its first trim + keep boundaries are final.
- * Only a kernel is enqueued.  The query for sdtw_prepare_queries is then
+ * Only a kernel is enqueued (no allocation), so the call may be captured in
+ * a hipGraph.  The query for sdtw_prepare_queries is then
  * events_dev with offsets r * keep .. r * keep + counts[r].
  */
 int sdtw_detect_events(const float* raw_dev, const int64_t* offsets_dev, int32_t nreads,
@@ -303,8 +304,9 @@ int sdtw_align_one(sdtw_ref ref, const void* q_dev, int32_t M, void* cost_dev,
  *          reference into at most 64 tiles, else into at most 256, else 64
  *          (the fastest choice measured for each reference length).
  *   cost_dev  out int32[1]; end_dev out int32[1] (0-based column).
- * Only kernels are enqueued.  Uses library-owned device scratch of 8 bytes
- * per tile per row (8 MiB per call in flight unless more is needed).  If a
+ * Enqueues three kernels and records an event that tracks the reuse of its
+ * library-owned scratch (8 bytes per tile per row: 8 MiB per call in flight
+ * unless more is needed), so the call is not for graph capture.  If a
  * tile waits for its left neighbour for about a second (a defect; never in
  * normal operation) every wait ends and cost and end are -1.
  * EINVAL for a float32 reference.

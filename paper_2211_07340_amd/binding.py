@@ -319,16 +319,21 @@ def align_one(ref: Reference, q, cost=None, end=None, stream=None):
     return cost, end
 
 
-def detect_events(raw, offsets, trim: int = 50, keep: int = 250, stream=None):
+def detect_events(raw, offsets, trim: int = 50, keep: int = 250, events=None, counts=None,
+                  stream=None):
     """sdtw_detect_events: (events float32 [nreads, keep], counts int32
     [nreads]) device tensors from raw samples (device float32) and int64
-    device offsets."""
+    device offsets; ``events`` / ``counts`` may be given (preallocated)."""
     torch = _torch()
     nreads = offsets.numel() - 1
     if nreads < 1:
         raise ValueError("no reads")
-    ev = torch.empty((nreads, keep), dtype=torch.float32, device=raw.device)
-    cnt = torch.empty(nreads, dtype=torch.int32, device=raw.device)
+    ev = events if events is not None else torch.empty((nreads, keep), dtype=torch.float32,
+                                                       device=raw.device)
+    cnt = counts if counts is not None else torch.empty(nreads, dtype=torch.int32,
+                                                        device=raw.device)
+    if ev.numel() != nreads * keep or cnt.numel() != nreads:
+        raise ValueError("events must hold nreads * keep values and counts nreads")
     _check(load_library().sdtw_detect_events(_dev(raw, torch.float32, "raw"),
                                              _dev(offsets, torch.int64, "offsets"), nreads,
                                              int(trim), int(keep), _dev(ev), _dev(cnt),
