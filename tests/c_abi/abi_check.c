@@ -6,9 +6,14 @@
  *   abi_check DIR   reads DIR/ref.i16 (int16 reference codes), DIR/q.i16
  *                   (int16 query codes, CSR) and DIR/offs.i64 (nq + 1
  *                   offsets); writes DIR/batch.i32 (cost, end per read:
- *                   sdtw_align_batch after sdtw_plan_autotune) and
+ *                   sdtw_align_batch after sdtw_plan_autotune),
  *                   DIR/stream.i32 (cost, end after each of two chunks of
- *                   read 0: sdtw_stream_open / extend / close).
+ *                   read 0: sdtw_stream_open / extend / close) and
+ *                   DIR/wide.i32 (cost, end of read 0 over the whole device:
+ *                   sdtw_align_one_wide).  With DIR/raw.f32 and
+ *                   DIR/raw_offs.i64 present it also writes DIR/events.f32
+ *                   and DIR/event_counts.i32 (sdtw_detect_events, trim 50,
+ *                   keep 250).
  */
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
@@ -128,6 +133,51 @@ int main(int argc, char** argv) {
   }
   SDTW(sdtw_stream_close(s));
   dump(dir, "stream.i32", res, sizeof res);
+
+  /* read 0 over the whole device */
+  int32_t wide[2];
+  SDTW(sdtw_align_one_wide(r, q_dev, (int32_t)m0, 0, cost_dev, end_dev, st));
+  HIP(hipStreamSynchronize(st));
+  HIP(hipMemcpy(&wide[0], cost_dev, sizeof(int32_t), hipMemcpyDeviceToHost));
+  HIP(hipMemcpy(&wide[1], end_dev, sizeof(int32_t), hipMemcpyDeviceToHost));
+  dump(dir, "wide.i32", wide, sizeof wide);
+
+  /* event detection on raw samples, when given */
+  char rawpath[4096];
+  snprintf(rawpath, sizeof rawpath, "%s/raw.f32", dir);
+  FILE* probe = fopen(rawpath, "rb");
+  if (probe) {
+    fclose(probe);
+    size_t xb, xob;
+    float* x = (float*)slurp(dir, "raw.f32", &xb);
+    int64_t* xo = (int64_t*)slurp(dir, "raw_offs.i64", &xob);
+    const int32_t nr = (int32_t)(xob / 8) - 1;
+    const int32_t keep = 250;
+    void *x_dev, *xo_dev, *ev_dev, *cnt_dev;
+    HIP(hipMalloc(&x_dev, xb));
+    HIP(hipMalloc(&xo_dev, xob));
+    HIP(hipMalloc(&ev_dev, sizeof(float) * (size_t)nr * keep));
+    HIP(hipMalloc(&cnt_dev, sizeof(int32_t) * (size_t)nr));
+    HIP(hipMemcpy(x_dev, x, xb, hipMemcpyHostToDevice));
+    HIP(hipMemcpy(xo_dev, xo, xob, hipMemcpyHostToDevice));
+    SDTW(sdtw_detect_events((const float*)x_dev, (const int64_t*)xo_dev, nr, 50, keep,
+                            (float*)ev_dev, (int32_t*)cnt_dev, st));
+    HIP(hipStreamSynchronize(st));
+    float* ev = (float*)malloc(sizeof(float) * (size_t)nr * keep);
+    int32_t* cnt = (int32_t*)malloc(sizeof(int32_t) * (size_t)nr);
+    HIP(hipMemcpy(ev, ev_dev, sizeof(float) * (size_t)nr * keep, hipMemcpyDeviceToHost));
+    HIP(hipMemcpy(cnt, cnt_dev, sizeof(int32_t) * (size_t)nr, hipMemcpyDeviceToHost));
+    dump(dir, "events.f32", ev, sizeof(float) * (size_t)nr * keep);
+    dump(dir, "event_counts.i32", cnt, sizeof(int32_t) * (size_t)nr);
+    HIP(hipFree(x_dev));
+    HIP(hipFree(xo_dev));
+    HIP(hipFree(ev_dev));
+    HIP(hipFree(cnt_dev));
+    free(ev);
+    free(cnt);
+    free(x);
+    free(xo);
+  }
 
   SDTW(sdtw_plan_destroy(plan));
   SDTW(sdtw_free_reference(r));

@@ -59,6 +59,10 @@ def test_c_client_matches_oracle(exe, tmp_path):
     offs = np.asarray(rd.offsets, np.int64)
     offs.tofile(tmp_path / "offs.i64")
 
+    raw = synth.simulate_raw(genome, table, 5, 320, 0.6, 29)
+    raw.values.tofile(tmp_path / "raw.f32")
+    raw.offsets.astype(np.int64).tofile(tmp_path / "raw_offs.i64")
+
     print(f"abi_check {tmp_path} nq={offs.size - 1} n={ref.size}", flush=True)
     r = subprocess.run([exe, str(tmp_path)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
@@ -77,3 +81,12 @@ def test_c_client_matches_oracle(exe, tmp_path):
     sc, se, _ = oracle.batch(oracle.I64, qq, pre, ref)
     got = np.fromfile(tmp_path / "stream.i32", np.int32)
     assert got.tolist() == [int(sc[0]), int(se[0]), int(sc[1]), int(se[1])]
+    # read 0 over the whole device
+    assert np.fromfile(tmp_path / "wide.i32", np.int32).tolist() == [int(sc[1]), int(se[1])]
+    # event detection
+    from oracle import events as oev
+    ev = np.fromfile(tmp_path / "events.f32", np.float32).reshape(5, 250)
+    cnt = np.fromfile(tmp_path / "event_counts.i32", np.int32)
+    for r in range(5):
+        want = oev.query_events(raw.values[raw.offsets[r]:raw.offsets[r + 1]], 50, 250)
+        assert cnt[r] == want.size and np.array_equal(ev[r, :cnt[r]], want), r
