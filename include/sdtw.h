@@ -162,6 +162,31 @@ int sdtw_detect_events(const float* raw_dev, const int64_t* offsets_dev, int32_t
                        int32_t trim, int32_t keep, float* events_dev, int32_t* counts_dev,
                        void* stream);
 
+/*
+ * Event detection on the samples received so far of reads still being
+ * sequenced (Read Until: events are cut from the start of a read while it
+ * passes through the pore).  Same detector as sdtw_detect_events; only
+ * events that more samples cannot change are written: the scan stops 5
+ * samples before the end (the t statistics there still depend on samples
+ * to come) and an event is written only if its end boundary is final.
+ * Events written for a prefix are the same as those of the whole read.
+ *   ranges_dev   int64[2 * nreads] (device): read r's samples so far are
+ *                raw_dev[ranges[2r] .. ranges[2r+1]).
+ *   firsts_dev   int32[nreads] (device): index of the first event wanted
+ *                (adaptor events plus events already taken), 0 <= first <=
+ *                max_first; a read outside that range gets count -1.
+ *   max_first, keep   0 <= max_first, 1 <= keep <= SDTW_MAX_QUERY,
+ *                max_first + keep <= 6144.
+ *   events_dev   out float32[nreads * keep]: read r's events first ..
+ *                first + counts[r] - 1, then zeros.
+ *   counts_dev   out int32[nreads]: events written (0 .. keep).
+ * Only a kernel is enqueued (no allocation).
+ */
+int sdtw_detect_events_prefix(const float* raw_dev, const int64_t* ranges_dev,
+                              const int32_t* firsts_dev, int32_t nreads, int32_t max_first,
+                              int32_t keep, float* events_dev, int32_t* counts_dev,
+                              void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Reference handle                                                          */
 /* ------------------------------------------------------------------------ */

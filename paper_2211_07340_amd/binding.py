@@ -60,6 +60,7 @@ def load_library():
         "sdtw_align_one": ([p, p, i32, p, p, p], C.c_int),
         "sdtw_align_one_wide": ([p, p, i32, C.c_int, p, p, p], C.c_int),
         "sdtw_detect_events": ([p, p, i32, i32, i32, p, p, p], C.c_int),
+        "sdtw_detect_events_prefix": ([p, p, p, i32, i32, i32, p, p, p], C.c_int),
         "sdtw_prepare_queries_ex": ([p, p, i32, dbl, p, p, p, p, p, p], C.c_int),
         "sdtw_stream_set_config": ([p, C.c_int, C.c_int], C.c_int),
         "sdtw_row_pool_trim": ([], C.c_int),
@@ -338,6 +339,26 @@ def detect_events(raw, offsets, trim: int = 50, keep: int = 250, events=None, co
                                              _dev(offsets, torch.int64, "offsets"), nreads,
                                              int(trim), int(keep), _dev(ev), _dev(cnt),
                                              _stream(stream)))
+    return ev, cnt
+
+
+def detect_events_prefix(raw, ranges, firsts, max_first: int, keep: int, events=None,
+                         counts=None, stream=None):
+    """sdtw_detect_events_prefix: final events of reads still being received.
+    ``ranges`` int64 [nreads, 2] (start, end) and ``firsts`` int32 [nreads]
+    device tensors; returns (events float32 [nreads, keep], counts int32)."""
+    torch = _torch()
+    nreads = firsts.numel()
+    if nreads < 1 or ranges.numel() != 2 * nreads:
+        raise ValueError("ranges must hold a (start, end) pair per read")
+    ev = events if events is not None else torch.empty((nreads, keep), dtype=torch.float32,
+                                                       device=raw.device)
+    cnt = counts if counts is not None else torch.empty(nreads, dtype=torch.int32,
+                                                        device=raw.device)
+    _check(load_library().sdtw_detect_events_prefix(
+        _dev(raw, torch.float32, "raw"), _dev(ranges, torch.int64, "ranges"),
+        _dev(firsts, torch.int32, "firsts"), nreads, int(max_first), int(keep), _dev(ev),
+        _dev(cnt), _stream(stream)))
     return ev, cnt
 
 

@@ -317,9 +317,26 @@ int sdtw_detect_events(const float* raw_dev, const int64_t* offsets_dev, int32_t
                    (int64_t)trim + keep <= kMaxEventList,
                "sdtw_detect_events: trim=%d keep=%d outside trim >= 0, 1 <= keep <= %d, "
                "trim + keep <= %d", trim, keep, SDTW_MAX_QUERY, kMaxEventList);
-  return check_hip(launch_detect_events(raw_dev, offsets_dev, nreads, trim, keep, events_dev,
-                                        counts_dev, (hipStream_t)stream),
+  return check_hip(launch_detect_events(raw_dev, offsets_dev, 1, nullptr, nreads, trim, keep, 0,
+                                        events_dev, counts_dev, (hipStream_t)stream),
                    "sdtw_detect_events: launch");
+}
+
+int sdtw_detect_events_prefix(const float* raw_dev, const int64_t* ranges_dev,
+                              const int32_t* firsts_dev, int32_t nreads, int32_t max_first,
+                              int32_t keep, float* events_dev, int32_t* counts_dev,
+                              void* stream) {
+  SDTW_REQUIRE(raw_dev && ranges_dev && firsts_dev && events_dev && counts_dev,
+               "sdtw_detect_events_prefix: null pointer");
+  SDTW_REQUIRE(nreads >= 1, "sdtw_detect_events_prefix: nreads=%d < 1", nreads);
+  SDTW_REQUIRE(max_first >= 0 && keep >= 1 && keep <= SDTW_MAX_QUERY &&
+                   (int64_t)max_first + keep <= kMaxEventList,
+               "sdtw_detect_events_prefix: max_first=%d keep=%d outside max_first >= 0, "
+               "1 <= keep <= %d, max_first + keep <= %d", max_first, keep, SDTW_MAX_QUERY,
+               kMaxEventList);
+  return check_hip(launch_detect_events(raw_dev, ranges_dev, 2, firsts_dev, nreads, max_first,
+                                        keep, 1, events_dev, counts_dev, (hipStream_t)stream),
+                   "sdtw_detect_events_prefix: launch");
 }
 
 // ---------------------------------------------------------------------------

@@ -149,8 +149,11 @@ int max_lds_bytes();
 // ---- launchers (events.hip) -------------------------------------------------
 // Event values of each read's raw samples (trim + keep <= kMaxEventList).
 constexpr int32_t kMaxEventList = 6144;
-hipError_t launch_detect_events(const float* raw, const int64_t* offs, int32_t nreads,
-                                int32_t trim, int32_t keep, float* out, int32_t* counts,
+// Read r: raw[offs[stride r] .. offs[stride r + 1]); events trims[r] (or trim)
+// onward; prefix: the samples are the start of a longer read.
+hipError_t launch_detect_events(const float* raw, const int64_t* offs, int32_t stride,
+                                const int32_t* trims, int32_t nreads, int32_t trim,
+                                int32_t keep, int32_t prefix, float* out, int32_t* counts,
                                 hipStream_t st);
 
 // ---- launchers (wide.hip) ---------------------------------------------------

@@ -126,45 +126,59 @@ __device__ __forceinline__ void step(Detector& d, Detector* other, int w, double
 // all R reads, then lane r runs the detectors of read r (R state machines
 // side by side instead of one lane at a time), then all lanes write the
 // events of each read in turn.
+//
+// Read r is raw[offs[stride r] .. offs[stride r + 1]) (stride 1: CSR offsets;
+// stride 2: start/end pairs).  Its events trim_r .. trim_r + keep - 1 are
+// wanted, trim_r = trims[r] (or `trim` without trims; trim_r <= trim).  With
+// `prefix` the samples are only the beginning of a longer read: the scan
+// stops where the t statistics still depend on samples not yet received
+// (position L - 5), and only events whose end boundary is final are written.
 template <int R>
 __global__ __launch_bounds__(64) void k_detect_events(const float* __restrict__ raw,
                                                       const int64_t* __restrict__ offs,
+                                                      int32_t stride,
+                                                      const int32_t* __restrict__ trims,
                                                       int32_t nreads, int32_t trim, int32_t keep,
-                                                      float* __restrict__ out,
+                                                      int32_t prefix, float* __restrict__ out,
                                                       int32_t* __restrict__ counts) {
   constexpr int B = kEvBlock / R;  // positions per block and read
   extern __shared__ double ev_lds[];
   double* ts = ev_lds;                              // [R][B]
   double* tl = ev_lds + R * B;                      // [R][B]
   int64_t* bs_all = (int64_t*)(ev_lds + 2 * R * B);  // [R][trim + keep]
-  __shared__ int32_t s_nb[R], s_active;
-  __shared__ int64_t s_end[R];
+  __shared__ int32_t s_nb[R], s_closed[R], s_active;
 
   const int lane = threadIdx.x;
   const int32_t r0 = (int32_t)blockIdx.x * R;
-  const int32_t cap = trim + keep;
+  const int32_t list = trim + keep;  // LDS words per read's list
   int64_t Lr[R];
   const float* xr[R];
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     const bool ok = r0 + k < nreads;
-    const int64_t a = ok ? offs[r0 + k] : 0;
-    Lr[k] = ok ? offs[r0 + k + 1] - a : 0;
+    const int64_t a = ok ? offs[(int64_t)stride * (r0 + k)] : 0;
+    Lr[k] = ok ? offs[(int64_t)stride * (r0 + k) + 1] - a : 0;
     xr[k] = raw + a;
   }
   // this lane's read (lanes >= R run no detector)
   const int me = lane < R ? lane : 0;
-  int64_t* bs = bs_all + (int64_t)me * cap;
+  int64_t* bs = bs_all + (int64_t)me * list;
   int64_t myL = 0;
 #pragma unroll
   for (int k = 0; k < R; ++k)
     if (k == me) myL = Lr[k];
+  // a first event outside [0, trim] marks the read as bad (count -1)
+  const int32_t first = trims && r0 + me < nreads ? trims[r0 + me] : trim;
+  const bool bad = first < 0 || first > trim;
+  const int32_t cap = (bad ? 0 : first) + keep;
+  // positions whose t statistics are final (all of them for a whole read)
+  const int64_t scanL = prefix ? (myL > kWLong - 1 ? myL - (kWLong - 1) : 0) : myL;
   Detector ds{-1, -1, INFINITY, false}, dl{-1, -1, INFINITY, false};
   int32_t nb = 0;
-  bool active = lane < R && myL > 0;
+  bool active = lane < R && scanL > 0 && !bad;
   if (lane < R) {
     s_nb[lane] = 0;
-    s_end[lane] = myL;
+    s_closed[lane] = prefix ? 0 : (myL > 0 ? 1 : 0);  // no samples, no event
   }
   for (int64_t b0 = 0;; b0 += B) {
     if (lane == 0) s_active = 0;
@@ -191,7 +205,7 @@ __global__ __launch_bounds__(64) void k_detect_events(const float* __restrict__ 
     }
     __syncthreads();
     if (active) {
-      const int64_t nblk = myL - b0 < B ? myL - b0 : B;
+      const int64_t nblk = scanL - b0 < B ? scanL - b0 : B;
       const double* mts = ts + me * B;
       const double* mtl = tl + me * B;
       for (int64_t j = 0; j < nblk; ++j) {
@@ -204,30 +218,39 @@ __global__ __launch_bounds__(64) void k_detect_events(const float* __restrict__ 
       if (dl.peak_pos >= 0 && dl.peak_pos < cut) cut = dl.peak_pos;
       s_nb[me] = nb;
       if (nb == cap && bs[cap - 1] < cut) {
-        s_end[me] = -1;  // stopped early: events 0 .. cap-1 are closed
+        s_closed[me] = cap;  // stopped early: events 0 .. cap-1 are closed
         active = false;
-      } else if (b0 + nblk >= myL) {
+      } else if (b0 + nblk >= scanL) {
         active = false;  // scanned to the end
+        if (prefix) {    // events whose end boundary is final
+          int32_t nf = 0;
+          while (nf < nb && bs[nf] < cut) ++nf;
+          s_closed[me] = nf;
+        } else {         // the last event ends at L
+          s_closed[me] = nb + 1;
+        }
       }
     }
     __syncthreads();
   }
-  // events of each read: cut_0 = 0, cut_j = bs[j-1]; the last one ends at L
-  // when the read was scanned to its end
+  // events of each read: cut_0 = 0, cut_j = bs[j-1], and L after the last
   for (int k = 0; k < R; ++k) {
     const int32_t r = r0 + k;
     if (r >= nreads) break;
-    const int64_t* kb = bs_all + (int64_t)k * cap;
+    const int64_t* kb = bs_all + (int64_t)k * list;
     const int32_t knb = s_nb[k];
     const int64_t L = Lr[k];
     const float* __restrict__ x = xr[k];
-    const int32_t closed = s_end[k] < 0 ? cap : (L > 0 ? knb + 1 : 0);  // no samples, no event
-    const int32_t hi = closed < cap ? closed : cap;
-    const int32_t n_out = hi > trim ? hi - trim : 0;
+    const int32_t tr0 = trims ? trims[r] : trim;
+    const bool kbad = tr0 < 0 || tr0 > trim;
+    const int32_t tr = kbad ? 0 : tr0;
+    const int32_t closed = kbad ? 0 : s_closed[k];
+    const int32_t hi = closed < tr + keep ? closed : tr + keep;
+    const int32_t n_out = hi > tr ? hi - tr : 0;
     for (int32_t e = lane; e < keep; e += 64) {
       float v = 0.0f;
       if (e < n_out) {
-        const int32_t j = trim + e;
+        const int32_t j = tr + e;
         const int64_t lo = j == 0 ? 0 : kb[j - 1];
         const int64_t up = j < knb ? kb[j] : L;
         double sum = 0.0;
@@ -236,7 +259,7 @@ __global__ __launch_bounds__(64) void k_detect_events(const float* __restrict__ 
       }
       out[(int64_t)r * keep + e] = v;
     }
-    if (lane == 0) counts[r] = n_out;
+    if (lane == 0) counts[r] = kbad ? -1 : n_out;
   }
 }
 
@@ -263,21 +286,22 @@ static int reads_per_wave(int32_t nreads, int32_t trim, int32_t keep) {
   return rpw;
 }
 
-hipError_t launch_detect_events(const float* raw, const int64_t* offs, int32_t nreads,
-                                int32_t trim, int32_t keep, float* out, int32_t* counts,
+hipError_t launch_detect_events(const float* raw, const int64_t* offs, int32_t stride,
+                                const int32_t* trims, int32_t nreads, int32_t trim,
+                                int32_t keep, int32_t prefix, float* out, int32_t* counts,
                                 hipStream_t st) {
   const int rpw = reads_per_wave(nreads, trim, keep);
   const size_t lds = lds_for(rpw, trim, keep);
   const dim3 grid((unsigned)((nreads + rpw - 1) / rpw));
   if (rpw == 4)
-    hipLaunchKernelGGL(k_detect_events<4>, grid, dim3(64), lds, st, raw, offs, nreads, trim, keep,
-                       out, counts);
+    hipLaunchKernelGGL(k_detect_events<4>, grid, dim3(64), lds, st, raw, offs, stride, trims,
+                       nreads, trim, keep, prefix, out, counts);
   else if (rpw == 2)
-    hipLaunchKernelGGL(k_detect_events<2>, grid, dim3(64), lds, st, raw, offs, nreads, trim, keep,
-                       out, counts);
+    hipLaunchKernelGGL(k_detect_events<2>, grid, dim3(64), lds, st, raw, offs, stride, trims,
+                       nreads, trim, keep, prefix, out, counts);
   else
-    hipLaunchKernelGGL(k_detect_events<1>, grid, dim3(64), lds, st, raw, offs, nreads, trim, keep,
-                       out, counts);
+    hipLaunchKernelGGL(k_detect_events<1>, grid, dim3(64), lds, st, raw, offs, stride, trims,
+                       nreads, trim, keep, prefix, out, counts);
   return hipGetLastError();
 }
 

@@ -15,9 +15,12 @@ import pytest
 import synth
 from oracle import events as ev
 
-def kernel_model(x, trim, keep, BLOCK=512):
+def kernel_model(x, trim, keep, BLOCK=512, prefix=False):
+    """prefix: x is the start of a longer read (scan to L - 5, final events
+    only)."""
     ts, tl = ev.tstat(x, 3), ev.tstat(x, 6)
     L, cap = x.size, trim + keep
+    scan = max(L - 5, 0) if prefix else L
     det = {k: dict(masked_to=-1, peak_pos=-1, peak_val=math.inf, valid=False)
            for k in ("s", "l")}
     bs = []
@@ -53,8 +56,9 @@ def kernel_model(x, trim, keep, BLOCK=512):
             d.update(peak_pos=-1, peak_val=v, valid=False)
 
     stopped = False
-    for b0 in range(0, L, BLOCK):
-        end = min(L, b0 + BLOCK)
+    cut = 0
+    for b0 in range(0, scan, BLOCK):
+        end = min(scan, b0 + BLOCK)
         for i in range(b0, end):
             step("s", 3, ev.T_SHORT, i, ts[i])
             step("l", 6, ev.T_LONG, i, tl[i])
@@ -65,7 +69,12 @@ def kernel_model(x, trim, keep, BLOCK=512):
         if len(bs) == cap and bs[-1] < cut:
             stopped = True
             break
-    closed = cap if stopped else (len(bs) + 1 if L > 0 else 0)
+    if stopped:
+        closed = cap
+    elif prefix:  # events whose end boundary is final
+        closed = sum(1 for b in bs if b < cut)
+    else:
+        closed = len(bs) + 1 if L > 0 else 0
     n_out = max(min(closed, cap) - trim, 0)
     out = []
     for k in range(n_out):
@@ -101,3 +110,21 @@ def test_reads_shorter_than_windows():
         x = np.linspace(80, 100, L).astype(np.float32)
         got, _ = kernel_model(x, 0, 5)
         assert np.array_equal(got, ev.query_events(x, 0, 5))
+
+
+@pytest.mark.parametrize("first,keep", [(0, 400), (50, 250), (130, 40), (0, 6000)])
+def test_prefix_events_are_those_of_the_whole_read(first, keep):
+    # a read still arriving: the events written for any prefix are the whole
+    # read's events from `first` on, as many as are final
+    g = synth.make_genome(synth.SMALL_GENOME, synth.SMALL_GENOME)
+    raw = synth.simulate_raw(g, synth.make_level_table(), 3, 300, 0.6, first + keep)
+    rng = np.random.default_rng(first)
+    for r in range(raw.nreads):
+        x = raw.values[raw.offsets[r]:raw.offsets[r + 1]]
+        full = ev.events(x)
+        for L in sorted(set(rng.integers(0, x.size + 1, size=6).tolist() + [0, 3, x.size])):
+            got, _ = kernel_model(x[:L], first, keep, 128, prefix=True)
+            assert np.array_equal(got, full[first:first + got.size]), (r, L)
+        # with the whole read given, only the last event or two stay open
+        got, _ = kernel_model(x, first, keep, 128, prefix=True)
+        assert got.size >= min(keep, max(full.size - first - 3, 0))

@@ -88,6 +88,38 @@ def test_large_batches_share_waves(dev, nreads):
         assert not e[r, c[r]:].any()
 
 
+def test_prefixes_of_reads_being_received(dev):
+    # the events written for a prefix are the whole read's, from `first` on
+    g = synth.make_genome(synth.SMALL_GENOME, synth.SMALL_GENOME)
+    raw = synth.simulate_raw(g, synth.make_level_table(), 10, 300, 0.5, 404)
+    rng = np.random.default_rng(5)
+    ranges, firsts, whole = [], [], []
+    for r in range(raw.nreads):
+        a, b = int(raw.offsets[r]), int(raw.offsets[r + 1])
+        full = ev.events(raw.values[a:b])
+        for L in (0, 4, 5, 6, 7, 40, int(rng.integers(100, b - a)), b - a):
+            ranges.append((a, a + L))
+            firsts.append(int(rng.integers(0, 60)))
+            whole.append(full)
+    ranges.append((0, 100))  # a first event beyond max_first: count -1
+    firsts.append(61)
+    note(f"prefix events: {len(firsts)} prefixes")
+    rg = torch.tensor(ranges, dtype=torch.int64, device=dev)
+    fs = torch.tensor(firsts, dtype=torch.int32, device=dev)
+    x = torch.from_numpy(raw.values).to(dev)
+    e, c = sd.detect_events_prefix(x, rg, fs, 60, 300)
+    torch.cuda.synchronize()
+    e, c = e.cpu().numpy(), c.cpu().numpy()
+    for i, full in enumerate(whole):
+        f, n = firsts[i], int(c[i])
+        assert 0 <= n <= 300
+        assert np.array_equal(e[i, :n], full[f:f + n]), (i, ranges[i], f, n)
+        assert not e[i, n:].any()
+        if ranges[i][1] - ranges[i][0] < 6:
+            assert n == 0
+    assert c[-1] == -1 and not e[-1].any()
+
+
 def test_noise_free_steps(dev):
     rng = np.random.default_rng(9)
     lens = rng.integers(3, 16, size=400)
