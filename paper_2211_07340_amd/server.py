@@ -43,6 +43,18 @@ This module simulates the channels and runs the decisions through the C ABI:
 
 ``mode="recompute"`` aligns every chunk's whole prefix from scratch instead
 (a fresh stream extended by the full prefix), for comparison.
+
+``ServerConfig(raw=True)`` serves raw current instead of events (targets from
+``make_raw_targets``): every chunk period a channel's read has
+``chunk_samples`` more samples (the pool's samples are resident on the
+device, standing for the sequencer's signal buffer), and each batch first
+cuts the samples received so far into events on the device
+(sdtw_detect_events_prefix: only events that later samples cannot change,
+from event ``trim_events`` + rows already aligned), then normalises and
+extends with them.  A read's first extension waits for ``chunk_events``
+final events (its normalisation statistics); later ones take whatever new
+final events there are.  A read without new events waits for its next
+chunk.
 """
 from __future__ import annotations
 
@@ -71,6 +83,9 @@ class ServerConfig:
     prewarm_rows: bool = True          # open (and close) rows for every channel before serving
     decision: str = "cost"             # "cost" or "mapq" (see the module doc)
     mapq_window: int = 2000            # columns around the best end excluded for the runner-up
+    raw: bool = False                  # chunks of raw samples, events detected on the device
+    chunk_samples: int = 2400          # raw mode: samples per channel per chunk period
+    trim_events: int = 50              # raw mode: adaptor events dropped at a read's start
 
 
 @dataclass
@@ -84,6 +99,8 @@ class Target:
     q_min: float = float("nan")        # mapping-quality threshold (0..60)
     streams: list = field(default_factory=list)  # HIP streams of this target's work (set
                                                  # by the server that serves it)
+    raw_dev: object = None             # raw mode: the pool's samples on the device
+    raw_offs: object = None            # raw mode: int64 offsets of the pool's reads
 
 
 @dataclass
@@ -183,6 +200,8 @@ class ReadUntilServer:
             raise ValueError("mode must be 'extend' or 'recompute'")
         if self.cfg.decision not in ("cost", "mapq"):
             raise ValueError("decision must be 'cost' or 'mapq'")
+        if self.cfg.raw and (mode != "extend" or any(t.raw_dev is None for t in targets)):
+            raise ValueError("raw mode extends resident rows of targets from make_raw_targets")
         self.mode = mode
         self.rng = np.random.default_rng(self.cfg.seed)
         k = max(1, self.cfg.streams_per_target)
@@ -208,10 +227,21 @@ class ReadUntilServer:
             cost, second = [], []
             for g0 in range(0, pick.size, group):
                 sub = pick[g0:g0 + group]
-                raw = np.concatenate([t.reads[i][:M] for i in sub]).astype(np.float32)
                 offs = np.arange(sub.size + 1, dtype=np.int64) * M
-                _, codes, _ = sd.prepare_queries(torch.from_numpy(raw).to(dev),
-                                                 torch.from_numpy(offs).to(dev), self.cfg.scale)
+                if self.cfg.raw:  # the first chunk_events events after the adaptor
+                    rg = np.stack([t.raw_offs[sub], t.raw_offs[sub + 1]], 1).astype(np.int64)
+                    fs = np.full(sub.size, self.cfg.trim_events, np.int32)
+                    ev, cnt = sd.detect_events_prefix(
+                        t.raw_dev, torch.from_numpy(rg).to(dev), torch.from_numpy(fs).to(dev),
+                        self.cfg.trim_events, M)
+                    if int(cnt.min().item()) < M:
+                        raise ValueError("calibration reads have too few events")
+                    raw_d = ev.reshape(-1)
+                else:
+                    raw_d = torch.from_numpy(
+                        np.concatenate([t.reads[i][:M] for i in sub]).astype(np.float32)).to(dev)
+                _, codes, _ = sd.prepare_queries(raw_d, torch.from_numpy(offs).to(dev),
+                                                 self.cfg.scale)
                 streams = [sd.Stream(t.ref) for _ in sub]
                 try:
                     c, _ = sd.stream_extend(streams, codes, offs)
@@ -381,9 +411,20 @@ class ReadUntilServer:
                     keep_waiting.extend(items)
                 else:
                     th = time.perf_counter()
-                    self._submit(ti, items, chan_read, inflight, dev)
+                    not_ready = self._submit(ti, items, chan_read, inflight, dev)
                     timed("submit " + self.targets[ti].name, th)
                     submitted = True
+                    for _, c in not_ready:  # raw mode: no new final events yet
+                        rd = chan_read[c]
+                        if rd.chunks_done * cfg.chunk_samples >= rd.raw.size + cfg.chunk_samples:
+                            # the read is over without enough events: rejected
+                            if rd.handle is not None:
+                                rd.handle.close()
+                                rd.handle = None
+                            chan_read[c] = self._new_read(time.perf_counter())
+                            heapq.heappush(arrivals, (time.perf_counter() + P, c))
+                        else:
+                            heapq.heappush(arrivals, (rd.start + (rd.chunks_done + 1) * P, c))
             waiting = keep_waiting
             if not submitted:
                 nxt = arrivals[0][0] if arrivals else now + 0.002
@@ -444,7 +485,10 @@ class ReadUntilServer:
         return None
 
     def _submit(self, ti, items, chan_read, inflight, dev):
-        """Normalise and extend the ready chunks of one target in one launch."""
+        """Normalise and extend the ready chunks of one target in one launch.
+        Returns the reads that could not be extended yet (raw mode)."""
+        if self.cfg.raw:
+            return self._submit_raw(ti, items, chan_read, inflight, dev)
         torch = self.torch
         cfg = self.cfg
         t = self.targets[ti]
@@ -524,6 +568,126 @@ class ReadUntilServer:
         inflight.append(_Tick(ev, ti, slot, out, host[0], host[1], host[2], host[3],
                               time.perf_counter(),
                               float(sum(lens)) * t.ref.n, scratch))
+        return []
+
+    def _submit_raw(self, ti, items, chan_read, inflight, dev):
+        """Raw mode: events of the samples received so far, then the same
+        normalisation and extension as for event chunks."""
+        torch = self.torch
+        cfg = self.cfg
+        t = self.targets[ti]
+        E = cfg.chunk_events
+        keep = 2 * E
+        slot = self._free_slot(ti, inflight)
+        hs = t.streams[slot]
+        n = len(items)
+        rg = np.empty((n, 2), np.int64)
+        fs = np.empty(n, np.int32)
+        for k, (_, c) in enumerate(items):
+            rd = chan_read[c]
+            a, b = int(t.raw_offs[rd.pool_idx]), int(t.raw_offs[rd.pool_idx + 1])
+            rg[k] = (a, min(b, a + (rd.chunks_done + 1) * cfg.chunk_samples))
+            fs[k] = cfg.trim_events + rd.rows
+        waiting = []
+        with torch.cuda.stream(hs):
+            rg_d = torch.from_numpy(rg).pin_memory().to(dev, non_blocking=True)
+            fs_d = torch.from_numpy(fs).pin_memory().to(dev, non_blocking=True)
+            ev, cnt = sd.detect_events_prefix(t.raw_dev, rg_d, fs_d,
+                                              cfg.trim_events + cfg.max_events, keep, stream=hs)
+            cnt_h = torch.empty(n, dtype=torch.int32, pin_memory=True)
+            cnt_h.copy_(cnt, non_blocking=True)
+            hs.synchronize()  # this stream had no batch in flight: only the detection
+            cnt_np = cnt_h.numpy().copy()
+            take = np.zeros(n, np.int64)
+            for k, (_, c) in enumerate(items):
+                rd = chan_read[c]
+                room = cfg.max_events - rd.rows
+                got = min(int(cnt_np[k]), room)
+                if rd.rows == 0:
+                    take[k] = E if got >= E else 0  # the first chunk fixes the statistics
+                else:
+                    take[k] = got
+            entries, code_parts, lens = [], [], []
+            for fresh in (True, False):
+                sel = [k for k, (_, c) in enumerate(items)
+                       if take[k] > 0 and (chan_read[c].rows == 0) == fresh]
+                if not sel:
+                    continue
+                sel_d = torch.tensor(sel, dtype=torch.int64, device=dev)
+                tk = torch.from_numpy(take[sel]).to(dev, non_blocking=True)
+                rows_ev = ev.index_select(0, sel_d)
+                mask = torch.arange(keep, device=dev)[None, :] < tk[:, None]
+                vals = rows_ev[mask]  # the taken events, read after read
+                offs_np = np.zeros(len(sel) + 1, np.int64)
+                np.cumsum(take[sel], out=offs_np[1:])
+                offs = torch.from_numpy(offs_np).to(dev, non_blocking=True)
+                group = [items[k] for k in sel]
+                if fresh:
+                    _, codes, _, st = sd.prepare_queries_ex(vals, offs, cfg.scale, stream=hs)
+                    for j, (_, c) in enumerate(group):
+                        chan_read[c].stats = st[j:j + 1]
+                else:
+                    st_in = torch.cat([chan_read[c].stats for _, c in group])
+                    _, codes, _, _ = sd.prepare_queries_ex(vals, offs, cfg.scale, st_in,
+                                                           stream=hs)
+                code_parts.append(codes)
+                lens += take[sel].tolist()
+                entries += [(c, chan_read[c], arr, int(take[k])) for k, (arr, c) in
+                            zip(sel, group)]
+            for k, (arr, c) in enumerate(items):
+                if take[k] == 0:
+                    waiting.append((arr, c))
+            if not entries:
+                for _, c in waiting:
+                    chan_read[c].chunks_done += 1
+                return waiting
+            codes = torch.cat(code_parts) if len(code_parts) > 1 else code_parts[0]
+            offs_np = np.zeros(len(lens) + 1, np.int64)
+            np.cumsum(lens, out=offs_np[1:])
+            handles = [rd.handle for _, rd, _, _ in entries]
+            cost, end = sd.stream_extend(handles, codes, offs_np, stream=hs)
+            pinned = [cost, end]
+            if cfg.decision == "mapq":
+                _, _, c2, e2 = sd.stream_best_two(handles, cfg.mapq_window, stream=hs)
+                pinned += [c2, e2]
+            host = []
+            for x in pinned:
+                h = torch.empty(x.shape, dtype=x.dtype, pin_memory=True)
+                h.copy_(x, non_blocking=True)
+                host.append(h)
+            host += [None] * (4 - len(host))
+            evt = torch.cuda.Event()
+            evt.record(hs)
+        out = []
+        for c, rd, arr, tk in entries:
+            rd.chunks_done += 1
+            rd.rows += tk
+            out.append((c, rd, arr, rd.rows))
+        for _, c in waiting:
+            chan_read[c].chunks_done += 1
+        inflight.append(_Tick(evt, ti, slot, out, host[0], host[1], host[2], host[3],
+                              time.perf_counter(), float(sum(lens)) * t.ref.n, []))
+        return waiting
+
+
+def make_raw_targets(specs, torch_device, k: int = 6, scale: float = 64.0):
+    """Raw-mode targets from (name, genome uint8 array, level table, raw
+    samples float32 (reads concatenated), int64 offsets, on-target flags):
+    the reference is prepared on the device and the pool's samples are
+    uploaded once."""
+    torch = __import__("torch")
+    out = []
+    for name, genome, table, values, offsets, on in specs:
+        g = torch.from_numpy(genome).to(torch_device)
+        t = torch.from_numpy(table).to(torch_device)
+        _, codes, _ = sd.prepare_reference(g, t, k, scale)
+        offs = np.asarray(offsets, np.int64)
+        reads = [values[offs[r]:offs[r + 1]] for r in range(offs.size - 1)]
+        tg = Target(name, sd.Reference(codes), reads, np.asarray(on, bool))
+        tg.raw_dev = torch.from_numpy(np.ascontiguousarray(values, np.float32)).to(torch_device)
+        tg.raw_offs = offs
+        out.append(tg)
+    return out
 
 
 def make_targets(specs, torch_device, k: int = 6, scale: float = 64.0):

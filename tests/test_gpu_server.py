@@ -76,3 +76,53 @@ def test_served_results_match_oracle(decision):
             assert (r[5], r[6]) == want, (t, r)
     for t in targets:
         t.ref.close()
+
+
+def test_raw_mode_served_results_match_oracle():
+    # chunks of raw samples: events detected on the device from the samples
+    # received so far; every served result equals the oracle's on the read's
+    # first events (the oracle's events of the whole read: events written for
+    # a prefix are final)
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import events as oev
+    from paper_2211_07340_amd import server as srv
+    dev = torch.device("cuda:0")
+    table = synth.make_level_table()
+    specs, codes_of, raws = [], [], []
+    for i, L in enumerate((synth.SMALL_GENOME, 600_000)):
+        genome = synth.make_genome(L, L)
+        rr = synth.simulate_raw(genome, table, 24, 800, 0.5, 700 + i)
+        specs.append((f"{L}-base", genome, table, rr.values, rr.offsets, rr.on_target))
+        _, codes, _ = oracle.prepare_reference(genome, table, 6)
+        codes_of.append(codes)
+        raws.append(rr)
+    targets = srv.make_raw_targets(specs, dev)
+    cfg = srv.ServerConfig(channels=24, raw=True, max_events=1200, min_reject_events=800)
+    rec = []
+    server = srv.ReadUntilServer(targets, cfg, record=rec)
+    server.calibrate(n_each=8)
+    res = server.run(3.0, 0.5)
+    print("raw mode", {k: res[k] for k in ("decisions", "decision_accuracy", "tau")}, flush=True)
+    assert res["decisions"] > 10 and res["decision_accuracy"] > 0.9, res
+    rng = np.random.default_rng(1)
+    for t in range(2):
+        mine = [r for r in rec if r[0] == t]
+        assert mine, f"nothing served for target {t}"
+        first_rows = {}
+        for r in mine:
+            first_rows[r[1]] = min(first_rows.get(r[1], 10 ** 9), r[2])
+        pick = [mine[i] for i in rng.choice(len(mine), min(10, len(mine)), replace=False)]
+        events = {}
+        for _, pi, rows, cost, end, _, _ in pick:
+            if pi not in events:
+                rr = raws[t]
+                events[pi] = oev.events(rr.values[rr.offsets[pi]:rr.offsets[pi + 1]])
+            e = events[pi][50:50 + rows]
+            assert e.size == rows
+            assert first_rows[pi] == 400
+            mean, sdv = oracle.zstats(e[:400])
+            q, _ = oracle.quantize(oracle.zapply(e, mean, sdv), 64.0)
+            assert (cost, end) == oracle.sdtw_i64(q, codes_of[t]), (t, pi, rows)
+    for t in targets:
+        t.ref.close()
