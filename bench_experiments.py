@@ -31,6 +31,12 @@ events   Pre-processing on the device (section 4.1's event detection, prefix
          29,903-base genome: device time per stage (HIP events, median of
          --reps), raw samples per second, and the share of each stage (the
          paper's pre-processing takes about 30% of its run time, section 6).
+serving_raw  The Read Until server on raw samples (events detected on the
+         device from the samples received so far, every batch), both
+         targets, 512 channels, 2,400 samples per channel per 0.1 s chunk
+         period, reads of 30 adaptor levels and 1,400 bases: reads/s,
+         accuracy, decision latency per target; beside the same server on
+         pre-detected events.
 wide     The whole-device single-query scan alone (sdtw_align_one_wide) on
          one genome length (--genome, default 5,000,000 bases) at one width
          (--cols, default automatic): device time per call, median of
@@ -40,7 +46,7 @@ best_two The runner-up search alone (sdtw_stream_best_two) over 1 to 256
          device time and the rate at which it reads the rows (4 bytes per
          column per row, the bound being HBM at 8 TB/s).
 
-Usage: python bench_experiments.py latency|scale|serving|decision|best_two|wide|events
+Usage: python bench_experiments.py latency|scale|serving|serving_raw|decision|best_two|wide|events
                                    [--max-genome BASES] [--genome BASES] [--cols C]
                                    [--reps R]
 """
@@ -241,6 +247,37 @@ def decision(args):
             t.ref.close()
 
 
+def serving_raw(args):
+    import torch
+
+    import synth
+    from paper_2211_07340_amd import server as srv
+    dev = torch.device("cuda:0")
+    table = synth.make_level_table()
+    specs = []
+    for i, (name, L) in enumerate((("29,903-base", synth.SMALL_GENOME),
+                                   ("5,000,000-base", synth.LARGE_GENOME))):
+        genome = synth.make_genome(L, L)
+        rr = synth.simulate_raw(genome, table, 512, 1400, 0.5, 4600 + i)
+        specs.append((name, genome, table, rr.values, rr.offsets, rr.on_target))
+    targets = srv.make_raw_targets(specs, dev)
+    for ch in (128, 512):
+        cfg = srv.ServerConfig(channels=ch, row_budget_bytes=64 << 30, raw=True)
+        server = srv.ReadUntilServer(targets, cfg, mode="extend")
+        server.calibrate()
+        r = server.run(8.0, 3.0)
+        print(json.dumps({"experiment": "serving from raw samples", "channels": ch,
+                          "chunk_samples": cfg.chunk_samples,
+                          **{k: r[k] for k in ("reads_per_s", "chunks_per_s", "gcups",
+                                               "decision_accuracy", "mean_events_at_decision",
+                                               "decision_latency_p50_ms",
+                                               "decision_latency_p99_ms")},
+                          "per_target": r["per_target"],
+                          "host_loop_ms": r["host_loop_ms"]}), flush=True)
+    for t in targets:
+        t.ref.close()
+
+
 def events(args):
     import torch
 
@@ -338,8 +375,8 @@ def best_two(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("experiment",
-                    choices=["latency", "scale", "serving", "decision", "best_two", "wide",
-                             "events"])
+                    choices=["latency", "scale", "serving", "serving_raw", "decision",
+                             "best_two", "wide", "events"])
     ap.add_argument("--max-genome", type=int, default=10_000_000)
     ap.add_argument("--genome", type=int, default=5_000_000, help="wide: genome bases")
     ap.add_argument("--cols", type=int, default=0, help="wide: columns per thread (0: auto)")
@@ -350,7 +387,7 @@ def main():
     t0 = time.perf_counter()
     {"latency": latency, "scale": scale, "serving": serving,
      "decision": decision, "best_two": best_two, "wide": wide,
-     "events": events}[args.experiment](args)
+     "events": events, "serving_raw": serving_raw}[args.experiment](args)
     print(json.dumps({"done": args.experiment, "seconds": round(time.perf_counter() - t0, 1)}),
           flush=True)
 
