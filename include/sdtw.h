@@ -187,6 +187,38 @@ int sdtw_detect_events_prefix(const float* raw_dev, const int64_t* ranges_dev,
                               int32_t keep, float* events_dev, int32_t* counts_dev,
                               void* stream);
 
+/*
+ * Event detection for reads received chunk by chunk, scanning each sample
+ * once: the detectors' state of every read is kept between calls in
+ * caller-owned device memory (sdtw_event_state_bytes() per read).  Events
+ * are delivered in order as soon as they are final (later samples cannot
+ * change them), and are the same as sdtw_detect_events on the whole read.
+ *   sdtw_event_state_init: resets states_dev slots slots_dev[0 .. n) (a
+ *     kernel; call it when a read starts on a slot, in order on `stream`).
+ *   sdtw_detect_events_continue:
+ *     ranges_dev  int64[2 * nreads]: read r's samples so far are
+ *                 raw_dev[ranges[2r] .. ranges[2r+1]); the start stays the
+ *                 same from call to call, the end only grows.
+ *     slots_dev   int32[nreads]: read r's state is slot slots[r] of
+ *                 states_dev; distinct within a call.
+ *     trim        the read's first `trim` events (the adaptor) are consumed
+ *                 and not written.
+ *     keep        at most keep events written per read and call (1 <= keep
+ *                 <= SDTW_MAX_QUERY); the rest stay for the next call.
+ *     events_dev  out float32[nreads * keep]: the read's next counts[r]
+ *                 events, then zeros.
+ *     counts_dev  out int32[nreads]; -1 if more than 32 boundaries were
+ *                 waiting to be delivered (keep too small for the samples
+ *                 given): the read's state is then unusable.
+ * Only kernels are enqueued (no allocation).
+ */
+int64_t sdtw_event_state_bytes(void);
+int sdtw_event_state_init(void* states_dev, const int32_t* slots_dev, int32_t n, void* stream);
+int sdtw_detect_events_continue(const float* raw_dev, const int64_t* ranges_dev,
+                                const int32_t* slots_dev, void* states_dev, int32_t nreads,
+                                int32_t trim, int32_t keep, float* events_dev,
+                                int32_t* counts_dev, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Reference handle                                                          */
 /* ------------------------------------------------------------------------ */

@@ -61,6 +61,9 @@ def load_library():
         "sdtw_align_one_wide": ([p, p, i32, C.c_int, p, p, p], C.c_int),
         "sdtw_detect_events": ([p, p, i32, i32, i32, p, p, p], C.c_int),
         "sdtw_detect_events_prefix": ([p, p, p, i32, i32, i32, p, p, p], C.c_int),
+        "sdtw_event_state_bytes": ([], C.c_int64),
+        "sdtw_event_state_init": ([p, p, i32, p], C.c_int),
+        "sdtw_detect_events_continue": ([p, p, p, p, i32, i32, i32, p, p, p], C.c_int),
         "sdtw_prepare_queries_ex": ([p, p, i32, dbl, p, p, p, p, p, p], C.c_int),
         "sdtw_stream_set_config": ([p, C.c_int, C.c_int], C.c_int),
         "sdtw_row_pool_trim": ([], C.c_int),
@@ -360,6 +363,45 @@ def detect_events_prefix(raw, ranges, firsts, max_first: int, keep: int, events=
         _dev(firsts, torch.int32, "firsts"), nreads, int(max_first), int(keep), _dev(ev),
         _dev(cnt), _stream(stream)))
     return ev, cnt
+
+
+class EventStates:
+    """Device memory for the detector state of `n` reads received chunk by
+    chunk (sdtw_detect_events_continue)."""
+
+    def __init__(self, n: int, device=None):
+        torch = _torch()
+        dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        nbytes = int(load_library().sdtw_event_state_bytes())
+        self.n = int(n)
+        self.buf = torch.zeros(self.n * nbytes, dtype=torch.uint8, device=dev)
+
+    def reset(self, slots, stream=None):
+        """Start new reads on these slots (int32 device tensor)."""
+        torch = _torch()
+        if slots.numel() == 0:
+            return
+        _check(load_library().sdtw_event_state_init(_dev(self.buf), _dev(slots, torch.int32,
+                                                                        "slots"),
+                                                    slots.numel(), _stream(stream)))
+
+    def detect(self, raw, ranges, slots, trim: int, keep: int, events=None, counts=None,
+               stream=None):
+        """(events float32 [n, keep], counts int32 [n]) for reads whose
+        samples so far are ranges (int64 [n, 2]) on state slots (int32 [n])."""
+        torch = _torch()
+        n = slots.numel()
+        if n < 1 or ranges.numel() != 2 * n:
+            raise ValueError("ranges must hold a (start, end) pair per read")
+        ev = events if events is not None else torch.empty((n, keep), dtype=torch.float32,
+                                                           device=raw.device)
+        cnt = counts if counts is not None else torch.empty(n, dtype=torch.int32,
+                                                            device=raw.device)
+        _check(load_library().sdtw_detect_events_continue(
+            _dev(raw, torch.float32, "raw"), _dev(ranges, torch.int64, "ranges"),
+            _dev(slots, torch.int32, "slots"), _dev(self.buf), n, int(trim), int(keep),
+            _dev(ev), _dev(cnt), _stream(stream)))
+        return ev, cnt
 
 
 def align_one_wide(ref: Reference, q, cols: int = 0, cost=None, end=None, stream=None):

@@ -339,6 +339,31 @@ int sdtw_detect_events_prefix(const float* raw_dev, const int64_t* ranges_dev,
                    "sdtw_detect_events_prefix: launch");
 }
 
+int64_t sdtw_event_state_bytes(void) { return (int64_t)event_state_bytes(); }
+
+int sdtw_event_state_init(void* states_dev, const int32_t* slots_dev, int32_t n, void* stream) {
+  SDTW_REQUIRE(states_dev && slots_dev, "sdtw_event_state_init: null pointer");
+  SDTW_REQUIRE(n >= 1, "sdtw_event_state_init: n=%d < 1", n);
+  return check_hip(launch_event_state_init(states_dev, slots_dev, n, (hipStream_t)stream),
+                   "sdtw_event_state_init: launch");
+}
+
+int sdtw_detect_events_continue(const float* raw_dev, const int64_t* ranges_dev,
+                                const int32_t* slots_dev, void* states_dev, int32_t nreads,
+                                int32_t trim, int32_t keep, float* events_dev,
+                                int32_t* counts_dev, void* stream) {
+  SDTW_REQUIRE(raw_dev && ranges_dev && slots_dev && states_dev && events_dev && counts_dev,
+               "sdtw_detect_events_continue: null pointer");
+  SDTW_REQUIRE(nreads >= 1, "sdtw_detect_events_continue: nreads=%d < 1", nreads);
+  SDTW_REQUIRE(trim >= 0 && keep >= 1 && keep <= SDTW_MAX_QUERY,
+               "sdtw_detect_events_continue: trim=%d keep=%d outside trim >= 0, "
+               "1 <= keep <= %d", trim, keep, SDTW_MAX_QUERY);
+  return check_hip(launch_events_continue(raw_dev, ranges_dev, slots_dev, states_dev, nreads,
+                                          trim, keep, events_dev, counts_dev,
+                                          (hipStream_t)stream),
+                   "sdtw_detect_events_continue: launch");
+}
+
 // ---------------------------------------------------------------------------
 // reference
 // ---------------------------------------------------------------------------

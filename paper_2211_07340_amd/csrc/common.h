@@ -156,6 +156,15 @@ hipError_t launch_detect_events(const float* raw, const int64_t* offs, int32_t s
                                 int32_t keep, int32_t prefix, float* out, int32_t* counts,
                                 hipStream_t st);
 
+// Reads received chunk by chunk: per-read detector state (event_state_bytes()
+// each) kept between calls.
+size_t event_state_bytes();
+hipError_t launch_event_state_init(void* states, const int32_t* slots, int32_t n,
+                                   hipStream_t st);
+hipError_t launch_events_continue(const float* raw, const int64_t* ranges, const int32_t* slots,
+                                  void* states, int32_t nreads, int32_t trim, int32_t keep,
+                                  float* out, int32_t* counts, hipStream_t st);
+
 // ---- launchers (wide.hip) ---------------------------------------------------
 // One int16 query over every compute unit: row scans with look-back between
 // tiles of 256 * cols columns (cols in {8, 16, 32, 64}).  `scratch` holds

@@ -89,10 +89,28 @@ __device__ __forceinline__ void insert_bound(int64_t* bs, int32_t& n, int32_t ca
   if (n < cap) ++n;
 }
 
-// One detector step at position i with statistic v (lane 0 only).
+// Insert b into the sorted distinct list bs[0..n) of at most cap entries;
+// a full list sets *overflow instead (nothing may be dropped).
+__device__ __forceinline__ void insert_pending(int64_t* bs, int32_t& n, int32_t cap, int64_t b,
+                                               int32_t* overflow) {
+  int32_t k = n;
+  while (k > 0 && bs[k - 1] > b) --k;
+  if (k > 0 && bs[k - 1] == b) return;
+  if (n == cap) {
+    *overflow = 1;
+    return;
+  }
+  for (int32_t j = n; j > k; --j) bs[j] = bs[j - 1];
+  bs[k] = b;
+  ++n;
+}
+
+// One detector step at position i with statistic v (lane 0 only).  Emitted
+// boundaries go to the truncating list, or with `overflow` to the pending
+// list.
 __device__ __forceinline__ void step(Detector& d, Detector* other, int w, double threshold,
                                      int64_t i, double v, int64_t* bs, int32_t& nb,
-                                     int32_t cap) {
+                                     int32_t cap, int32_t* overflow = nullptr) {
   if (d.masked_to >= i) return;
   if (d.peak_pos < 0) {
     if (v < d.peak_val) {
@@ -115,7 +133,10 @@ __device__ __forceinline__ void step(Detector& d, Detector* other, int w, double
   }
   if (d.peak_val - v > kPeakHeight && d.peak_val > threshold) d.valid = true;
   if (d.valid && i - d.peak_pos > w / 2) {
-    insert_bound(bs, nb, cap, d.peak_pos);
+    if (overflow)
+      insert_pending(bs, nb, cap, d.peak_pos, overflow);
+    else
+      insert_bound(bs, nb, cap, d.peak_pos);
     d.peak_pos = -1;
     d.peak_val = v;
     d.valid = false;
@@ -263,7 +284,162 @@ __global__ __launch_bounds__(64) void k_detect_events(const float* __restrict__ 
   }
 }
 
+// ---- reads received chunk by chunk: the detectors' state kept between calls
+
+constexpr int kPending = 32;  // emitted boundaries not yet delivered, per read
+
+struct EventState {
+  int64_t pos;           // next position to scan (from the read's first sample)
+  int64_t last;          // start of the next undelivered event
+  int64_t s_masked, s_peak, l_masked, l_peak;
+  double s_val, l_val;
+  int32_t s_valid, l_valid;
+  int32_t index;         // index of the next undelivered event in the read
+  int32_t npend;
+  int64_t pend[kPending];
+};
+
+__global__ void k_event_state_init(EventState* __restrict__ states,
+                                   const int32_t* __restrict__ slots, int32_t n) {
+  const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= n) return;
+  EventState& e = states[slots[i]];
+  e.pos = 0;
+  e.last = 0;
+  e.s_masked = e.l_masked = -1;
+  e.s_peak = e.l_peak = -1;
+  e.s_val = e.l_val = INFINITY;
+  e.s_valid = e.l_valid = 0;
+  e.index = 0;
+  e.npend = 0;
+}
+
+// One wave per read.  Read r's samples so far are raw[ranges[2r] ..
+// ranges[2r+1]) (the start fixed across calls); its state is
+// states[slots[r]].  Positions pos .. L-6 are scanned (those whose t
+// statistics are final) and emitted boundaries join the pending list (in
+// LDS, room for keep + 32); then the final ones (below every open
+// candidate) are delivered in order as events last .. boundary, events
+// below `trim` consumed without being written, at most keep written; at most
+// 32 undelivered boundaries may carry over to the next call.
+__global__ __launch_bounds__(64) void k_events_continue(
+    const float* __restrict__ raw, const int64_t* __restrict__ ranges,
+    const int32_t* __restrict__ slots, EventState* __restrict__ states, int32_t nreads,
+    int32_t trim, int32_t keep, float* __restrict__ out, int32_t* __restrict__ counts) {
+  __shared__ double ts[kEvBlock], tl[kEvBlock];
+  extern __shared__ int64_t pend[];  // [keep + kPending]
+  __shared__ int32_t s_nout, s_skip, s_over;
+  __shared__ int64_t s_start;
+  const int32_t r = (int32_t)blockIdx.x;
+  if (r >= nreads) return;
+  const int lane = threadIdx.x;
+  const int32_t room = keep + kPending;
+  const int64_t a = ranges[2 * (int64_t)r];
+  const int64_t L = ranges[2 * (int64_t)r + 1] - a;
+  const float* __restrict__ x = raw + a;
+  EventState* __restrict__ st = states + slots[r];
+  const int64_t scanL = L > kWLong - 1 ? L - (kWLong - 1) : 0;
+  const int64_t pos0 = st->pos;
+  int32_t np = st->npend;
+  if (lane < kPending) pend[lane] = st->pend[lane];
+  Detector ds{st->s_masked, st->s_peak, st->s_val, st->s_valid != 0};
+  Detector dl{st->l_masked, st->l_peak, st->l_val, st->l_valid != 0};
+  int32_t over = 0;
+  __syncthreads();
+  for (int64_t b0 = pos0; b0 < scanL; b0 += kEvBlock) {
+    const int64_t nblk = scanL - b0 < kEvBlock ? scanL - b0 : kEvBlock;
+    for (int64_t j = lane; j < nblk; j += 64) {
+      ts[j] = tstat<kWShort>(x, L, b0 + j);
+      tl[j] = tstat<kWLong>(x, L, b0 + j);
+    }
+    __syncthreads();
+    if (lane == 0) {
+      for (int64_t j = 0; j < nblk; ++j) {
+        step(ds, &dl, kWShort, kTShort, b0 + j, ts[j], pend, np, room, &over);
+        step(dl, nullptr, kWLong, kTLong, b0 + j, tl[j], pend, np, room, &over);
+      }
+    }
+    __syncthreads();
+  }
+  int32_t used = 0;
+  if (lane == 0) {
+    const int64_t scanned = scanL > pos0 ? scanL : pos0;
+    // below the smallest open candidate no boundary can still appear
+    int64_t cut = scanned;
+    if (ds.peak_pos >= 0 && ds.peak_pos < cut) cut = ds.peak_pos;
+    if (dl.peak_pos >= 0 && dl.peak_pos < cut) cut = dl.peak_pos;
+    int64_t start = st->last;
+    int32_t index = st->index, nout = 0, skip = 0;
+    while (used < np && pend[used] < cut && nout < keep) {
+      if (index >= trim) {
+        ++nout;
+      } else {
+        start = pend[used];
+        ++skip;
+      }
+      ++index;
+      ++used;
+    }
+    st->pos = scanned;
+    st->last = used > 0 ? pend[used - 1] : st->last;
+    st->index = index;
+    st->s_masked = ds.masked_to;
+    st->s_peak = ds.peak_pos;
+    st->s_val = ds.peak_val;
+    st->s_valid = ds.valid;
+    st->l_masked = dl.masked_to;
+    st->l_peak = dl.peak_pos;
+    st->l_val = dl.peak_val;
+    st->l_valid = dl.valid;
+    if (np - used > kPending) over = 1;
+    s_nout = nout;
+    s_skip = skip;
+    s_start = start;
+    s_over = over;
+  }
+  __syncthreads();
+  // the delivered events: start .. pend[skip], pend[skip] .. pend[skip+1], ...
+  const int32_t nout = s_nout, skip = s_skip;
+  const int64_t start = s_start;
+  for (int32_t e = lane; e < keep; e += 64) {
+    float v = 0.0f;
+    if (e < nout) {
+      const int64_t lo = e == 0 ? start : pend[skip + e - 1];
+      const int64_t up = pend[skip + e];
+      double sum = 0.0;
+      for (int64_t q = lo; q < up; ++q) sum += (double)x[q];
+      v = (float)(sum / (double)(up - lo));
+    }
+    out[(int64_t)r * keep + e] = v;
+  }
+  __syncthreads();
+  if (lane == 0) {
+    const int32_t left = np - used < kPending ? np - used : kPending;
+    for (int32_t j = 0; j < left; ++j) st->pend[j] = pend[used + j];
+    st->npend = left;
+    counts[r] = s_over ? -1 : nout;
+  }
+}
+
 }  // namespace
+
+size_t event_state_bytes() { return sizeof(EventState); }
+
+hipError_t launch_event_state_init(void* states, const int32_t* slots, int32_t n,
+                                   hipStream_t st) {
+  hipLaunchKernelGGL(k_event_state_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                     (EventState*)states, slots, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_events_continue(const float* raw, const int64_t* ranges, const int32_t* slots,
+                                  void* states, int32_t nreads, int32_t trim, int32_t keep,
+                                  float* out, int32_t* counts, hipStream_t st) {
+  const size_t lds = sizeof(int64_t) * (size_t)(keep + kPending);
+  hipLaunchKernelGGL(k_events_continue, dim3((unsigned)nreads), dim3(64), lds, st, raw, ranges,
+                     slots, (EventState*)states, nreads, trim, keep, out, counts);
+  return hipGetLastError();
+}
 
 // Reads per wave: more reads share a wave (their detectors run side by side)
 // only while the launch still has two waves per SIMD; measured on MI355X for

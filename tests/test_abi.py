@@ -69,6 +69,10 @@ def test_argument_validation(lib):
     assert lib.sdtw_detect_events_prefix(p, None, p, 1, 0, 5, p, p, None) == 1
     assert lib.sdtw_detect_events_prefix(p, p, p, 1, -1, 5, p, p, None) == 1
     assert lib.sdtw_detect_events_prefix(p, p, p, 1, 6000, 500, p, p, None) == 1
+    assert lib.sdtw_event_state_bytes() > 0
+    assert lib.sdtw_event_state_init(None, p, 1, None) == 1
+    assert lib.sdtw_detect_events_continue(p, p, p, None, 1, 0, 5, p, p, None) == 1
+    assert lib.sdtw_detect_events_continue(p, p, p, p, 1, 0, 5000, p, p, None) == 1
     assert lib.sdtw_align_one_wide(p, None, 5, 0, p, p, None) == 1
     assert lib.sdtw_load_reference(None, 10, 1, 0, None, C.byref(C.c_void_p())) == 1
     assert lib.sdtw_load_reference(p, 0, 1, 0, None, C.byref(C.c_void_p())) == 1

@@ -120,6 +120,53 @@ def test_prefixes_of_reads_being_received(dev):
     assert c[-1] == -1 and not e[-1].any()
 
 
+def test_continuing_detection_over_chunks(dev):
+    # reads received in chunks of different sizes, each sample scanned once:
+    # the events delivered call after call are the whole read's
+    g = synth.make_genome(synth.SMALL_GENOME, synth.SMALL_GENOME)
+    raw = synth.simulate_raw(g, synth.make_level_table(), 6, 500, 0.5, 606)
+    x = torch.from_numpy(raw.values).to(dev)
+    n = raw.nreads
+    states = sd.EventStates(n + 3)
+    slots = torch.tensor([n + 2 - r for r in range(n)], dtype=torch.int32, device=dev)
+    states.reset(slots)
+    chunk = [300, 700, 1200, 2400, 2400, 5000]
+    got = [[] for _ in range(n)]
+    lens = np.zeros(n, np.int64)
+    total = np.diff(raw.offsets)
+    for call in range(40):
+        lens = np.minimum(total, lens + np.array(chunk))
+        rg = np.stack([raw.offsets[:-1], raw.offsets[:-1] + lens], 1).astype(np.int64)
+        e, c = states.detect(x, torch.from_numpy(rg).to(dev), slots, 50, 1200)
+        torch.cuda.synchronize()
+        e, c = e.cpu().numpy(), c.cpu().numpy()
+        assert (c >= 0).all(), c
+        for r in range(n):
+            got[r].append(e[r, :c[r]].copy())
+            assert not e[r, c[r]:].any()
+        if (lens == total).all() and call > 0 and not c.any():
+            break
+    note(f"continuing detection: {call + 1} calls")
+    for r in range(n):
+        full = ev.events(raw.values[raw.offsets[r]:raw.offsets[r + 1]])
+        mine = np.concatenate(got[r])
+        assert np.array_equal(mine, full[50:50 + mine.size]), r
+        assert mine.size >= full.size - 50 - 3, (r, mine.size, full.size)
+
+
+def test_continuing_detection_overflow_is_reported(dev):
+    g = synth.make_genome(synth.SMALL_GENOME, synth.SMALL_GENOME)
+    raw = synth.simulate_raw(g, synth.make_level_table(), 1, 300, 1.0, 3)
+    x = torch.from_numpy(raw.values).to(dev)
+    states = sd.EventStates(1)
+    slots = torch.zeros(1, dtype=torch.int32, device=dev)
+    states.reset(slots)
+    rg = torch.tensor([[0, int(raw.offsets[1])]], dtype=torch.int64, device=dev)
+    _, c = states.detect(x, rg, slots, 0, 1)  # one event may leave per call
+    torch.cuda.synchronize()
+    assert int(c.item()) == -1
+
+
 def test_noise_free_steps(dev):
     rng = np.random.default_rng(9)
     lens = rng.integers(3, 16, size=400)
