@@ -48,13 +48,15 @@ This module simulates the channels and runs the decisions through the C ABI:
 ``make_raw_targets``): every chunk period a channel's read has
 ``chunk_samples`` more samples (the pool's samples are resident on the
 device, standing for the sequencer's signal buffer), and each batch first
-cuts the samples received so far into events on the device
-(sdtw_detect_events_prefix: only events that later samples cannot change,
-from event ``trim_events`` + rows already aligned), then normalises and
-extends with them.  A read's first extension waits for ``chunk_events``
-final events (its normalisation statistics); later ones take whatever new
-final events there are.  A read without new events waits for its next
-chunk.
+cuts the new samples into events on the device (sdtw_detect_events_continue:
+the detectors' state of every channel's read is kept on the device between
+chunks, each sample is scanned once, events are delivered when later
+samples cannot change them, the first ``trim_events`` dropped), appends them
+to the channel's event buffer, then normalises and extends with the
+buffered events not aligned yet.  A read's first extension waits for
+``chunk_events`` events (its normalisation statistics); later ones take
+whatever new events there are.  A read without new events waits for its
+next chunk.
 """
 from __future__ import annotations
 
@@ -101,6 +103,8 @@ class Target:
                                                  # by the server that serves it)
     raw_dev: object = None             # raw mode: the pool's samples on the device
     raw_offs: object = None            # raw mode: int64 offsets of the pool's reads
+    ev_states: object = None           # raw mode: detector state per channel (set by the server)
+    ev_buf: object = None              # raw mode: [channels, max_events] detected events
 
 
 @dataclass
@@ -114,6 +118,8 @@ class _Read:
     stats: object = None               # (1, 2) float64 device tensor after chunk 1
     rows: int = 0
     chunks_done: int = 0
+    have: int = 0                      # raw mode: events detected (buffered) so far
+    fresh_state: bool = True           # raw mode: its detector state is still to be reset
 
 
 @dataclass
@@ -209,6 +215,11 @@ class ReadUntilServer:
             t.streams = _server_streams(torch, i * k, k)
         if self.cfg.row_budget_bytes is not None:
             sd.set_row_budget(self.cfg.row_budget_bytes)
+        if self.cfg.raw:
+            for t in self.targets:
+                t.ev_states = sd.EventStates(self.cfg.channels)
+                t.ev_buf = torch.zeros((self.cfg.channels, self.cfg.max_events),
+                                       dtype=torch.float32, device=torch.device("cuda"))
 
     # ------------------------------------------------------------------
     def calibrate(self, n_each: int = 128, seed: int = 77, group: int = 32):
@@ -571,7 +582,8 @@ class ReadUntilServer:
         return []
 
     def _submit_raw(self, ti, items, chan_read, inflight, dev):
-        """Raw mode: events of the samples received so far, then the same
+        """Raw mode: events of each read's new samples (the detectors
+        continue from their state), buffered per channel, then the same
         normalisation and extension as for event chunks."""
         torch = self.torch
         cfg = self.cfg
@@ -582,56 +594,76 @@ class ReadUntilServer:
         hs = t.streams[slot]
         n = len(items)
         rg = np.empty((n, 2), np.int64)
-        fs = np.empty(n, np.int32)
+        chans = np.array([c for _, c in items], np.int32)
+        new = [c for _, c in items if chan_read[c].fresh_state]
         for k, (_, c) in enumerate(items):
             rd = chan_read[c]
             a, b = int(t.raw_offs[rd.pool_idx]), int(t.raw_offs[rd.pool_idx + 1])
             rg[k] = (a, min(b, a + (rd.chunks_done + 1) * cfg.chunk_samples))
-            fs[k] = cfg.trim_events + rd.rows
         waiting = []
         with torch.cuda.stream(hs):
+            if new:
+                t.ev_states.reset(torch.from_numpy(np.array(new, np.int32)).to(
+                    dev, non_blocking=True), stream=hs)
+                for c in new:
+                    chan_read[c].fresh_state = False
             rg_d = torch.from_numpy(rg).pin_memory().to(dev, non_blocking=True)
-            fs_d = torch.from_numpy(fs).pin_memory().to(dev, non_blocking=True)
-            ev, cnt = sd.detect_events_prefix(t.raw_dev, rg_d, fs_d,
-                                              cfg.trim_events + cfg.max_events, keep, stream=hs)
+            ch_d = torch.from_numpy(chans).pin_memory().to(dev, non_blocking=True)
+            ev, cnt = t.ev_states.detect(t.raw_dev, rg_d, ch_d, cfg.trim_events, keep,
+                                         stream=hs)
             cnt_h = torch.empty(n, dtype=torch.int32, pin_memory=True)
             cnt_h.copy_(cnt, non_blocking=True)
             hs.synchronize()  # this stream had no batch in flight: only the detection
             cnt_np = cnt_h.numpy().copy()
+            if (cnt_np < 0).any():
+                raise RuntimeError("event detection: more boundaries waiting than it keeps")
+            # append the new events to the channels' buffers
+            have = np.array([chan_read[c].have for _, c in items], np.int64)
+            add = np.minimum(cnt_np, cfg.max_events - have)
+            if add.any():
+                j = torch.arange(keep, device=dev)[None, :]
+                mask = j < torch.from_numpy(add).to(dev)[:, None]
+                rows_i = ch_d.long()[:, None].expand(n, keep)[mask]
+                cols_i = (torch.from_numpy(have).to(dev)[:, None] + j)[mask]
+                t.ev_buf[rows_i, cols_i] = ev[mask]
             take = np.zeros(n, np.int64)
             for k, (_, c) in enumerate(items):
                 rd = chan_read[c]
-                room = cfg.max_events - rd.rows
-                got = min(int(cnt_np[k]), room)
+                rd.have += int(add[k])
+                avail = rd.have - rd.rows
                 if rd.rows == 0:
-                    take[k] = E if got >= E else 0  # the first chunk fixes the statistics
+                    take[k] = E if avail >= E else 0  # the first chunk fixes the statistics
                 else:
-                    take[k] = got
+                    take[k] = avail
             entries, code_parts, lens = [], [], []
             for fresh in (True, False):
                 sel = [k for k, (_, c) in enumerate(items)
                        if take[k] > 0 and (chan_read[c].rows == 0) == fresh]
                 if not sel:
                     continue
-                sel_d = torch.tensor(sel, dtype=torch.int64, device=dev)
-                tk = torch.from_numpy(take[sel]).to(dev, non_blocking=True)
-                rows_ev = ev.index_select(0, sel_d)
-                mask = torch.arange(keep, device=dev)[None, :] < tk[:, None]
-                vals = rows_ev[mask]  # the taken events, read after read
-                offs_np = np.zeros(len(sel) + 1, np.int64)
-                np.cumsum(take[sel], out=offs_np[1:])
-                offs = torch.from_numpy(offs_np).to(dev, non_blocking=True)
                 group = [items[k] for k in sel]
+                tk = np.array([take[k] for k in sel], np.int64)
+                start = np.array([chan_read[c].rows for _, c in group], np.int64)
+                width = int(tk.max())
+                j = torch.arange(width, device=dev)[None, :]
+                mask = j < torch.from_numpy(tk).to(dev)[:, None]
+                rows_i = torch.from_numpy(chans[sel].astype(np.int64)).to(dev)[:, None] \
+                    .expand(len(sel), width)[mask]
+                cols_i = (torch.from_numpy(start).to(dev)[:, None] + j)[mask]
+                vals = t.ev_buf[rows_i, cols_i]  # the taken events, read after read
+                offs_np = np.zeros(len(sel) + 1, np.int64)
+                np.cumsum(tk, out=offs_np[1:])
+                offs = torch.from_numpy(offs_np).to(dev, non_blocking=True)
                 if fresh:
                     _, codes, _, st = sd.prepare_queries_ex(vals, offs, cfg.scale, stream=hs)
-                    for j, (_, c) in enumerate(group):
-                        chan_read[c].stats = st[j:j + 1]
+                    for i2, (_, c) in enumerate(group):
+                        chan_read[c].stats = st[i2:i2 + 1]
                 else:
                     st_in = torch.cat([chan_read[c].stats for _, c in group])
                     _, codes, _, _ = sd.prepare_queries_ex(vals, offs, cfg.scale, st_in,
                                                            stream=hs)
                 code_parts.append(codes)
-                lens += take[sel].tolist()
+                lens += tk.tolist()
                 entries += [(c, chan_read[c], arr, int(take[k])) for k, (arr, c) in
                             zip(sel, group)]
             for k, (arr, c) in enumerate(items):
