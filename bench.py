@@ -11,6 +11,8 @@ forward+reverse signal of a 29,903-base genome (seeded synthetic data of the
 SARS-CoV-2 workload's shape), int16 inputs with 32-bit accumulation.
 
 `value` is GCUPS (cells = sum over reads of M x N, per second of step time).
+`extras.end_to_end` gives the same pass with its host transfers (inputs up
+from pinned host memory, results back), which `value` leaves out.
 The roofline object reports the alignment kernel's cell rate, timed with HIP
 events on the launch stream, against the VALU roof of the chip: 256 CUs x 4
 SIMDs x 2.4 GHz, where a SIMD spends 4 cycles on a full-rate 32-bit VALU
@@ -54,8 +56,8 @@ SIMD_CYCLES_PER_64_CELLS = {"i16": 4 + 4, "f32": 2 + 4 + 2}
 # (sha256 of csrc/align.hip); otherwise `traffic` is null.
 MEASURED_TRAFFIC = {
     ("4096 reads M=250 vs 29,903-base genome", "i16", 32, 1, 1): {
-        "fetch_bytes": 4812976, "write_bytes": 371381,
-        "align_hip_sha256": "4df1be903108c3a53c95cf2d586f822a68fa9a02f497a6afa1da96dc64b928d1"},
+        "fetch_bytes": 4747551, "write_bytes": 360341,
+        "align_hip_sha256": "a5e458355022dd14e2c4518df708ec4049fb045ad2592095122e8d2855f46f3d"},
 }
 
 
@@ -204,6 +206,8 @@ def main():
     if not args.no_extras:
         out["extras"] = extras(sd, torch, dev, w, reads, zref, cref, args, stream)
         out["extras"]["hip_graph"] = graph_step(sd, torch, step, cost, end, args.steps)
+        out["extras"]["end_to_end"] = end_to_end(sd, torch, dev, reads, ref, plan, dt, cells,
+                                                 args.steps)
 
     if args.serve_seconds > 0:
         out["serving"] = serving(torch, dev, args.serve_seconds, args.serve_warmup,
@@ -240,6 +244,45 @@ def graph_step(sd, torch, step, cost, end, steps):
     ms = (time.perf_counter() - t0) * 1e3 / steps
     same = same and bool(torch.equal(cost, want[0]) and torch.equal(end, want[1]))
     return {"ms_per_step": round(ms, 4), "replays": steps + 1, "equal_to_eager": same}
+
+
+def end_to_end(sd, torch, dev, reads, ref, plan, dt, cells, reps):
+    """The step with its host transfers: the raw events and offsets go up from
+    pinned host memory, the step runs, cost and end come back to pinned host
+    memory; host wall time per pass until the results are on the host
+    (median).  Not the headline value, whose inputs are resident."""
+    h_raw = torch.empty(reads.values.size, dtype=torch.float32, pin_memory=True)
+    h_raw.copy_(torch.from_numpy(reads.values))
+    h_offs = torch.empty(reads.offsets.size, dtype=torch.int64, pin_memory=True)
+    h_offs.copy_(torch.from_numpy(reads.offsets))
+    cdt = torch.int32 if dt == sd.I16 else torch.float32
+    h_cost = torch.empty(reads.nq, dtype=cdt, pin_memory=True)
+    h_end = torch.empty(reads.nq, dtype=torch.int32, pin_memory=True)
+    d_raw = torch.empty(h_raw.shape, dtype=torch.float32, device=dev)
+    d_offs = torch.empty(h_offs.shape, dtype=torch.int64, device=dev)
+    d_cost = torch.empty(reads.nq, dtype=cdt, device=dev)
+    d_end = torch.empty(reads.nq, dtype=torch.int32, device=dev)
+    cur = torch.cuda.current_stream()
+
+    def run():
+        d_raw.copy_(h_raw, non_blocking=True)
+        d_offs.copy_(h_offs, non_blocking=True)
+        z, codes, _ = sd.prepare_queries(d_raw, d_offs, 64.0)
+        sd.align_batch(ref, plan, codes if dt == sd.I16 else z, d_cost, d_end)
+        h_cost.copy_(d_cost, non_blocking=True)
+        h_end.copy_(d_end, non_blocking=True)
+        cur.synchronize()
+
+    run()
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        run()
+        times.append(time.perf_counter() - t0)
+    ms = float(np.median(times)) * 1e3
+    up = reads.values.size * 4 + reads.offsets.size * 8
+    return {"ms": round(ms, 4), "gcups": round(cells / (ms * 1e-3) / 1e9, 1),
+            "h2d_bytes": int(up), "d2h_bytes": int(reads.nq * 8), "passes": reps}
 
 
 def extras(sd, torch, dev, w, reads, zref, cref, args, stream):

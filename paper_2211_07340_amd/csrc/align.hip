@@ -417,6 +417,9 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
       for (int h = 1; h < K; ++h) xs[h] = nxtx[h];
       xs[0] = e0.x;
       load_entries(r + 1);
+      // keep the prefetch at the top of the step: scheduled next to its use,
+      // as the compiler would otherwise place it, every step waits for it
+      __builtin_amdgcn_sched_barrier(0);
       uint32_t left[K];
       if constexpr (K == 1)
         left[0] = from_left_lane(up[W - 1], e0.y);
