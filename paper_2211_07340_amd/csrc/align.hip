@@ -405,6 +405,18 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
     const uint32_t* upsrc = zeros;
     const uint32_t* d0src = zeros;
     uint32_t* fin = my_stage;
+    // The last lane's boundary store of a step is issued at the top of the
+    // next step, after that step's lane shift and before its prefetch: the
+    // store still precedes every read of its row, and the shift then waits
+    // only for the prefetch issued a whole step earlier (a store issued just
+    // before it, under the lane mask, would be waited for as well).
+    bool pend = false;
+    int32_t pend_i = 0;
+    uint32_t pend_v = 0;
+    auto flush = [&]() {
+      if (pend && lane == 63) bxl[pend_i].y = pend_v;
+      pend = false;
+    };
     // One row step.  CH >= 0: sub-lane r (lane r / K, chain CH == r % K)
     // enters its next tile in this step; the edges its right neighbours need
     // are read before the switch overwrites `up`.
@@ -416,15 +428,16 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
 #pragma unroll
       for (int h = 1; h < K; ++h) xs[h] = nxtx[h];
       xs[0] = e0.x;
-      load_entries(r + 1);
-      // keep the prefetch at the top of the step: scheduled next to its use,
-      // as the compiler would otherwise place it, every step waits for it
-      __builtin_amdgcn_sched_barrier(0);
       uint32_t left[K];
       if constexpr (K == 1)
         left[0] = from_left_lane(up[W - 1], e0.y);
       else
         left[0] = asm_from_left_lane(up[W - 1], e0.y);
+      flush();
+      load_entries(r + 1);
+      // keep the prefetch at the top of the step: scheduled next to its use,
+      // as the compiler would otherwise place it, every step waits for it
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int h = 1; h < K; ++h) left[h] = up[h * H - 1];
       if constexpr (CH >= 0) {
@@ -465,7 +478,9 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
         chains_row<F, K, H, W>(xs, y, up, nw, dprev, left);
 #pragma unroll
       for (int h = 0; h < K; ++h) dprev[h] = left[h];
-      if (write_b && lane == 63) bxl[wrap ? r + Mb : r].y = nw[W - 1];
+      pend = write_b;
+      pend_i = wrap ? r + Mb : r;
+      pend_v = nw[W - 1];
     };
     using NoSwitch = std::integral_constant<int, -1>;
 
@@ -494,6 +509,7 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
                  !first || r + u + 1 == S - 1, r + u + 1 != S - 1);
           });
         }
+        flush();
         // every lane has finished tile p-1: the last band folds its last row
         // (and writes it back as the new resident row); stage tile p+1
         if (p >= 1 && last) {
@@ -540,6 +556,7 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
 #pragma unroll
             for (int w = 0; w < W; ++w) a[w] = b[w];
           }
+          flush();
         }
       }
       if constexpr (P > 1) __syncthreads();
