@@ -443,9 +443,14 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
       if constexpr (CH >= 0) {
         if (lane == r / K) {
           [[maybe_unused]] const uint32_t old_last = up[W - 1];
-          // new reference strip, then the finished row out (the last band's
-          // fin is the stage itself), then the new previous row: ordered so
-          // that the loads can land in the registers they replace
+          // the diagonal first (the first cell needs it), then per group of
+          // four columns: new reference values, the finished row's values
+          // out (the last band's fin is the stage itself, so each group is
+          // read before it is overwritten), the new previous row's values
+          // into the registers just stored.  The cells of the step wait for
+          // the groups in order, so they start after the first few LDS
+          // operations instead of after all of them.
+          dprev[CH] = CH == 0 ? *d0src : upsrc[CH * H - 1];
 #pragma unroll
           for (int w = CH * H; w < (CH + 1) * H; w += 4) {
             const uint4 nv = *(const uint4*)(my_stage + w);
@@ -453,20 +458,14 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
             y[w + 1] = nv.y;
             y[w + 2] = nv.z;
             y[w + 3] = nv.w;
-          }
-#pragma unroll
-          for (int w = CH * H; w < (CH + 1) * H; w += 4)
             *(uint4*)(fin + w) = make_uint4(up[w], up[w + 1], up[w + 2], up[w + 3]);
-          __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-          for (int w = CH * H; w < (CH + 1) * H; w += 4) {
             const uint4 zv = *(const uint4*)(upsrc + w);
             up[w] = zv.x;
             up[w + 1] = zv.y;
             up[w + 2] = zv.z;
             up[w + 3] = zv.w;
+            __builtin_amdgcn_sched_barrier(0);
           }
-          dprev[CH] = CH == 0 ? *d0src : upsrc[CH * H - 1];
           if constexpr (P > 1 && CH == K - 1) {
             if (!last && lane == 63) edge_out[(p - 1) & 3] = old_last;
           }
