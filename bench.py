@@ -50,14 +50,17 @@ SIMD_CYCLES_PER_64_CELLS = {"i16": 4 + 4, "f32": 2 + 4 + 2}
 
 # HBM bytes per launch of the alignment kernel, from the rocprofv3 FETCH_SIZE
 # and WRITE_SIZE passes summarised in
-# profiles/counters_k_align_skew_i16_w32_b1_4096x250.md (each scaled by what
-# the counter reads for a plain copy of known size), keyed by workload and
-# launch shape, valid only while the kernel source is the one measured
-# (sha256 of csrc/align.hip); otherwise `traffic` is null.
+# profiles/counters_k_align_skew_i16_w32_k2_b1_4096x250.md (two chains, the
+# shape the autotuner picks) and profiles/counters_k_align_skew_i16_w32_b1_4096x250.md
+# (one chain), each scaled by what the counter reads for a plain copy of known
+# size, keyed by workload and launch shape, valid only while the kernel source
+# is the one measured (sha256 of csrc/align.hip); otherwise `traffic` is null.
+_ALIGN_SHA = "a4350885f68caeeb4a1a639aa789222f3a9bc9082851972af2fd72f2411f2967"
 MEASURED_TRAFFIC = {
+    ("4096 reads M=250 vs 29,903-base genome", "i16", 32, 2, 1): {
+        "fetch_bytes": 4717118, "write_bytes": 342379, "align_hip_sha256": _ALIGN_SHA},
     ("4096 reads M=250 vs 29,903-base genome", "i16", 32, 1, 1): {
-        "fetch_bytes": 4753801, "write_bytes": 367531,
-        "align_hip_sha256": "21d8c6b26b5cca9a683fcea0e2609dd98753f39a48c70ad60e3d0297650c0d85"},
+        "fetch_bytes": 4752309, "write_bytes": 356128, "align_hip_sha256": _ALIGN_SHA},
 }
 
 

@@ -449,8 +449,16 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
           // read before it is overwritten), the new previous row's values
           // into the registers just stored.  The cells of the step wait for
           // the groups in order, so they start after the first few LDS
-          // operations instead of after all of them.
-          dprev[CH] = CH == 0 ? *d0src : upsrc[CH * H - 1];
+          // operations instead of after all of them.  With one band and no
+          // resident row the previous row is always gamma(0, .) = 0 (and so
+          // is the diagonal), and a cell's minimum is 0 as soon as one of
+          // its operands is (costs are non-negative): the diagonal and
+          // every other column of the strip (offsets 1, 3, ...) are cleared
+          // instead of the row being loaded, a third fewer LDS operations
+          // in the switch; the other registers keep values never read as a
+          // previous row again.
+          constexpr bool kZeroRow = P == 1 && !STREAM;
+          dprev[CH] = kZeroRow ? 0u : (CH == 0 ? *d0src : upsrc[CH * H - 1]);
 #pragma unroll
           for (int w = CH * H; w < (CH + 1) * H; w += 4) {
             const uint4 nv = *(const uint4*)(my_stage + w);
@@ -459,11 +467,16 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
             y[w + 2] = nv.z;
             y[w + 3] = nv.w;
             *(uint4*)(fin + w) = make_uint4(up[w], up[w + 1], up[w + 2], up[w + 3]);
-            const uint4 zv = *(const uint4*)(upsrc + w);
-            up[w] = zv.x;
-            up[w + 1] = zv.y;
-            up[w + 2] = zv.z;
-            up[w + 3] = zv.w;
+            if constexpr (kZeroRow) {
+              up[w + 1] = 0u;
+              up[w + 3] = 0u;
+            } else {
+              const uint4 zv = *(const uint4*)(upsrc + w);
+              up[w] = zv.x;
+              up[w + 1] = zv.y;
+              up[w + 2] = zv.z;
+              up[w + 3] = zv.w;
+            }
             __builtin_amdgcn_sched_barrier(0);
           }
           if constexpr (P > 1 && CH == K - 1) {
