@@ -9,8 +9,12 @@ which sub-lane r enters its next tile (after its outgoing edge has been read
 by its right neighbour), the query/boundary LDS entries at K(63 - l) + r +
 (K - 1 - h) read one step ahead, the boundary writes of the last sub-lane (at
 r, or r + M while its row wraps), the per-tile fold of the staged last rows
-and the lexicographic final reduction.  It checks the schedule itself against
-the oracle on the CPU; the GPU parity tests check the compiled kernel.
+and the lexicographic final reduction.  At a tile switch the previous row is
+cleared the way the kernel clears it (the diagonal and every other column
+only), so the model also checks that a zero among each cell's minimum
+operands is all the first row of a tile needs.  It checks the schedule
+itself against the oracle on the CPU; the GPU parity tests check the
+compiled kernel.
 """
 import numpy as np
 import pytest
@@ -68,7 +72,12 @@ def skew_model(x, yref, W, K=1):
             nv = stage[l, cols].copy()
             stage[l, cols] = up[l, cols]
             y[l, cols] = nv
-            up[l, cols] = 0
+            # the previous row of a tile is gamma(0, .) = 0; like the kernel,
+            # clear only the diagonal and every other column (offsets 1, 3,
+            # ...) and leave the finished row's values in the others: each
+            # cell's minimum still has a zero operand
+            up[l, h * H + 1:(h + 1) * H:2] = 0
+            dprev[h][l] = 0
         for h in range(K):
             ex = ent[h][0]
             diag, lf = dprev[h].copy(), lefts[h].copy()
