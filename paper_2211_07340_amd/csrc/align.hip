@@ -455,8 +455,8 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
           // its operands is (costs are non-negative): the diagonal and
           // every other column of the strip (offsets 1, 3, ...) are cleared
           // instead of the row being loaded, a third fewer LDS operations
-          // in the switch; the other registers keep values never read as a
-          // previous row again.
+          // in the switch; the other registers keep the finished row's
+          // values, which in this step only meet a zero in each minimum.
           constexpr bool kZeroRow = P == 1 && !STREAM;
           dprev[CH] = kZeroRow ? 0u : (CH == 0 ? *d0src : upsrc[CH * H - 1]);
 #pragma unroll
