@@ -301,8 +301,9 @@ int sdtw_plan_get_config(sdtw_plan plan, int* strip, int* chains, int* bands,
  * candidate (strip 16 or 32, 1 or 2 chains, 1 to 4 bands where valid,
  * with 3 or 4 bands also band_rows targets of a half and a third of the
  * median read, each at the waves per CU its LDS allows and at half that)
- * in two passes, each a warm-up launch and one timed with HIP events on
- * `stream`; keep the candidate with the fastest of its two times on the plan
+ * in two passes (the second in reverse order), each a warm-up launch and one
+ * timed with HIP events on `stream`; keep the candidate with the fastest of
+ * its two times on the plan
  * and remember it for sdtw_plan_use_tuned (keyed by device, dtype, reference
  * length, number of reads, longest read and total rows).
  *   max_columns  time the candidates on the first min(n, max_columns)

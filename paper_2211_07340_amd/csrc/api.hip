@@ -841,13 +841,16 @@ int sdtw_plan_autotune(sdtw_ref ref, sdtw_plan plan, const void* q_dev, void* co
                         plan->band_rows};
   TuneVal best = keep;
   int rc = SDTW_OK;
-  // two passes over the candidates, each timed once per pass after a
-  // warm-up launch, keeping a candidate's faster time: the first pass also
-  // brings the clock up (the first launches of a cold device run slower),
-  // and a single timing can misorder shapes a few percent apart
+  // two passes over the candidates, the second in reverse order, each
+  // candidate timed once per pass after a warm-up launch, keeping its faster
+  // time: the first pass also brings the clock up (the first launches of a
+  // cold device run slower), a single timing can misorder shapes a few
+  // percent apart, and a clock that drifts during the passes favours no
+  // position in the list
   std::vector<float> cand_ms(cand.size(), 0.f);
   for (int pass = 0; pass < 2 && !rc; ++pass) {
-    for (size_t i = 0; i < cand.size(); ++i) {
+    for (size_t j = 0; j < cand.size(); ++j) {
+      const size_t i = pass == 0 ? j : cand.size() - 1 - j;
       const TuneVal& c = cand[i];
       plan->strip = c.strip;
       plan->chains = c.chains;
