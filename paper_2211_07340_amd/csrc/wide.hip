@@ -31,8 +31,9 @@
 //
 // Value ranges (32-bit): costs < 2^28 (M <= 4096 rows of |x - y| <= 65535),
 // +inf = 2^31, a tile's D < 2^30 (at most 16,384 columns), and the look-back
-// saturates the D it accumulates at 2^30: x + D then still exceeds every
-// cost, so the min picks the same value as with the exact sum.
+// saturates the D it accumulates at 2^30 - 1, the largest value the 30-bit D
+// field of a flag word holds: x + D then still exceeds every cost, so the
+// min picks the same value as with the exact sum, and kInf + D < 2^32.
 #include <limits.h>
 
 #include "common.h"
@@ -43,7 +44,7 @@ namespace {
 constexpr int kWideThreads = 256;
 constexpr int kLookback = 64;  // tiles one look-back round trip covers (one per lane)
 constexpr uint32_t kInf = 1u << 31;
-constexpr uint32_t kDCap = 1u << 30;
+constexpr uint32_t kDCap = (1u << 30) - 1;  // largest D a flag word's 30-bit field holds
 constexpr uint64_t kAgg = 1, kIncl = 2;  // flag status, low two bits of a flag word
 constexpr uint32_t kSpinLimit = 1u << 20;  // polling rounds (each a memory round trip) before
                                            // a wait aborts: about a second

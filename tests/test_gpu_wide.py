@@ -158,3 +158,34 @@ def test_float_reference_rejected(dev):
     with pytest.raises(sd.SdtwError):
         sd.align_one_wide(r, torch.zeros(5, dtype=torch.int16, device=dev))
     r.close()
+
+
+@pytest.mark.parametrize("cols", [8, 16])
+def test_free_skip_over_saturated_groups_is_impossible(dev, cols):
+    # Query (0, 500, 1000).  Reference: one look-back group (64 tiles) of
+    # (0, 500) pairs, two groups of -30000 (each group's summed distances far
+    # above 2^30, so its map saturates), one group of (500, 1000) pairs.  The
+    # best cost is 500 (end at column 1).  A group map whose saturated sum
+    # read back as 0 would let the right-hand tiles start from the left
+    # group's cost 0 and report 0.
+    group = 64 * 256 * cols
+    ref = np.concatenate([np.tile(np.array([0, 500], np.int16), group // 2),
+                          np.full(2 * group, -30000, np.int16),
+                          np.tile(np.array([500, 1000], np.int16), group // 2)])
+    q = np.array([0, 500, 1000], np.int16)
+    want = oracle.sdtw_i64(q, ref)
+    assert want == (500, 1)
+    note(f"wide saturated groups N={ref.size} cols={cols}")
+    for _ in range(3):
+        assert run_wide(dev, ref, q, cols) == want
+
+
+def test_random_extremes_over_many_groups(dev):
+    # random extreme codes over 2.3 groups of 8-column tiles: every group map
+    # saturates
+    rng = np.random.default_rng(41)
+    ref = np.where(rng.random(300_000) < 0.5, 32767, -32768).astype(np.int16)
+    ref[rng.integers(0, ref.size, size=3000)] = 0
+    q = rng.integers(-32768, 32767, size=40).astype(np.int16)
+    note("wide random extremes N=300000 cols=8")
+    assert run_wide(dev, ref, q, 8) == oracle.sdtw_i64(q, ref)

@@ -334,6 +334,13 @@ def _dp(x, y, variant):
             elif variant == "transposed":  # X indexed by column, Y by row
                 d = abs(x[min(j, M) - 1] - y[min(i, N) - 1])
                 m = min(up, diag, left)
+            elif variant == "shifted_neighbours":
+                # the diagonal and left operands taken one row too low:
+                # gamma(i, j-1) in place of gamma(i-1, j-1) and gamma(i+1, j-1)
+                # in place of gamma(i, j-1) (the reading of Algorithm 2's
+                # neighbour indices that section 2.3 Eq. 1 rules out)
+                below = C[i + 1] if i < M else INF
+                m = min(up, left, below)
             else:
                 m = min(up, diag, left)
             C[i] = d + m
@@ -344,31 +351,12 @@ def _dp(x, y, variant):
     return best, pos - 1
 
 
-def _literal_algorithm2(x, y):
-    # the neighbour reads exactly as printed in Algorithm 2 (section 4.3):
-    # nw <- C[1], w <- C[2] before the row loop and w := C[i+2] inside it
-    M, N = len(x), len(y)
-    INF = float("inf")
-    C = [INF] * (M + 3)
-    best, pos = INF, -1
-    for j in range(1, N + 1):
-        n, nw, w = 0, C[1], C[2]
-        for i in range(1, M + 1):
-            C[i] = abs(x[i - 1] - y[j - 1]) + min(n, nw, w)
-            n = C[i]
-            nw = w
-            w = C[i + 2]
-        if C[M] < best:
-            best, pos = C[M], j
-    return best, pos - 1
-
-
 @pytest.mark.parametrize("variant", ["drop_diag", "drop_left", "no_free_start",
                                      "signed_distance", "transposed", "last_tie",
-                                     "literal_algorithm2"])
+                                     "shifted_neighbours"])
 def test_pins_reject_planted_mistakes(variant):
-    fn = _literal_algorithm2 if variant == "literal_algorithm2" else (
-        lambda x, y: _dp(x, y, variant))
+    def fn(x, y):
+        return _dp(x, y, variant)
     # the correct copy passes the same checks, so a failure below is the mistake
     rng = np.random.default_rng(21)
     cases = [_random_small(rng) for _ in range(300)]
@@ -381,9 +369,11 @@ def test_pins_reject_planted_mistakes(variant):
     assert caught, f"planted mistake {variant} passed every pin"
 
 
-def test_literal_algorithm2_counterexample():
-    # the reading recorded for the garbled neighbour indices of Algorithm 2
-    assert _literal_algorithm2([0, 10], [0, 10]) == (10, 0)
+def test_shifted_neighbours_counterexample():
+    # the reading recorded for the garbled neighbour indices of Algorithm 2:
+    # taken one row too low they give (10, first column) on this pair, where
+    # Eq. 1 gives (0, second column)
+    assert _dp([0, 10], [0, 10], "shifted_neighbours") == (10, 0)
     assert brute.enumerate_paths([0, 10], [0, 10]) == (0, 1)
 
 
@@ -413,3 +403,211 @@ def test_best_two_against_sorted_scan():
         rest = [p for p in pairs[1:] if abs(p[1] - b[1]) > w]
         want = (b[0], b[1]) + ((rest[0][0], rest[0][1]) if rest else (float("inf"), -1))
         assert oracle.best_two(row, w) == want, (row, w)
+
+
+# ---- float32 arithmetic: one rounding per subtraction and per addition -----
+# (section 2.3 Eq. 1 evaluated in binary32; the fixed-point path of section
+# 4.3 is pinned by the integer cases above)
+
+
+def _rne32(q):
+    """Round a rational to the nearest binary32 value, ties to even (IEEE 754
+    round-to-nearest-even, subnormals included), exactly, as a Fraction."""
+    q = Fraction(q)
+    if q == 0:
+        return Fraction(0)
+    a = abs(q)
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    if Fraction(2) ** e > a:
+        e -= 1
+    elif Fraction(2) ** (e + 1) <= a:
+        e += 1
+    quantum = Fraction(2) ** max(e - 23, -149)  # 24-bit significand; subnormal spacing
+    n, rem = divmod(a / quantum, 1)
+    n = int(n)
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and n % 2 == 1):
+        n += 1
+    r = n * quantum
+    assert r < Fraction(2) ** 128
+    return r if q > 0 else -r
+
+
+def test_rne32_matches_float32_conversion():
+    # the rounding helper itself against numpy's float32 conversion
+    rng = np.random.default_rng(40)
+    for _ in range(2000):
+        v = float(rng.normal() * 2.0 ** int(rng.integers(-140, 100)))
+        assert _rne32(Fraction(v)) == Fraction(float(np.float32(v)))
+    assert _rne32(Fraction(1) + Fraction(1, 2 ** 24)) == 1       # tie: to even
+    assert _rne32(Fraction(1) + Fraction(3, 2 ** 24)) == 1 + Fraction(1, 2 ** 22)
+
+
+def _enumerate_paths_f32(x, y):
+    """Every warping path with its sum accumulated in binary32 along the path:
+    acc <- rne32(|rne32(x_i - y_j)| + acc), cell by cell (exact rationals and
+    explicit rounding, no hardware float).  Rounding is monotone, so
+    rne32(d + min(a, b, c)) = min of rne32(d + a), rne32(d + b), rne32(d + c)
+    and the recurrence of Eq. 1 in binary32 computes exactly the smallest such
+    path sum at every cell: its (cost, first end) is this enumeration's."""
+    M, N = len(x), len(y)
+    xs = [Fraction(float(v)) for v in x]
+    ys = [Fraction(float(v)) for v in y]
+    best = {}
+
+    def dist(i, j):
+        return abs(_rne32(xs[i] - ys[j]))
+
+    def walk(i, j, acc):
+        if i == M - 1 and (j not in best or acc < best[j]):
+            best[j] = acc
+        if i + 1 < M:
+            walk(i + 1, j, _rne32(dist(i + 1, j) + acc))
+            if j + 1 < N:
+                walk(i + 1, j + 1, _rne32(dist(i + 1, j + 1) + acc))
+        if j + 1 < N:
+            walk(i, j + 1, _rne32(dist(i, j + 1) + acc))
+
+    for j0 in range(N):
+        walk(0, j0, dist(0, j0))
+    cost = min(best.values())
+    return cost, min(j for j, c in best.items() if c == cost)
+
+
+def _rounding_cases(seed, count):
+    # values of mixed magnitudes, so that x - y is often not a binary32 value
+    # and the additions round too
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        M, N = int(rng.integers(1, 5)), int(rng.integers(1, 6))
+        x = (rng.normal(size=M) * 2.0 ** rng.integers(-12, 12, size=M)).astype(np.float32)
+        y = (rng.normal(size=N) * 2.0 ** rng.integers(-12, 12, size=N)).astype(np.float32)
+        out.append((x, y))
+    return out
+
+
+def test_f32_oracle_rounds_once_per_operation():
+    rounded = 0
+    for x, y in _rounding_cases(41, 300):
+        want_c, want_e = _enumerate_paths_f32(x, y)
+        c, e = oracle.sdtw_f32(x, y)
+        assert (Fraction(float(c)), e) == (want_c, want_e), (x, y)
+        rounded += any(Fraction(float(a)) - Fraction(float(b)) != _rne32(
+            Fraction(float(a)) - Fraction(float(b))) for a in x for b in y)
+    assert rounded > 200  # the cases exercise rounding
+
+
+def _rowmajor_f32(x, y):
+    """Eq. 1 filled row by row (rows outer, columns inner), keeping only the
+    previous row, in numpy float32 scalars (one rounding per operation)."""
+    M, N = len(x), len(y)
+    inf = np.float32(np.inf)
+    prev = [np.float32(0)] * N          # gamma(0, j) = 0
+    for i in range(M):
+        cur = []
+        left, diag = inf, inf           # gamma(i, 0) = inf; gamma(i-1, 0) = inf (0 in row 1)
+        if i == 0:
+            diag = np.float32(0)
+        for j in range(N):
+            m = min(prev[j], diag, left)
+            v = np.float32(abs(np.float32(x[i] - y[j])) + m)
+            cur.append(v)
+            diag, left = prev[j], v
+        prev = cur
+    c = min(prev)
+    return c, prev.index(c), np.array(prev, np.float32)
+
+
+def test_row_major_traversal_equals_column_major_oracle():
+    # section 2.3 defines gamma cell by cell; the order in which the cells are
+    # filled cannot change any of them (each is one subtraction, one min and
+    # one addition of the same three operands), so a row-major pass equals
+    # the column-major oracle bit for bit, last row included
+    rng = np.random.default_rng(42)
+    for t in range(60):
+        M, N = int(rng.integers(1, 30)), int(rng.integers(1, 70))
+        x = (rng.normal(size=M) * 2.0 ** rng.integers(-6, 6, size=M)).astype(np.float32)
+        y = (rng.normal(size=N) * 2.0 ** rng.integers(-6, 6, size=N)).astype(np.float32)
+        c, e, row = _rowmajor_f32(x, y)
+        oc, oe, olr = oracle.sdtw_f32(x, y, lastrow=True)
+        assert (c.tobytes(), e) == (oc.tobytes(), oe)
+        assert row.tobytes() == olr.tobytes()
+
+
+def _dp_f32_double_accumulate(x, y):
+    """Planted mistake: each cell's distance and sum taken in double and
+    rounded to binary32 once, instead of once per operation."""
+    M, N = len(x), len(y)
+    C = [np.float32(0)] + [np.float32(np.inf)] * M
+    best, pos = np.float32(np.inf), -1
+    for j in range(N):
+        diag = np.float32(0)
+        for i in range(1, M + 1):
+            up, left = C[i - 1], C[i]
+            m = min(up, diag, left)
+            C[i] = np.float32(abs(float(x[i - 1]) - float(y[j])) + float(m))
+            diag = left
+        if C[M] < best:
+            best, pos = C[M], j
+    return best, pos
+
+
+def test_pins_reject_double_accumulating_f32():
+    caught = False
+    for x, y in _rounding_cases(41, 300):
+        c, e = _dp_f32_double_accumulate(x, y)
+        caught = caught or (Fraction(float(c)), e) != _enumerate_paths_f32(x, y)
+    assert caught
+
+
+# ---- z statistics of a first chunk and their application (section 4.1) -----
+
+
+def _zstats_ddof1(v):
+    """Planted mistake: the sample (n - 1) variance."""
+    v = np.asarray(v, np.float64)
+    return float(v.mean()), float(np.sqrt(((v - v.mean()) ** 2).sum() / (v.size - 1)))
+
+
+def test_zstats_hand_worked():
+    p = golden.prep_cases()
+    for key in ("", "2"):
+        v = np.array(p["ZSTATS_IN" + key], np.float32)
+        mean, sd = oracle.zstats(v)
+        assert mean == p["ZSTATS_MEAN" + key][0]
+        assert sd == np.sqrt(p["ZSTATS_VAR" + key][0])  # correctly rounded sqrt
+        m1, s1 = _zstats_ddof1(v)
+        assert s1 != sd  # the planted mistake fails this pin
+    assert oracle.zstats(np.full(7, 2.5, np.float32)) == (2.5, 0.0)
+    assert oracle.zstats(np.array([3.0], np.float32)) == (3.0, 0.0)
+
+
+def test_zstats_against_exact_rationals():
+    # mean and population sd from exact rational sums; the oracle accumulates
+    # in double, so it agrees to within a few double ulps
+    rng = np.random.default_rng(43)
+    for n in (2, 5, 250, 2000):
+        v = rng.normal(90, 12, size=n).astype(np.float32)
+        fr = [Fraction(float(a)) for a in v]
+        mean = sum(fr) / n
+        var = sum((a - mean) ** 2 for a in fr) / n
+        m, sd = oracle.zstats(v)
+        assert abs(Fraction(m) - mean) <= abs(mean) * Fraction(1, 2 ** 48)
+        assert abs(Fraction(sd) ** 2 - var) <= var * Fraction(1, 2 ** 46)
+        _, s1 = _zstats_ddof1(v)
+        assert abs(Fraction(s1) ** 2 - var) > var * Fraction(1, 2 ** 46)
+
+
+def test_zapply_hand_worked_and_consistent_with_znorm():
+    p = golden.prep_cases()
+    mean, sd = oracle.zstats(np.array(p["ZSTATS_IN"], np.float32))
+    out = oracle.zapply(np.array(p["ZAPPLY_IN"], np.float32), mean, sd)
+    want = (np.array(p["ZAPPLY_OUT_TIMES_SQRT5"]) / np.sqrt(5.0)).astype(np.float32)
+    assert np.array_equal(out, want)
+    # sd == 0 gives zeros
+    assert oracle.zapply(np.array([1, 2], np.float32), 1.0, 0.0).tolist() == [0.0, 0.0]
+    # statistics of a whole read applied to that read are its z-score
+    rng = np.random.default_rng(44)
+    for n in (1, 3, 400, 2000):
+        v = rng.normal(90, 12, size=n).astype(np.float32)
+        assert oracle.zapply(v, *oracle.zstats(v)).tobytes() == oracle.znorm(v).tobytes()

@@ -21,7 +21,16 @@ def comp(f, g, cap=None):
     return (min(g[0], f[0] + g[1]), d if cap is None else min(d, cap))
 
 
-def look_back(t, agg, inc, gag, GT, GW, rng, cap):
+def flag_roundtrip(f, dbits):
+    """A map published in a flag word and read back: status in the low two
+    bits, d in the next dbits bits, a above them (the kernel's 64-bit word
+    has dbits = 30 and a in the high 32 bits).  A d that does not fit in its
+    field spills into a's lowest bit and reads back truncated."""
+    w = (f[0] << (dbits + 2)) | (f[1] << 2) | 1
+    return (w >> (dbits + 2), (w & ((1 << (dbits + 2)) - 1)) >> 2)
+
+
+def look_back(t, agg, inc, gag, GT, GW, rng, cap, dbits):
     """x entering tile t, or None while a flag it needs is missing."""
     def seen(p):  # an inc flag may be published but not yet visible
         return p in inc and (p == 0 or rng.random() < 0.6)
@@ -40,7 +49,7 @@ def look_back(t, agg, inc, gag, GT, GW, rng, cap):
         for j in reversed(range(k)):
             win = comp(win, agg[lanes[j]], cap)
         if closer:
-            gag[t // GT] = comp(win, agg[t], cap)
+            gag[t // GT] = flag_roundtrip(comp(win, agg[t], cap), dbits)
         if kn is not None:
             part = IDN
             for j in reversed(range(kn)):
@@ -48,7 +57,7 @@ def look_back(t, agg, inc, gag, GT, GW, rng, cap):
             return min(part[0], inc[lanes[kn]] + part[1])
         acc = win
     elif closer:
-        gag[t // GT] = agg[t]
+        gag[t // GT] = agg[t]  # already a published word
     gbase, gacc = t // GT - 1, IDN
     while True:
         lanes = [gbase - k for k in range(GW)]
@@ -74,7 +83,7 @@ def look_back(t, agg, inc, gag, GT, GW, rng, cap):
         gbase -= GW
 
 
-def row_scan_sdtw(q, ref, C, TH, GT, GW, seed, cap=1 << 30):
+def row_scan_sdtw(q, ref, C, TH, GT, GW, seed, cap=(1 << 30) - 1, dbits=30):
     rng = np.random.default_rng(seed)
     x_all = q.astype(np.int64) + 32768
     y = ref.astype(np.int64) + 32768
@@ -100,11 +109,11 @@ def row_scan_sdtw(q, ref, C, TH, GT, GW, seed, cap=1 << 30):
             for m in maps:
                 ex.append(acc)
                 acc = comp(acc, m)
-            agg[t], before[t] = acc, ex
+            agg[t], before[t] = flag_roundtrip(acc, dbits), ex
         xin, pending = {}, list(rng.permutation(ntiles))
         while pending:
             t = int(pending.pop(0))
-            v = look_back(t, agg, inc, gag, GT, GW, rng, cap)
+            v = look_back(t, agg, inc, gag, GT, GW, rng, cap, dbits)
             if v is None:
                 pending.append(t)
                 continue
@@ -158,3 +167,33 @@ def test_planted_mistake_is_caught():
         assert bad > 0
     finally:
         comp = ok
+
+
+def test_group_maps_saturate_within_their_flag_field():
+    # Group maps saturate D at the largest value their flag field holds.  The
+    # field is narrowed here (15 bits) so that small groups reach the cap.
+    # Query (0, 500, 1000); the reference is one group of (0, 500) pairs, two
+    # groups of -1000 (their summed distances exceed the field) and one group
+    # of (500, 1000) pairs: the best cost is 500.  A path that skipped the
+    # middle groups for free would reach 0, which is what a map whose D spilt
+    # out of its field (a cap of 2^bits instead of 2^bits - 1) hands the
+    # tiles to the right whenever they look back over a saturated group.
+    bits, TH, C, GT = 15, 4, 3, 4
+    group = TH * C * GT
+    ref = np.array([0, 500] * (group // 2) + [-1000] * (2 * group) +
+                   [500, 1000] * (group // 2), np.int16)
+    q = np.array([0, 500, 1000], np.int16)
+    want = oracle.sdtw_i64(q, ref)
+    assert want == (500, 1)
+    fails = 0
+    for s in range(10):
+        assert row_scan_sdtw(q, ref, C, TH, GT, 2, s, cap=(1 << bits) - 1, dbits=bits) == want
+        fails += row_scan_sdtw(q, ref, C, TH, GT, 2, s, cap=1 << bits, dbits=bits) != want
+    assert fails > 0
+    # random values with the narrowed field and the right cap
+    rng = np.random.default_rng(100)
+    for s in range(6):
+        ref = rng.integers(-1000, 1000, size=480).astype(np.int16)
+        q = rng.integers(-1000, 1000, size=3).astype(np.int16)
+        assert row_scan_sdtw(q, ref, C, TH, GT, 2, s, cap=(1 << bits) - 1,
+                             dbits=bits) == oracle.sdtw_i64(q, ref)
