@@ -6,9 +6,12 @@ batched alignment of every read against the reference (sdtw_align_batch).
 The reference is prepared once on the device (sdtw_prepare_reference) before
 the timed region; all inputs are resident in HBM when timing starts.
 
-Workload (default): 4,096 reads of 250 events against the 59,796-value
-forward+reverse signal of a 29,903-base genome (seeded synthetic data of the
-SARS-CoV-2 workload's shape), int16 inputs with 32-bit accumulation.
+Workload (default, the largest batch): 1,024 reads of 250-500 events against
+the 9,999,990-value forward+reverse signal of a 5,000,000-base genome
+(seeded synthetic data; the reference is streamed through the kernel in
+column tiles), int16 inputs with 32-bit accumulation.  The 4,096-read and
+8,192-read workloads against the 29,903-base genome are measured in the same
+run (`extras.workloads`), in both number formats.
 
 `value` is GCUPS (cells = sum over reads of M x N, per second of step time).
 `extras.end_to_end` gives the same pass with its host transfers (inputs up
@@ -18,9 +21,10 @@ events on the launch stream, against the VALU roof of the chip: 256 CUs x 4
 SIMDs x 2.4 GHz, where a SIMD spends 4 cycles on a full-rate 32-bit VALU
 instruction of a 64-lane wave (min, max, min3, sad; 16 lanes per cycle) and 2
 cycles on a float32 add/sub (the published 157.3 TFLOP/s float32 vector peak
-is twice the full rate).  A cell costs v_min3_u32 + v_sad_u32 = 8 SIMD cycles
-per 64 cells on the int16 path and v_sub_f32 + v_min3_u32 + v_add_f32 = 2 + 4
-+ 2 = 8 on the float32 path: 19.66 TCUPS for both.
+is twice the full rate; the issue-rate measurements are in
+profiles/valu_issue_rates_gfx950.md).  A cell costs v_min3_u32 + v_sad_u32 =
+8 SIMD cycles per 64 cells on the int16 path and v_sub_f32 + v_min3_u32 +
+v_add_f32 = 2 + 4 + 2 = 8 on the float32 path: 19.66 TCUPS for both.
 """
 from __future__ import annotations
 
@@ -86,7 +90,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=1, choices=[1, 2, 3])
+    ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3])
     ap.add_argument("--dtype", default="i16", choices=["i16", "f32"])
     ap.add_argument("--strip", type=int, default=0)
     ap.add_argument("--chains", type=int, default=0)
@@ -208,9 +212,11 @@ def main():
 
     if not args.no_extras:
         out["extras"] = extras(sd, torch, dev, w, reads, zref, cref, args, stream)
-        out["extras"]["hip_graph"] = graph_step(sd, torch, step, cost, end, args.steps)
+        # about two seconds of replays each
+        reps = max(3, min(args.steps, int(2000 / max(ms_step, 1e-3))))
+        out["extras"]["hip_graph"] = graph_step(sd, torch, step, cost, end, reps)
         out["extras"]["end_to_end"] = end_to_end(sd, torch, dev, reads, ref, plan, dt, cells,
-                                                 args.steps)
+                                                 reps)
 
     if args.serve_seconds > 0:
         out["serving"] = serving(torch, dev, args.serve_seconds, args.serve_warmup,
@@ -288,8 +294,83 @@ def end_to_end(sd, torch, dev, reads, ref, plan, dt, cells, reps):
             "h2d_bytes": int(up), "d2h_bytes": int(reads.nq * 8), "passes": reps}
 
 
+def workload_leg(sd, torch, dev, c, stream, reps=10):
+    """Workload c in both number formats: device preparation, autotuned launch
+    shape, median kernel time of `reps` launches (HIP events on the launch
+    stream)."""
+    import synth
+    w = synth.workload(c)
+    reads = w.reads
+    g = torch.from_numpy(w.genome).to(dev)
+    tab = torch.from_numpy(w.table).to(dev)
+    zref, cref, _ = sd.prepare_reference(g, tab, w.k, 64.0)
+    raw = torch.from_numpy(reads.values).to(dev)
+    offs_dev = torch.from_numpy(reads.offsets).to(dev)
+    z, codes, _ = sd.prepare_queries(raw, offs_dev, 64.0)
+    out = {"workload": w.name, "reads": int(reads.nq), "reference_values": int(zref.numel())}
+    for name, dt, rv, q in (("i16", sd.I16, cref, codes), ("f32", sd.F32, zref, z)):
+        ref = sd.Reference(rv)
+        plan = sd.Plan(reads.offsets, dt)
+        sd.autotune(ref, plan, q)
+        cost, end = sd.align_batch(ref, plan, q)
+        ms = _median_event_ms(torch, stream, lambda: sd.align_batch(ref, plan, q, cost, end),
+                              reps)
+        cells = float(reads.lengths.sum()) * ref.n
+        out[name] = {"kernel_ms": round(ms, 4), "gcups": round(cells / ms / 1e6, 1),
+                     "frac_valu_peak": round(cells / ms / 1e9 / valu_peak_tcups(name), 4),
+                     **plan.config}
+        plan.close()
+        ref.close()
+    return out
+
+
+def scale_sweep(sd, torch, dev):
+    """Accuracy against the fixed-point scale (section 6): for scales 2 ..
+    256, the share of the 4,096 reads of workload 1 whose int16-path end
+    equals the float32-path end, and the saturated values."""
+    import synth
+    w = synth.workload(1)
+    reads = w.reads
+    g = torch.from_numpy(w.genome).to(dev)
+    tab = torch.from_numpy(w.table).to(dev)
+    raw = torch.from_numpy(reads.values).to(dev)
+    offs = torch.from_numpy(reads.offsets).to(dev)
+    zref, _, _ = sd.prepare_reference(g, tab, w.k, 64.0)
+    fref = sd.Reference(zref)
+    zq, _, _ = sd.prepare_queries(raw, offs, 64.0)
+    fplan = sd.Plan(reads.offsets, sd.F32)
+    _, fend = sd.align_batch(fref, fplan, zq)
+    torch.cuda.synchronize()
+    fend = fend.cpu().numpy()
+    on = reads.on_target
+    rows = []
+    for s in (2, 4, 8, 16, 32, 64, 128, 256):
+        _, cref, rsat = sd.prepare_reference(g, tab, w.k, float(s))
+        _, cq, qsat = sd.prepare_queries(raw, offs, float(s))
+        iref = sd.Reference(cref)
+        iplan = sd.Plan(reads.offsets, sd.I16)
+        _, iend = sd.align_batch(iref, iplan, cq)
+        torch.cuda.synchronize()
+        iend = iend.cpu().numpy()
+        same = iend == fend
+        rows.append({"scale": s,
+                     "pct_end_equal_all": round(100 * float(same.mean()), 2),
+                     "pct_end_equal_on_target": round(100 * float(same[on].mean()), 2),
+                     "pct_end_within_10_on_target": round(
+                         100 * float((np.abs(iend - fend) <= 10)[on].mean()), 2),
+                     "saturated_reference_values": int(rsat),
+                     "saturated_query_values": int(qsat)})
+        iplan.close()
+        iref.close()
+    fplan.close()
+    fref.close()
+    return {"workload": w.name, "reads": int(reads.nq), "by_scale": rows}
+
+
 def extras(sd, torch, dev, w, reads, zref, cref, args, stream):
-    """The other number format and the one-read-per-launch baseline."""
+    """The other number format, the other workloads, the one-read-per-launch
+    baseline, the whole-device single query, event detection and the
+    accuracy-against-scale sweep."""
     res = {}
     other = "f32" if args.dtype == "i16" else "i16"
     dt = sd.F32 if other == "f32" else sd.I16
@@ -301,23 +382,21 @@ def extras(sd, torch, dev, w, reads, zref, cref, args, stream):
     plan = sd.Plan(reads.offsets, dt)
     sd.autotune(ref, plan, q)
     cost, end = sd.align_batch(ref, plan, q)
-    torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record(stream)
-    for _ in range(5):
-        sd.align_batch(ref, plan, q, cost, end)
-    b.record(stream)
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / 5
+    reps = 5 if ref.n > 1_000_000 else 20
+    ms = _median_event_ms(torch, stream, lambda: sd.align_batch(ref, plan, q, cost, end), reps)
     cells = float(reads.lengths.sum()) * ref.n
     res[other] = {"kernel_ms": round(ms, 4), "gcups": round(cells / ms / 1e6, 1),
                   "frac_valu_peak": round(cells / ms / 1e9 / valu_peak_tcups(other), 4),
                   **plan.config}
+    plan.close()
+    # the other batch workloads, both number formats
+    res["workloads"] = [workload_leg(sd, torch, dev, c, stream) for c in (1, 2, 3)
+                        if c != args.config]
     # one read per launch with the single-wave kernel, on the main dtype
     dt0 = sd.I16 if args.dtype == "i16" else sd.F32
     ref0 = sd.Reference(cref if dt0 == sd.I16 else zref)
     q0 = codes if dt0 == sd.I16 else z
-    n1 = min(256, reads.nq)
+    n1 = min(256 if ref0.n < 1_000_000 else 2, reads.nq)
     offs = reads.offsets
     sd.align_one(ref0, q0[offs[0]:offs[1]])
     torch.cuda.synchronize()
@@ -339,16 +418,17 @@ def extras(sd, torch, dev, w, reads, zref, cref, args, stream):
             "paper_accelerator_model_ms": round((ref0.n + m1 - 1) / 1e8 * 1e3, 4)}
     # pre-processing on the device: event detection and trimming of raw reads
     import synth
-    rr = synth.simulate_raw(w.genome, w.table, 4096, 320, 0.5, 4242)
+    sg = synth.make_genome(synth.SMALL_GENOME, synth.SMALL_GENOME)
+    rr = synth.simulate_raw(sg, w.table, 4096, 320, 0.5, 4242)
     xr = torch.from_numpy(rr.values).to(dev)
     xo = torch.from_numpy(rr.offsets).to(dev)
     ms_ev = _median_event_ms(torch, stream, lambda: sd.detect_events(xr, xo, 50, 250), 5)
     res["event_detection"] = {"raw_reads": rr.nreads, "raw_samples": int(rr.values.size),
                               "trim": 50, "keep": 250, "ms": round(ms_ev, 4),
                               "reads_per_s": round(rr.nreads / (ms_ev * 1e-3), 1)}
+    res["accuracy_vs_scale"] = scale_sweep(sd, torch, dev)
     ref0.close()
     ref.close()
-    plan.close()
     return res
 
 
@@ -411,7 +491,9 @@ def cpu_baseline(w, reads, args):
     import oracle
     z, codes, _ = oracle.prepare_reference(w.genome, w.table, w.k)
     qz, qc, _ = oracle.prepare_queries(reads.values, reads.offsets)
-    cores = len(os.sched_getaffinity(0))
+    # the host share of one GPU on the GPU machines is 16 cores, whatever the
+    # affinity mask shows
+    cores = min(16, len(os.sched_getaffinity(0)))
     kind = oracle.I64 if args.dtype == "i16" else oracle.F32
     q = qc if args.dtype == "i16" else qz
     r = codes if args.dtype == "i16" else z
@@ -429,7 +511,9 @@ def cpu_baseline(w, reads, args):
     cells = float(reads.lengths[:n].sum()) * r.size
     return {"value": round(cells / t / 1e9, 3), "unit": "GCUPS", "cores": used,
             "kind": "oracle", "seconds": round(t, 2),
-            "sample": f"first {n} reads of the same batch, {'int64' if kind == oracle.I64 else 'float32'} oracle"}
+            "sample": f"first {n} of the {reads.nq} reads of the same batch "
+                      f"({cells:.3g} cells), {'int64' if kind == oracle.I64 else 'float32'} "
+                      f"oracle, one read per task on {used} threads"}
 
 
 if __name__ == "__main__":

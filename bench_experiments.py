@@ -20,7 +20,7 @@ serving  The Read Until server (workload 4) against the channel count and the
          for the 29,903-base target alone and for both targets (50/50), and
          with a budget that holds only part of the large target's rows.
 decision The two decision rules of the server (per-event cost threshold and
-         the mapping-quality score from best and runner-up ends, section 5.2)
+         the mapping-quality score from best and runner-up ends, section 5.1)
          on both targets at 512 channels, with off-target reads that are
          i.i.d. noise and, harder, pore signal of a 1,000,000-base background
          genome: accuracy, on-target reads kept, off-target reads rejected,

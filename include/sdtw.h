@@ -95,7 +95,9 @@ int sdtw_version(void);
  *   z_dev       out float32[2(L-k+1)]: forward strand k-mers 0..L-k, then
  *               the reverse-complement strand read 5'->3', jointly z-scored
  *               (mean and population standard deviation of the whole
- *               concatenation, accumulated in double; sd == 0 gives zeros).
+ *               concatenation, each sum accumulated in double in index
+ *               order, so the statistics equal a plain sequential loop's
+ *               bit for bit; sd == 0 gives zeros).
  *   codes_dev   out int16[2(L-k+1)] or NULL: saturate(rint(z * scale)), the
  *               product and rounding in double, round-half-even.
  *   nsat_dev    out int64[1] or NULL: number of saturated codes.
@@ -139,7 +141,7 @@ int sdtw_prepare_queries_ex(const float* raw_dev, const int64_t* offsets_dev, in
 
 /*
  * Event detection (section 4.1: raw samples are cut into events before
- * normalisation; section 5.3: the R9.4 parameters of the f5c / nanopolish
+ * normalisation; section 5.2: the R9.4 parameters of the f5c / nanopolish
  * two-window t-test detector).  Per read: t statistics over windows of 3
  * and 6 samples, a short (threshold 1.4) and a long (threshold 9.0) peak
  * detector with peak height 0.2 give the event boundaries; an event's value
@@ -359,7 +361,7 @@ int sdtw_align_one(sdtw_ref ref, const void* q_dev, int32_t M, void* cost_dev,
  * latency no longer grows with N / (columns of one workgroup).
  *   q_dev  M int16 values; 1 <= M <= SDTW_MAX_QUERY.
  *   cols   columns per thread, 8, 16, 32 or 64; 0 = the fewest that cut the
- *          reference into at most 64 tiles, else into at most 256, else 64
+ *          reference into at most 64 tiles, else into at most 256, else 32
  *          (the fastest choice measured for each reference length).
  *   cost_dev  out int32[1]; end_dev out int32[1] (0-based column).
  * Enqueues three kernels and records an event that tracks the reuse of its
@@ -442,7 +444,7 @@ int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk
 /*
  * Best and runner-up ends of the resident rows of `ns` streams on one
  * reference: the two mapped positions and scores a mapping quality is
- * computed from (section 5.2).  best = the first column with the row's
+ * computed from (section 5.1).  best = the first column with the row's
  * minimum (the end the last sdtw_stream_extend returned); second = the first
  * column with the minimum among the columns farther than `window` from best.
  *   window           >= 0 columns.

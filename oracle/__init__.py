@@ -20,11 +20,11 @@ What it computes (each function cites the passage it follows):
 * ``batch``         -- the same over a CSR batch of reads with POSIX threads.
 * ``best_two``      -- the best end and the best end outside a window around
   it, on a last row (the two mapped positions a MAPQ-like decision compares;
-  section 5.2 computes a mapping quality from the positions and scores).
+  section 5.1 computes a mapping quality from the positions and scores).
 
 * ``oracle.events`` -- event detection on raw samples (section 4.1's
   pre-processing with the two-window t-test detector whose R9.4 parameters
-  section 5.3 takes from f5c and nanopolish), and prefix trimming; plain
+  section 5.2 takes from f5c and nanopolish), and prefix trimming; plain
   Python.
 
 The C source is ``sdtw_oracle.c``; ``build()`` compiles it with gcc.  The

@@ -2,10 +2,13 @@
 ONLY; the same rules as the package doc of ``oracle``).
 
 Section 4.1 (software processing layer) segments each read's raw samples
-into events before normalisation, to shrink the query; section 5.3 takes the
+into events before normalisation, to shrink the query; section 5.2 takes the
 R9.4 event-detection parameters from f5c and nanopolish, whose detector is a
 two-window t-test.  The paper prints neither the algorithm nor its numbers,
-so this module follows a reading of that detector, stated in full:
+so this module follows a reading of that detector, stated in full.  Parity
+unpinned against the paper: nothing the paper prints fixes these events;
+the tests pin the reading itself (hand-worked detector traces, window
+statistics against closed forms).
 
 1. t statistic at every boundary position i (between samples i-1 and i), for
    a window length w: with m1, v1 the mean and population variance of

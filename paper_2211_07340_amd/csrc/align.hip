@@ -442,7 +442,13 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
       for (int h = 1; h < K; ++h) left[h] = up[h * H - 1];
       if constexpr (CH >= 0) {
         if (lane == r / K) {
-          [[maybe_unused]] const uint32_t old_last = up[W - 1];
+          // the band below needs this tile's last column (lane 63's last
+          // value of the finished row): stored before the groups reload the
+          // registers, so that the last group's loads can go straight into
+          // them and the cells wait for the groups in order
+          if constexpr (P > 1 && CH == K - 1) {
+            if (!last && lane == 63) edge_out[(p - 1) & 3] = up[W - 1];
+          }
           // the diagonal first (the first cell needs it), then per group of
           // four columns: new reference values, the finished row's values
           // out (the last band's fin is the stage itself, so each group is
@@ -478,9 +484,6 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
               up[w + 3] = zv.w;
             }
             __builtin_amdgcn_sched_barrier(0);
-          }
-          if constexpr (P > 1 && CH == K - 1) {
-            if (!last && lane == 63) edge_out[(p - 1) & 3] = old_last;
           }
         }
       }

@@ -85,7 +85,7 @@ inline int64_t padded_length(int64_t n) {
 hipError_t launch_prepare_reference(const uint8_t* g, int64_t L, const float* table,
                                     int k, double scale, float* z, int16_t* codes,
                                     int64_t* nsat, double* scratch, hipStream_t st);
-constexpr int kRefPartials = 512;  // doubles of scratch: partials + 2 stats
+constexpr int kRefPartials = 2;  // doubles of scratch: the reference's mean and sd
 hipError_t launch_prepare_queries(const float* raw, const int64_t* offs, int32_t nq,
                                   double scale, const double* stats_in, double* stats_out,
                                   float* z, int16_t* codes, int64_t* nsat, hipStream_t st);

@@ -1,6 +1,6 @@
 // Event detection on the device: raw samples of each read -> the event values
 // the alignment uses as its query (section 4.1 segments raw samples into
-// events before normalisation; section 5.3 takes its R9.4 parameters from the
+// events before normalisation; section 5.2 takes its R9.4 parameters from the
 // two-window t-test detector of f5c and nanopolish).
 //
 // The detector, as this library reads it:

@@ -1,9 +1,10 @@
 // Reference and query preparation (section 4.1; section 2.2 k-mer model).
 //
 // Reference: k-mer model lookup of both strands (one thread per output
-// sample), then a joint z-score whose mean and population sd are accumulated
-// in double by a fixed-partition, fixed-order reduction (deterministic from
-// run to run), then fixed-point codes.
+// sample), then a joint z-score over the concatenation whose mean and
+// population sd are accumulated in double in index order by one lane (the
+// same sequence of IEEE double operations as a plain sequential loop; it is
+// a one-time step), then fixed-point codes.
 //
 // Queries: one wave per read; lane 0 walks the read's events in index order
 // for the mean and for the sum of squared deviations, so each read's
@@ -41,47 +42,6 @@ __global__ void k_kmer(const uint8_t* __restrict__ g, int64_t L, int k,
     for (int m = 0; m < k; ++m) idx = idx * 4u + (3u - (g[L - 1 - (q + m)] & 3u));
   }
   sig[p] = table[idx];
-}
-
-// mode 0: partial sums of x; mode 1: partial sums of (x - mean)^2.
-// Block b owns [b*chunk, min(n, (b+1)*chunk)); fixed order within the block.
-__global__ void k_partial(const float* __restrict__ x, int64_t n, int64_t chunk, int mode,
-                          const double* __restrict__ stats, double* __restrict__ partials) {
-  __shared__ double red[kPrepThreads];
-  const int64_t lo = (int64_t)blockIdx.x * chunk;
-  const int64_t hi = min(n, lo + chunk);
-  const double mean = mode ? stats[0] : 0.0;
-  double acc = 0.0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += kPrepThreads) {
-    double v = (double)x[i];
-    if (mode) {
-      double d = v - mean;
-      acc += d * d;
-    } else {
-      acc += v;
-    }
-  }
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = kPrepThreads / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
-}
-
-// One thread: stats[0] = mean (mode 0) or stats[1] = population sd (mode 1).
-__global__ void k_finalize(const double* __restrict__ partials, int nb, int64_t n, int mode,
-                           double* __restrict__ stats, int64_t* __restrict__ nsat) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += partials[b];
-  if (mode == 0) {
-    stats[0] = s / (double)n;
-    if (nsat) *nsat = 0;
-  } else {
-    stats[1] = sqrt(s / (double)n);
-  }
 }
 
 // x and z may be the same array (normalised in place): each thread reads its
@@ -132,6 +92,21 @@ __device__ __forceinline__ double wave_seq_sum(const float* __restrict__ raw, in
     __syncthreads();
   }
   return __shfl(acc, 0);
+}
+
+// One wave: stats[0] = mean and stats[1] = population sd of x[0..n), each
+// sum accumulated by lane 0 in index order; nsat (optional) cleared.
+__global__ __launch_bounds__(64) void k_seq_stats(const float* __restrict__ x, int64_t n,
+                                                  double* __restrict__ stats,
+                                                  int64_t* __restrict__ nsat) {
+  __shared__ float buf[kQChunk];
+  const double mean = wave_seq_sum(x, 0, n, 0.0, false, buf) / (double)n;
+  const double sd = sqrt(wave_seq_sum(x, 0, n, mean, true, buf) / (double)n);
+  if (threadIdx.x == 0) {
+    stats[0] = mean;
+    stats[1] = sd;
+    if (nsat) *nsat = 0;
+  }
 }
 
 // stats_in (optional): per-read (mean, sd) to apply instead of the read's
@@ -203,17 +178,8 @@ hipError_t launch_prepare_reference(const uint8_t* g, int64_t L, const float* ta
   // the raw signal is produced in z and normalised in place
   hipLaunchKernelGGL(k_kmer, dim3(grid_for(n, kPrepThreads)), dim3(kPrepThreads), 0, st,
                      g, L, k, table, z);
-  double* partials = scratch;
-  double* stats = scratch + (kRefPartials - 2);
-  int nb = (int)std::min<int64_t>(kRefPartials - 2, (n + kPrepThreads - 1) / kPrepThreads);
-  if (nb < 1) nb = 1;
-  const int64_t chunk = (n + nb - 1) / nb;
-  for (int mode = 0; mode < 2; ++mode) {
-    hipLaunchKernelGGL(k_partial, dim3(nb), dim3(kPrepThreads), 0, st, z, n, chunk, mode,
-                       stats, partials);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, partials, nb, n, mode, stats,
-                       mode == 0 ? nsat : nullptr);
-  }
+  double* stats = scratch;
+  hipLaunchKernelGGL(k_seq_stats, dim3(1), dim3(64), 0, st, z, n, stats, nsat);
   hipLaunchKernelGGL(k_normalize, dim3(grid_for(n, kPrepThreads)), dim3(kPrepThreads), 0, st,
                      z, n, stats, scale, z, codes, nsat);
   return hipGetLastError();

@@ -1,4 +1,4 @@
-// Best and runner-up ends of resident last rows (section 5.2: a mapping
+// Best and runner-up ends of resident last rows (section 5.1: a mapping
 // quality is computed from the mapped positions and their scores before the
 // selection decision).
 //

@@ -24,7 +24,7 @@ This module simulates the channels and runs the decisions through the C ABI:
   own streams, so short-reference work never waits behind long-reference
   work (give the process at least as many hardware queues as streams,
   GPU_MAX_HW_QUEUES, or streams share queues and run in order);
-* decision rules (readings; section 5.2 only says that a mapping quality
+* decision rules (readings; section 5.1 only says that a mapping quality
   is computed from the mapped positions and scores and that the selection
   criteria act on it):
   ``decision="cost"``: s = cost / (scale * rows), the mean per-event

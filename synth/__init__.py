@@ -7,7 +7,7 @@ would hand to the method, in raw units.
 * ``make_genome``       -- uniform random bases A/C/G/T coded 0..3.
 * ``make_level_table``  -- a stand-in pore model: one expected current per
   6-mer, drawn i.i.d. from N(90, 12) pA (the real R9.4 table is not
-  available; section 5.3 data are not available either).
+  available; the section 5.3 datasets are not available either).
 * ``simulate_raw``      -- raw sample streams in pA (30 adaptor levels, then
   one level per base, each held for 4-14 samples, N(0, 1.5 pA) sample
   noise), the input of event detection.

@@ -126,3 +126,91 @@ def test_raw_mode_served_results_match_oracle():
             assert (cost, end) == oracle.sdtw_i64(q, codes_of[t]), (t, pi, rows)
     for t in targets:
         t.ref.close()
+
+
+def _check_records(rec, t, raws, codes, n, seed):
+    """A seeded sample of n records of target t equals the int64 oracle on
+    the read's prefix, normalised with its first chunk."""
+    mine = [r for r in rec if r[0] == t]
+    assert mine, f"nothing served for target {t}"
+    rng = np.random.default_rng(seed)
+    pick = [mine[i] for i in rng.choice(len(mine), min(n, len(mine)), replace=False)]
+    qs = [_prefix_codes(raws[r[1]], r[2]) for r in pick]
+    q, offs = synth.csr(qs)
+    want_c, want_e, _ = oracle.batch(oracle.I64, q.astype(np.int16), offs, codes,
+                                     nthreads=THREADS)
+    got = [(r[3], r[4]) for r in pick]
+    assert got == list(zip(want_c.astype(np.int64).tolist(), want_e.tolist())), t
+    return len(pick), len(mine)
+
+
+THREADS = 16
+
+
+def _targets(dev, lengths, pool, seed):
+    from paper_2211_07340_amd import server as srv
+    table = synth.make_level_table()
+    targets, codes_of, raws_of = [], [], []
+    for i, L in enumerate(lengths):
+        genome = synth.make_genome(L, L)
+        rd = synth.simulate_reads(genome, table, np.full(pool, 2000), 0.5, seed + i)
+        raws = [rd.values[rd.offsets[r]:rd.offsets[r + 1]] for r in range(pool)]
+        _, codes, _ = oracle.prepare_reference(genome, table, 6)
+        targets.append(srv.Target(f"{L}-base", sd.Reference(torch.from_numpy(codes).to(dev)),
+                                  raws, np.asarray(rd.on_target, bool)))
+        codes_of.append(codes)
+        raws_of.append(raws)
+    return targets, codes_of, raws_of
+
+
+def test_large_target_served_results_match_oracle():
+    # the serving workload's two targets at their full sizes: the 29,903-base
+    # genome and the 5,000,000-base genome (9,999,990 columns, 40 MB resident
+    # rows); 32 served results of the large target and 16 of the small one
+    # equal the oracle
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_07340_amd import server as srv
+    dev = torch.device("cuda:0")
+    targets, codes_of, raws_of = _targets(dev, (synth.SMALL_GENOME, synth.LARGE_GENOME), 32, 95)
+    rec = []
+    server = srv.ReadUntilServer(targets, srv.ServerConfig(channels=32, row_budget_bytes=8 << 30),
+                                 record=rec)
+    server.calibrate(n_each=8)
+    res = server.run(4.0, 0.5)
+    print("large target", {k: res[k] for k in ("decisions", "decision_accuracy", "per_target")},
+          flush=True)
+    assert res["decision_accuracy"] > 0.9, res
+    n1, m1 = _check_records(rec, 1, raws_of[1], codes_of[1], 32, 5)
+    n0, m0 = _check_records(rec, 0, raws_of[0], codes_of[0], 16, 6)
+    print(f"checked {n1} of {m1} large-target and {n0} of {m0} small-target records",
+          flush=True)
+    assert n1 == 32
+    for t in targets:
+        t.ref.close()
+
+
+def test_small_budget_admission_waits_keep_results():
+    # a row budget of 8 rows of the 600,000-base target (4.8 MB each) for 32
+    # channels: reads wait for admission and their chunks queue; what is
+    # served still equals the oracle
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_07340_amd import server as srv
+    dev = torch.device("cuda:0")
+    targets, codes_of, raws_of = _targets(dev, (synth.SMALL_GENOME, 600_000), 32, 97)
+    row_bytes = 4 * (((1_199_990 + 2047) // 2048) * 2048 + 2048)
+    rec = []
+    budget = 8 * row_bytes
+    server = srv.ReadUntilServer(targets, srv.ServerConfig(channels=32, row_budget_bytes=budget),
+                                 record=rec)
+    server.calibrate(n_each=8, group=4)  # 4 rows at a time fit the budget
+    res = server.run(3.0, 0.5)
+    sd.set_row_budget(16 << 30)
+    print("small budget", {k: res[k] for k in ("decisions", "admission_waits",
+                                                "max_waiting_chunks")}, flush=True)
+    assert res["admission_waits"] > 0 and res["decisions"] > 10, res
+    for t in (0, 1):
+        _check_records(rec, t, raws_of[t], codes_of[t], 16, 7 + t)
+    for t in targets:
+        t.ref.close()
