@@ -374,6 +374,26 @@ int sdtw_align_one(sdtw_ref ref, const void* q_dev, int32_t M, void* cost_dev,
 int sdtw_align_one_wide(sdtw_ref ref, const void* q_dev, int32_t M, int cols, void* cost_dev,
                         int32_t* end_dev, void* stream);
 
+/*
+ * sdtw_align_one_wide for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels, arguments and results, but the scratch is a
+ * fixed array of 2^20 64-bit words (8 MiB) that the library holds on every
+ * device it runs on until the process ends, and the call records no event.
+ * It calls no hipMalloc, hipFree or allocating routine; the first call on a
+ * device looks the array's address up once.
+ *   Limit: wide scratch words = 2 M t + M ceil(t / 64) + t + 1 for t =
+ *   ceil(N / (256 cols)) tiles must not exceed 2^20 (EINVAL otherwise, with
+ *   the sizes in the message; nothing is launched).  For example M = 250
+ *   fits up to about 16 M columns at cols = 32.
+ *   Every call on a device shares that device's array, which keeps the last
+ *   call's contents (each call clears what it needs itself, with a kernel):
+ *   calls that overlap in time on one device race and must be ordered by
+ *   the caller (one stream, or events).
+ */
+int sdtw_align_one_wide_noalloc(sdtw_ref ref, const void* q_dev, int32_t M, int cols,
+                                void* cost_dev, int32_t* end_dev, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Streaming extension (Read Until: section 2.2 rejection before most of a   */
 /* read is sequenced; section 4.1 reads arrive as the sequencer produces     */

@@ -59,6 +59,7 @@ def load_library():
         "sdtw_align_batch": ([p, p, p, p, p, p], C.c_int),
         "sdtw_align_one": ([p, p, i32, p, p, p], C.c_int),
         "sdtw_align_one_wide": ([p, p, i32, C.c_int, p, p, p], C.c_int),
+        "sdtw_align_one_wide_noalloc": ([p, p, i32, C.c_int, p, p, p], C.c_int),
         "sdtw_detect_events": ([p, p, i32, i32, i32, p, p, p], C.c_int),
         "sdtw_detect_events_prefix": ([p, p, p, i32, i32, i32, p, p, p], C.c_int),
         "sdtw_event_state_bytes": ([], C.c_int64),
@@ -411,6 +412,16 @@ def align_one_wide(ref: Reference, q, cols: int = 0, cost=None, end=None, stream
     _check(load_library().sdtw_align_one_wide(ref.handle, _dev(q, torch.int16, "q"), q.numel(),
                                               int(cols), _dev(cost),
                                               _dev(end, torch.int32, "end"), _stream(stream)))
+    return cost, end
+
+
+def align_one_wide_noalloc(ref: Reference, q, cost, end, cols: int = 0, stream=None):
+    """sdtw_align_one_wide_noalloc: the same on the library's fixed scratch;
+    the caller passes the outputs (int32[1] each), nothing is allocated."""
+    torch = _torch()
+    _check(load_library().sdtw_align_one_wide_noalloc(
+        ref.handle, _dev(q, torch.int16, "q"), q.numel(), int(cols),
+        _dev(cost, torch.int32, "cost"), _dev(end, torch.int32, "end"), _stream(stream)))
     return cost, end
 
 

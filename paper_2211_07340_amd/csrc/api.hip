@@ -764,6 +764,33 @@ int sdtw_align_one_wide(sdtw_ref ref, const void* q_dev, int32_t M, int cols, vo
   return rc ? rc : rc_ev;
 }
 
+int sdtw_align_one_wide_noalloc(sdtw_ref ref, const void* q_dev, int32_t M, int cols,
+                                void* cost_dev, int32_t* end_dev, void* stream) {
+  SDTW_REQUIRE(ref, "sdtw_align_one_wide_noalloc: null reference");
+  SDTW_REQUIRE(q_dev && cost_dev && end_dev, "sdtw_align_one_wide_noalloc: null device pointer");
+  SDTW_REQUIRE(ref->dtype == SDTW_I16, "sdtw_align_one_wide_noalloc: int16 references only");
+  SDTW_REQUIRE(M >= 1 && M <= SDTW_MAX_QUERY, "sdtw_align_one_wide_noalloc: M=%d outside [1, %d]",
+               M, SDTW_MAX_QUERY);
+  SDTW_REQUIRE(cols == 0 || cols == 8 || cols == 16 || cols == 32 || cols == 64,
+               "sdtw_align_one_wide_noalloc: cols=%d not in {0, 8, 16, 32, 64}", cols);
+  if (int rc = require_device(ref->device, "sdtw_align_one_wide_noalloc")) return rc;
+  if (cols == 0) cols = wide_pick_cols(ref->n, ref->device);
+  SDTW_REQUIRE(wide_tiles(ref->n, cols) <= (int64_t)INT32_MAX,
+               "sdtw_align_one_wide_noalloc: reference too long for %d columns per thread", cols);
+  const int64_t need = wide_scratch_words(ref->n, M, cols);
+  SDTW_REQUIRE(need <= wide_noalloc_words(),
+               "sdtw_align_one_wide_noalloc: %d rows x %lld columns at %d columns per thread "
+               "need %lld words of scratch, the fixed array holds %lld", M, (long long)ref->n,
+               cols, (long long)need, (long long)wide_noalloc_words());
+  uint64_t* scratch = nullptr;
+  int rc = check_hip(wide_noalloc_scratch(ref->device, &scratch),
+                     "sdtw_align_one_wide_noalloc: scratch address");
+  if (rc) return rc;
+  return check_hip(launch_align_wide(ref->data, ref->n, (const int16_t*)q_dev, M, cols, scratch,
+                                     (int32_t*)cost_dev, end_dev, (hipStream_t)stream),
+                   "sdtw_align_one_wide_noalloc: launch");
+}
+
 // ---------------------------------------------------------------------------
 // autotuning
 // ---------------------------------------------------------------------------

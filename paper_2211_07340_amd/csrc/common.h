@@ -173,6 +173,11 @@ hipError_t launch_events_continue(const float* raw, const int64_t* ranges, const
 int64_t wide_tiles(int64_t n, int cols);
 int64_t wide_scratch_words(int64_t n, int32_t m, int cols);
 int wide_pick_cols(int64_t n, int device);  // columns per thread for sdtw_align_one_wide(cols=0)
+// The fixed per-device scratch of sdtw_align_one_wide_noalloc: its size in
+// 64-bit words, and its device address on `device` (the current device),
+// looked up once per device.
+int64_t wide_noalloc_words();
+hipError_t wide_noalloc_scratch(int device, uint64_t** out);
 hipError_t launch_align_wide(const uint32_t* ref, int64_t n, const int16_t* q, int32_t m,
                              int cols, uint64_t* scratch, int32_t* cost, int32_t* end,
                              hipStream_t st);

@@ -36,9 +36,20 @@
 // min picks the same value as with the exact sum, and kInf + D < 2^32.
 #include <limits.h>
 
+#include <mutex>
+
 #include "common.h"
 
 namespace sdtw {
+
+// Scratch of sdtw_align_one_wide_noalloc: one fixed array per device (every
+// device the library runs on holds it until the process ends), so that the
+// call allocates nothing.  Host code never passes the array's name to a
+// kernel (on the host it is a stand-in, not a device address); it passes the
+// address hipGetSymbolAddress returns for the current device.
+constexpr int64_t kNoallocWords = int64_t(1) << 20;  // 64-bit words: 8 MiB
+static __device__ __align__(256) uint64_t g_noalloc_scratch[kNoallocWords];
+
 namespace {
 
 constexpr int kWideThreads = 256;
@@ -436,6 +447,25 @@ int wide_pick_cols(int64_t n, int device) {
     for (int k = 0; k < 4; ++k)
       if (wide_tiles(n, cols[k]) <= limit) return cols[k];
   return 32;
+}
+
+int64_t wide_noalloc_words() { return kNoallocWords; }
+
+hipError_t wide_noalloc_scratch(int device, uint64_t** out) {
+  constexpr int kDevices = 64;
+  static std::mutex mu;
+  static uint64_t* addr[kDevices] = {};
+  if (device < 0 || device >= kDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_noalloc_scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[device] = (uint64_t*)p;
+  }
+  *out = addr[device];
+  return hipSuccess;
 }
 
 int64_t wide_tiles(int64_t n, int cols) { return (n + (int64_t)kWideThreads * cols - 1) /
