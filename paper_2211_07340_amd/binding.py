@@ -488,6 +488,10 @@ class Stream:
         return self._h
 
     @property
+    def closed(self) -> bool:
+        return self._h is None
+
+    @property
     def rows(self) -> int:
         r, n = C.c_int32(), C.c_int64()
         _check(load_library().sdtw_stream_info(self.handle, C.byref(r), C.byref(n)))

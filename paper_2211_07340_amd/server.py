@@ -44,6 +44,26 @@ This module simulates the channels and runs the decisions through the C ABI:
 ``mode="recompute"`` aligns every chunk's whole prefix from scratch instead
 (a fresh stream extended by the full prefix), for comparison.
 
+Faults.  A read must be decided while most of the molecule is still in the
+pore (section 2.2); a lost or late decision only costs sequencing time, so
+the loop gives such reads up rather than stalling:
+
+* ``end_read(channel)``: the read ended before a decision (the molecule left
+  the pore).  Its queued chunk is dropped, a chunk in flight finishes and its
+  result is ignored, its row is released once no work that uses it is in
+  flight (a close waits for such work), and the channel starts its next read;
+* a row closed elsewhere (``handle.closed``): the read restarts on a new row
+  from its first event -- the whole prefix in one extension, equal to
+  extending it chunk by chunk;
+* ``SDTW_EBUDGET`` on a row: the chunk waits for a row (admission queue); in
+  recompute mode too, where each chunk takes a fresh row;
+* ``chunk_timeout_s``: a read whose chunk has waited longer than this since it
+  arrived, queued or in flight, is given up undecided (``timeouts``).
+
+``run(..., events=[(seconds, fn), ...])`` calls ``fn(server)`` once the
+server's clock passes each time, and the constructor takes the clock and the
+wait of the loop, so that these faults can be forced on the host.
+
 ``ServerConfig(raw=True)`` serves raw current instead of events (targets from
 ``make_raw_targets``): every chunk period a channel's read has
 ``chunk_samples`` more samples (the pool's samples are resident on the
@@ -88,6 +108,7 @@ class ServerConfig:
     raw: bool = False                  # chunks of raw samples, events detected on the device
     chunk_samples: int = 2400          # raw mode: samples per channel per chunk period
     trim_events: int = 50              # raw mode: adaptor events dropped at a read's start
+    chunk_timeout_s: float | None = None  # give up a read whose chunk waits longer (None: never)
 
 
 @dataclass
@@ -120,6 +141,8 @@ class _Read:
     chunks_done: int = 0
     have: int = 0                      # raw mode: events detected (buffered) so far
     fresh_state: bool = True           # raw mode: its detector state is still to be reset
+    restart: bool = False              # its row was lost: the next extension starts at event 0
+    abandoned: str | None = None       # "ended" or "timeout" once given up undecided
 
 
 @dataclass
@@ -134,7 +157,6 @@ class _Tick:
     second_end: object
     t_submit: float
     cells: float
-    scratch: list                      # recompute mode: fresh streams to close
 
 
 @dataclass
@@ -153,6 +175,9 @@ class ServerStats:
     decision_target: list = field(default_factory=list)
     admission_waits: int = 0
     max_queue: int = 0
+    timeouts: int = 0                  # reads given up after a chunk timeout
+    ended: int = 0                     # reads that ended before a decision (end_read)
+    restarts: int = 0                  # reads restarted on a new row after theirs was lost
 
 
 def _median(x):
@@ -192,13 +217,30 @@ def mapq(best, second):
     return np.where(none, MAPQ_MAX, q).astype(np.int64)
 
 
+@dataclass
+class _Loop:
+    """State of one run(): what every channel is doing."""
+    chan_read: list                    # the read each channel is sequencing
+    arrivals: list                     # heap of (arrival of a channel's next chunk, channel)
+    waiting: list                      # (arrival, channel): chunks arrived, not submitted yet
+    inflight: list                     # _Tick
+    stats: ServerStats
+    t0: float
+    t_meas: float
+    t_end: float
+    host: dict = field(default_factory=dict)  # host time per loop phase: [total s, max s, calls]
+
+    def in_window(self, now: float) -> bool:
+        return self.t_meas <= now <= self.t_end
+
+
 class ReadUntilServer:
     def __init__(self, targets: list[Target], cfg: ServerConfig | None = None,
-                 mode: str = "extend", record: list | None = None):
-        """record: optional list receiving (target, pool read, rows, cost, end)
-        for every served chunk."""
-        import torch
-        self.torch = torch
+                 mode: str = "extend", record: list | None = None, clock=None, sleep=None):
+        """record: optional list receiving (target, pool read, rows, cost, end,
+        second cost, second end) for every served chunk.  clock / sleep: the
+        serving loop's time source and wait (time.perf_counter and time.sleep
+        unless given; a host test passes a simulated clock)."""
         self.record = record
         self.targets = targets
         self.cfg = cfg or ServerConfig()
@@ -210,6 +252,17 @@ class ReadUntilServer:
             raise ValueError("raw mode extends resident rows of targets from make_raw_targets")
         self.mode = mode
         self.rng = np.random.default_rng(self.cfg.seed)
+        self.clock = clock or time.perf_counter
+        self.sleep = sleep or time.sleep
+        self._loop: _Loop | None = None
+        self._setup_device()
+
+    # ------------------------------------------------------------------
+    # device side (the C ABI through the binding)
+    def _setup_device(self):
+        """HIP streams per target, the row budget, raw mode's detector states."""
+        import torch
+        self.torch = torch
         k = max(1, self.cfg.streams_per_target)
         for i, t in enumerate(self.targets):
             t.streams = _server_streams(torch, i * k, k)
@@ -220,6 +273,28 @@ class ReadUntilServer:
                 t.ev_states = sd.EventStates(self.cfg.channels)
                 t.ev_buf = torch.zeros((self.cfg.channels, self.cfg.max_events),
                                        dtype=torch.float32, device=torch.device("cuda"))
+
+    def _prepare_run(self):
+        for t in self.targets:
+            sd.set_stream_config(self.cfg.stream_strip, 0, ref=t.ref)
+        if self.cfg.prewarm_rows and self.mode == "extend":
+            self.prewarm()
+
+    def _open_stream(self, ti: int):
+        """A resident row on target ti's reference (raises sd.SdtwError
+        EBUDGET when the row budget is exhausted)."""
+        return sd.Stream(self.targets[ti].ref)
+
+    def _tick_ready(self, tk: _Tick) -> bool:
+        return tk.event.query()
+
+    def _tick_results(self, tk: _Tick):
+        """(costs, ends, runner-up costs or None, runner-up ends or None)."""
+        tk.event.synchronize()
+        # pinned host copies, complete with the event
+        return (tk.cost.numpy(), tk.end.numpy(),
+                None if tk.second is None else tk.second.numpy(),
+                None if tk.second_end is None else tk.second_end.numpy())
 
     # ------------------------------------------------------------------
     def calibrate(self, n_each: int = 128, seed: int = 77, group: int = 32):
@@ -296,155 +371,231 @@ class ReadUntilServer:
         """Fill the library's row pool: open as many rows per target as there
         are channels (or as the budget allows) and close them again, so that
         admissions while serving reuse cached rows instead of allocating."""
-        for t in self.targets:
+        for ti in range(len(self.targets)):
             rows = []
             try:
                 for _ in range(self.cfg.channels):
-                    rows.append(sd.Stream(t.ref))
+                    rows.append(self._open_stream(ti))
             except sd.SdtwError as e:
                 if e.code != "EBUDGET":
                     raise
             for r in rows:
                 r.close()
 
-    def run(self, duration_s: float, warmup_s: float = 0.0) -> dict:
-        """Serve for warmup_s + duration_s seconds of wall-clock time; report
-        what was decided and measured during the last duration_s seconds."""
-        torch = self.torch
+    # ------------------------------------------------------------------
+    # faults and their handling
+    def end_read(self, channel: int):
+        """The sequencer reports that the read on ``channel`` ended before a
+        decision (its molecule left the pore).  Its chunk still queued is
+        dropped; a chunk in flight is left to finish and its result ignored;
+        its row is released once no work that uses it is in flight (closing
+        a row waits for such work, which would stall the serving loop); the
+        channel starts its next read.  Only valid while run() serves (from
+        one of its scheduled events)."""
+        if self._loop is None:
+            raise RuntimeError("end_read: the server is not serving")
+        self._abandon(self._loop, channel, "ended", self.clock())
+
+    def _in_flight(self, lp: _Loop, rd: _Read) -> bool:
+        return any(e[1] is rd for tk in lp.inflight for e in tk.entries)
+
+    def _release(self, rd: _Read):
+        if rd.handle is not None:
+            th = time.perf_counter()
+            rd.handle.close()
+            self._timed(self._loop, "stream_close", th)
+            rd.handle = None
+
+    def _abandon(self, lp: _Loop, c: int, why: str, now: float):
+        """Give up the read on channel c (``why``: "ended" or "timeout")."""
+        rd = lp.chan_read[c]
+        rd.abandoned = why
+        lp.waiting = [(a, ch) for a, ch in lp.waiting if ch != c]
+        if any(ch == c for _, ch in lp.arrivals):
+            lp.arrivals = [(a, ch) for a, ch in lp.arrivals if ch != c]
+            heapq.heapify(lp.arrivals)
+        if not self._in_flight(lp, rd):
+            self._release(rd)
+        if lp.in_window(now):
+            if why == "timeout":
+                lp.stats.timeouts += 1
+            else:
+                lp.stats.ended += 1
+        lp.chan_read[c] = self._new_read(now)
+        heapq.heappush(lp.arrivals, (now + self.cfg.chunk_period_s, c))
+
+    def _expire(self, lp: _Loop, now: float):
+        """Chunk timeout: a read whose chunk has waited (queued or in flight)
+        longer than chunk_timeout_s since it arrived is given up undecided:
+        a decision that late no longer saves sequencing time."""
+        lim = self.cfg.chunk_timeout_s
+        if lim is None:
+            return
+        late = [c for arr, c in lp.waiting if now - arr > lim]
+        late += [c for tk in lp.inflight for c, rd, arr, _ in tk.entries
+                 if not rd.abandoned and now - arr > lim]
+        for c in late:
+            self._abandon(lp, c, "timeout", now)
+
+    @staticmethod
+    def _timed(lp, key, t_start):
+        if lp is None:
+            return
+        d = time.perf_counter() - t_start
+        v = lp.host.setdefault(key, [0.0, 0.0, 0])
+        v[0] += d
+        v[1] = max(v[1], d)
+        v[2] += 1
+
+    # ------------------------------------------------------------------
+    def run(self, duration_s: float, warmup_s: float = 0.0, events=None) -> dict:
+        """Serve for warmup_s + duration_s seconds of the server's clock;
+        report what was decided and measured during the last duration_s
+        seconds.  events: optional (seconds after the start, callable taking
+        the server) pairs, each called once when the clock passes its time
+        (host-side fault injection: end_read, closing a row, the budget)."""
         cfg = self.cfg
-        dev = torch.device("cuda")
-        for t in self.targets:
-            sd.set_stream_config(cfg.stream_strip, 0, ref=t.ref)
-        if cfg.prewarm_rows and self.mode == "extend":
-            self.prewarm()
+        self._prepare_run()
         P = cfg.chunk_period_s
-        t0 = time.perf_counter()
-        t_meas = t0 + warmup_s
-        t_end = t_meas + duration_s
-        stats = ServerStats()
-        chan_read: list[_Read] = []
-        arrivals = []  # heap of (arrival time of the channel's next chunk, channel)
+        t0 = self.clock()
+        lp = _Loop([], [], [], [], ServerStats(), t0, t0 + warmup_s, t0 + warmup_s + duration_s)
+        self._loop = lp
+        pending = sorted(events or [], key=lambda e: e[0])
         for c in range(cfg.channels):
             start = t0 + float(self.rng.random()) * P
-            chan_read.append(self._new_read(start))
-            heapq.heappush(arrivals, (start + P, c))
-        inflight: list[_Tick] = []
-        waiting = []  # chunks that have arrived but are not submitted yet
-        host = {}  # host time per loop phase: key -> [total s, max s, calls]
+            lp.chan_read.append(self._new_read(start))
+            heapq.heappush(lp.arrivals, (start + P, c))
+        try:
+            while True:
+                now = self.clock()
+                if now > lp.t_end:
+                    break
+                while pending and t0 + pending[0][0] <= now:
+                    pending.pop(0)[1](self)
+                self._harvest(lp)
+                self._expire(lp, now)
+                while lp.arrivals and lp.arrivals[0][0] <= now:
+                    lp.waiting.append(heapq.heappop(lp.arrivals))
+                lp.stats.max_queue = max(lp.stats.max_queue, len(lp.waiting))
+                submitted = self._dispatch(lp)
+                if not submitted:
+                    nxt = lp.arrivals[0][0] if lp.arrivals else now + 0.002
+                    self.sleep(max(0.0, min(nxt - self.clock(),
+                                            0.0005 if lp.inflight else 0.002)))
+            self._harvest(lp, block=True)
+        finally:
+            for tk in lp.inflight:  # only after an exception: wait before closing rows
+                self._tick_results(tk)
+            lp.inflight.clear()
+            for rd in lp.chan_read:
+                self._release(rd)
+            self._loop = None
+        return self._report(lp, duration_s)
 
-        def timed(key, t_start):
-            d = time.perf_counter() - t_start
-            v = host.setdefault(key, [0.0, 0.0, 0])
-            v[0] += d
-            v[1] = max(v[1], d)
-            v[2] += 1
-
-        def harvest(block=False):
-            done = [tk for tk in inflight if block or tk.event.query()]
-            for tk in done:
-                inflight.remove(tk)
-                th = time.perf_counter()
-                tk.event.synchronize()
-                costs = tk.cost.numpy()  # pinned host copies, complete with the event
-                ends = tk.end.numpy()
-                seconds = None if tk.second is None else tk.second.numpy()
-                second_ends = None if tk.second_end is None else tk.second_end.numpy()
-                timed("results", th)
-                th = time.perf_counter()
-                for s in tk.scratch:
-                    s.close()
-                timed("close_scratch", th)
-                now = time.perf_counter()
-                in_window = t_meas <= now <= t_end
-                if in_window:
-                    stats.cells += tk.cells
-                for k, (c, rd, arr, rows) in enumerate(tk.entries):
-                    if in_window:
-                        stats.chunks += 1
-                        stats.chunk_latency.append(now - arr)
-                    c2 = None if seconds is None else float(seconds[k])
-                    if self.record is not None:
-                        self.record.append((rd.target, rd.pool_idx, rows, int(costs[k]),
-                                            int(ends[k]), None if c2 is None else int(c2),
-                                            None if second_ends is None else int(second_ends[k])))
-                    verdict = self._decide(rd, float(costs[k]), c2)
-                    if verdict is None:  # the read's next chunk
-                        heapq.heappush(arrivals, (rd.start + (rd.chunks_done + 1) * P, c))
-                        continue
-                    if in_window:
-                        stats.decisions += 1
-                        stats.decision_latency.append(now - arr)
-                        stats.decision_target.append(rd.target)
-                        stats.kept += verdict == "keep"
-                        stats.rejected += verdict == "reject"
-                        stats.decided_on_target += rd.on
-                        stats.kept_on_target += rd.on and verdict == "keep"
-                        stats.decision_events.append(rd.rows)
-                        stats.correct += (verdict == "keep") == rd.on
-                    if rd.handle is not None:
-                        th = time.perf_counter()
-                        rd.handle.close()
-                        timed("stream_close", th)
-                        rd.handle = None
-                    chan_read[c] = self._new_read(now)
-                    heapq.heappush(arrivals, (now + P, c))
-
-        while True:
-            now = time.perf_counter()
-            if now > t_end:
-                break
-            harvest()
-            while arrivals and arrivals[0][0] <= now:
-                waiting.append(heapq.heappop(arrivals))
-            stats.max_queue = max(stats.max_queue, len(waiting))
-            groups: dict[int, list] = {}
-            keep_waiting = []
-            for arr, c in waiting:
-                rd = chan_read[c]
-                if self.mode == "extend" and rd.handle is None:
-                    try:
-                        th = time.perf_counter()
-                        rd.handle = sd.Stream(self.targets[rd.target].ref)
-                        timed("stream_open", th)
-                    except sd.SdtwError as e:
-                        if e.code != "EBUDGET":
-                            raise
-                        stats.admission_waits += 1
-                        keep_waiting.append((arr, c))
-                        continue
-                groups.setdefault(rd.target, []).append((arr, c))
-            # continuous batching: a target's ready chunks go out together on
-            # one of its HIP streams that has no batch in flight; while all
-            # are busy they wait and join the next batch
-            submitted = False
-            for ti, items in groups.items():
-                if self._free_slot(ti, inflight) is None:
-                    keep_waiting.extend(items)
-                else:
-                    th = time.perf_counter()
-                    not_ready = self._submit(ti, items, chan_read, inflight, dev)
-                    timed("submit " + self.targets[ti].name, th)
-                    submitted = True
-                    for _, c in not_ready:  # raw mode: no new final events yet
-                        rd = chan_read[c]
-                        if rd.chunks_done * cfg.chunk_samples >= rd.raw.size + cfg.chunk_samples:
-                            # the read is over without enough events: rejected
-                            if rd.handle is not None:
-                                rd.handle.close()
-                                rd.handle = None
-                            chan_read[c] = self._new_read(time.perf_counter())
-                            heapq.heappush(arrivals, (time.perf_counter() + P, c))
-                        else:
-                            heapq.heappush(arrivals, (rd.start + (rd.chunks_done + 1) * P, c))
-            waiting = keep_waiting
-            if not submitted:
-                nxt = arrivals[0][0] if arrivals else now + 0.002
-                time.sleep(max(0.0, min(nxt - time.perf_counter(), 0.0005 if inflight else 0.002)))
-        harvest(block=True)
-        for rd in chan_read:
-            if rd.handle is not None:
-                rd.handle.close()
+    def _dispatch(self, lp: _Loop) -> bool:
+        """Admit the waiting chunks' reads (a row each) and submit one batch
+        per target that has a free HIP stream.  Returns whether anything was
+        submitted."""
+        cfg = self.cfg
+        P = cfg.chunk_period_s
+        groups: dict[int, list] = {}
+        keep_waiting = []
+        for arr, c in lp.waiting:
+            rd = lp.chan_read[c]
+            if rd.handle is not None and rd.handle.closed:
+                # its row was closed elsewhere: the read restarts on a new row
+                # from its first event (equal to extending it chunk by chunk)
                 rd.handle = None
+                rd.restart = rd.rows > 0
+                lp.stats.restarts += 1
+            if rd.handle is None:
+                try:
+                    th = time.perf_counter()
+                    rd.handle = self._open_stream(rd.target)
+                    self._timed(lp, "stream_open", th)
+                except sd.SdtwError as e:
+                    if e.code != "EBUDGET":
+                        raise
+                    lp.stats.admission_waits += 1
+                    keep_waiting.append((arr, c))
+                    continue
+            groups.setdefault(rd.target, []).append((arr, c))
+        # continuous batching: a target's ready chunks go out together on one
+        # of its HIP streams that has no batch in flight; while all are busy
+        # they wait and join the next batch
+        submitted = False
+        for ti, items in groups.items():
+            if self._free_slot(ti, lp.inflight) is None:
+                keep_waiting.extend(items)
+                continue
+            th = time.perf_counter()
+            not_ready = self._submit(ti, items, lp.chan_read, lp.inflight)
+            self._timed(lp, "submit " + self.targets[ti].name, th)
+            submitted = True
+            for _, c in not_ready:  # raw mode: no new final events yet
+                rd = lp.chan_read[c]
+                if rd.chunks_done * cfg.chunk_samples >= rd.raw.size + cfg.chunk_samples:
+                    # the read is over without enough events: rejected
+                    self._release(rd)
+                    now = self.clock()
+                    lp.chan_read[c] = self._new_read(now)
+                    heapq.heappush(lp.arrivals, (now + P, c))
+                else:
+                    heapq.heappush(lp.arrivals, (rd.start + (rd.chunks_done + 1) * P, c))
+        lp.waiting = keep_waiting
+        return submitted
+
+    def _harvest(self, lp: _Loop, block: bool = False):
+        """Decide on the results of the batches that have completed."""
+        P = self.cfg.chunk_period_s
+        stats = lp.stats
+        done = [tk for tk in lp.inflight if block or self._tick_ready(tk)]
+        for tk in done:
+            lp.inflight.remove(tk)
+            th = time.perf_counter()
+            costs, ends, seconds, second_ends = self._tick_results(tk)
+            self._timed(lp, "results", th)
+            now = self.clock()
+            in_window = lp.in_window(now)
+            if in_window:
+                stats.cells += tk.cells
+            for k, (c, rd, arr, rows) in enumerate(tk.entries):
+                if self.mode == "recompute":
+                    self._release(rd)  # a fresh row per chunk
+                if rd.abandoned:
+                    # ended or timed out while in flight: the result is not
+                    # used and the row can be released now
+                    self._release(rd)
+                    continue
+                if in_window:
+                    stats.chunks += 1
+                    stats.chunk_latency.append(now - arr)
+                c2 = None if seconds is None else float(seconds[k])
+                if self.record is not None:
+                    self.record.append((rd.target, rd.pool_idx, rows, int(costs[k]),
+                                        int(ends[k]), None if c2 is None else int(c2),
+                                        None if second_ends is None else int(second_ends[k])))
+                verdict = self._decide(rd, float(costs[k]), c2)
+                if verdict is None:  # the read's next chunk
+                    heapq.heappush(lp.arrivals, (rd.start + (rd.chunks_done + 1) * P, c))
+                    continue
+                if in_window:
+                    stats.decisions += 1
+                    stats.decision_latency.append(now - arr)
+                    stats.decision_target.append(rd.target)
+                    stats.kept += verdict == "keep"
+                    stats.rejected += verdict == "reject"
+                    stats.decided_on_target += rd.on
+                    stats.kept_on_target += rd.on and verdict == "keep"
+                    stats.decision_events.append(rd.rows)
+                    stats.correct += (verdict == "keep") == rd.on
+                self._release(rd)
+                lp.chan_read[c] = self._new_read(now)
+                heapq.heappush(lp.arrivals, (now + P, c))
+
+    def _report(self, lp: _Loop, duration_s: float) -> dict:
+        cfg = self.cfg
+        stats = lp.stats
         lat = np.asarray(stats.decision_latency)
         clat = np.asarray(stats.chunk_latency)
 
@@ -474,10 +625,13 @@ class ReadUntilServer:
             "chunk_latency_p99_ms": pct(clat, 99),
             "admission_waits": stats.admission_waits,
             "max_waiting_chunks": stats.max_queue,
+            "timeouts": stats.timeouts,
+            "ended": stats.ended,
+            "restarts": stats.restarts,
             "tau": {t.name: round(t.tau, 4) for t in self.targets},
             "q_min": {t.name: round(t.q_min, 2) for t in self.targets},
             "host_loop_ms": {k: {"total": round(v[0] * 1e3, 1), "max": round(v[1] * 1e3, 2),
-                                 "calls": v[2]} for k, v in host.items()},
+                                 "calls": v[2]} for k, v in lp.host.items()},
             "per_target": {
                 t.name: {"decisions": int((np.asarray(stats.decision_target) == ti).sum()),
                          "decision_latency_p50_ms": pct(lat[np.asarray(stats.decision_target)
@@ -495,30 +649,48 @@ class ReadUntilServer:
                 return k
         return None
 
-    def _submit(self, ti, items, chan_read, inflight, dev):
+    def _submit(self, ti, items, chan_read, inflight):
         """Normalise and extend the ready chunks of one target in one launch.
         Returns the reads that could not be extended yet (raw mode)."""
         if self.cfg.raw:
-            return self._submit_raw(ti, items, chan_read, inflight, dev)
+            return self._submit_raw(ti, items, chan_read, inflight)
+        E = self.cfg.chunk_events
+        # per chunk: (channel, read, arrival, first event, end event); the
+        # read's whole prefix from scratch in recompute mode and after a
+        # restart, else the new chunk alone
+        batch = []
+        for arr, c in items:
+            rd = chan_read[c]
+            lo = 0 if (self.mode == "recompute" or rd.restart) else rd.chunks_done * E
+            batch.append((c, rd, arr, lo, (rd.chunks_done + 1) * E))
+        slot = self._free_slot(ti, inflight)
+        tk = self._launch(ti, slot, batch)
+        for c, rd, arr, _, _ in batch:
+            rd.chunks_done += 1
+            rd.rows = rd.chunks_done * E
+            rd.restart = False
+            tk.entries.append((c, rd, arr, rd.rows))
+        inflight.append(tk)
+        return []
+
+    def _launch(self, ti, slot, batch) -> _Tick:
+        """Device work of one batch on target ti's HIP stream ``slot``: the
+        raw events [lo, hi) of every read normalised (with its first chunk's
+        statistics, computed here for a read's first chunk) and its row
+        extended; results copied to pinned host memory behind an event."""
         torch = self.torch
         cfg = self.cfg
         t = self.targets[ti]
-        E = cfg.chunk_events
-        first = [(a, c) for a, c in items if chan_read[c].chunks_done == 0]
-        cont = [(a, c) for a, c in items if chan_read[c].chunks_done > 0]
-        entries, code_parts, lens, scratch = [], [], [], []
-        slot = self._free_slot(ti, inflight)
+        dev = torch.device("cuda")
         hs = t.streams[slot]
+        first = [b for b in batch if b[1].chunks_done == 0]
+        cont = [b for b in batch if b[1].chunks_done > 0]
+        code_parts, lens, order = [], [], []
         with torch.cuda.stream(hs):
             for group, fresh in ((first, True), (cont, False)):
                 if not group:
                     continue
-                lo = 0 if self.mode == "recompute" else None
-                segs = []
-                for _, c in group:
-                    rd = chan_read[c]
-                    a = 0 if lo == 0 else rd.chunks_done * E
-                    segs.append(rd.raw[a:(rd.chunks_done + 1) * E])
+                segs = [rd.raw[lo:hi] for _, rd, _, lo, hi in group]
                 # pinned staging and asynchronous copies: the host loop never
                 # waits for earlier work queued on the stream
                 offs_np = np.zeros(len(segs) + 1, np.int64)
@@ -530,31 +702,19 @@ class ReadUntilServer:
                 if fresh:
                     # the read's statistics are those of its first chunk
                     _, codes, _, st = sd.prepare_queries_ex(raw, offs, cfg.scale, stream=hs)
-                    for k, (_, c) in enumerate(group):
-                        chan_read[c].stats = st[k:k + 1]
+                    for k, (_, rd, _, _, _) in enumerate(group):
+                        rd.stats = st[k:k + 1]
                 else:
-                    st_in = torch.cat([chan_read[c].stats for _, c in group])
+                    st_in = torch.cat([rd.stats for _, rd, _, _, _ in group])
                     _, codes, _, _ = sd.prepare_queries_ex(raw, offs, cfg.scale, st_in,
                                                            stream=hs)
                 code_parts.append(codes)
                 lens += [x.size for x in segs]
-                entries += [(c, chan_read[c], arr) for arr, c in group]
+                order += group
             codes = torch.cat(code_parts) if len(code_parts) > 1 else code_parts[0]
             offs_np = np.zeros(len(lens) + 1, np.int64)
             np.cumsum(lens, out=offs_np[1:])
-            if self.mode == "extend":
-                handles = [rd.handle for _, rd, _ in entries]
-            else:  # from scratch: a fresh stream extended by the whole prefix
-                for _ in entries:
-                    while True:
-                        try:
-                            scratch.append(sd.Stream(t.ref))
-                            break
-                        except sd.SdtwError as e:
-                            if e.code != "EBUDGET":
-                                raise
-                            time.sleep(0.001)
-                handles = scratch
+            handles = [rd.handle for _, rd, _, _, _ in order]
             cost, end = sd.stream_extend(handles, codes, offs_np, stream=hs)
             pinned = [cost, end]
             if cfg.decision == "mapq":
@@ -571,22 +731,19 @@ class ReadUntilServer:
             host += [None] * (4 - len(host))
             ev = torch.cuda.Event()
             ev.record(hs)
-        out = []
-        for c, rd, arr in entries:
-            rd.chunks_done += 1
-            rd.rows = rd.chunks_done * E
-            out.append((c, rd, arr, rd.rows))
-        inflight.append(_Tick(ev, ti, slot, out, host[0], host[1], host[2], host[3],
-                              time.perf_counter(),
-                              float(sum(lens)) * t.ref.n, scratch))
-        return []
+        # results follow `order` (first chunks, then continuing reads): put
+        # the batch in that order so entries and results line up
+        batch[:] = order
+        return _Tick(ev, ti, slot, [], host[0], host[1], host[2], host[3], self.clock(),
+                     float(sum(lens)) * t.ref.n)
 
-    def _submit_raw(self, ti, items, chan_read, inflight, dev):
+    def _submit_raw(self, ti, items, chan_read, inflight):
         """Raw mode: events of each read's new samples (the detectors
         continue from their state), buffered per channel, then the same
         normalisation and extension as for event chunks."""
         torch = self.torch
         cfg = self.cfg
+        dev = torch.device("cuda")
         t = self.targets[ti]
         E = cfg.chunk_events
         keep = 2 * E
@@ -626,11 +783,15 @@ class ReadUntilServer:
                 rows_i = ch_d.long()[:, None].expand(n, keep)[mask]
                 cols_i = (torch.from_numpy(have).to(dev)[:, None] + j)[mask]
                 t.ev_buf[rows_i, cols_i] = ev[mask]
+            # a read's events not aligned yet start at `base` (0 after a
+            # restart: the whole buffered prefix again, on a new row)
+            base = np.array([0 if chan_read[c].restart else chan_read[c].rows for _, c in items],
+                            np.int64)
             take = np.zeros(n, np.int64)
             for k, (_, c) in enumerate(items):
                 rd = chan_read[c]
                 rd.have += int(add[k])
-                avail = rd.have - rd.rows
+                avail = rd.have - base[k]
                 if rd.rows == 0:
                     take[k] = E if avail >= E else 0  # the first chunk fixes the statistics
                 else:
@@ -643,7 +804,7 @@ class ReadUntilServer:
                     continue
                 group = [items[k] for k in sel]
                 tk = np.array([take[k] for k in sel], np.int64)
-                start = np.array([chan_read[c].rows for _, c in group], np.int64)
+                start = base[sel]
                 width = int(tk.max())
                 j = torch.arange(width, device=dev)[None, :]
                 mask = j < torch.from_numpy(tk).to(dev)[:, None]
@@ -693,12 +854,13 @@ class ReadUntilServer:
         out = []
         for c, rd, arr, tk in entries:
             rd.chunks_done += 1
-            rd.rows += tk
+            rd.rows = (0 if rd.restart else rd.rows) + tk
+            rd.restart = False
             out.append((c, rd, arr, rd.rows))
         for _, c in waiting:
             chan_read[c].chunks_done += 1
         inflight.append(_Tick(evt, ti, slot, out, host[0], host[1], host[2], host[3],
-                              time.perf_counter(), float(sum(lens)) * t.ref.n, []))
+                              self.clock(), float(sum(lens)) * t.ref.n))
         return waiting
 
 
