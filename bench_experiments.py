@@ -41,12 +41,20 @@ wide     The whole-device single-query scan alone (sdtw_align_one_wide) on
          one genome length (--genome, default 5,000,000 bases) at one width
          (--cols, default automatic): device time per call, median of
          --reps calls (HIP events), for a kernel trace of exactly that case.
+issue    VALU issue rates on gfx950 (libsdtw_probe.so): cycles per 64-lane
+         wave instruction per SIMD for v_min3_u32, v_sad_u32, v_sub_f32,
+         v_add_f32 |a| and v_add_u32, by independent chains per wave (1, 2,
+         4) and waves per SIMD (1-8), at the nominal 2.4 GHz clock: the basis
+         of the cycles per cell of the roof in bench.py.
+lds      LDS cost of the tile switch's operations (libsdtw_probe.so): blocks
+         of 8 ds_read_b128 + 8 ds_write_b128 per wave with 1, 16 or 64 lanes
+         active, cycles per LDS instruction per CU by waves per SIMD.
 best_two The runner-up search alone (sdtw_stream_best_two) over 1 to 256
          resident rows of the 5,000,000-base target (9,999,990 columns):
          device time and the rate at which it reads the rows (4 bytes per
          column per row, the bound being HBM at 8 TB/s).
 
-Usage: python bench_experiments.py latency|scale|serving|serving_raw|decision|best_two|wide|events
+Usage: python bench_experiments.py latency|scale|serving|serving_raw|decision|best_two|wide|events|issue|lds
                                    [--max-genome BASES] [--genome BASES] [--cols C]
                                    [--reps R]
 """
@@ -372,11 +380,83 @@ def best_two(args):
     ref.close()
 
 
+def issue(args):
+    """VALU issue rates (libsdtw_probe.so): cycles per 64-lane wave instruction
+    per SIMD for the instruction kinds of the cell update, by independent
+    chains per wave and waves per SIMD; the basis of the roof in bench.py."""
+    import ctypes as C
+
+    import torch
+    from paper_2211_07340_amd import build as hipbuild
+    lib = C.CDLL(hipbuild.PROBE_LIB)
+    lib.sdtw_probe_issue.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p,
+                                     C.c_void_p]
+    lib.sdtw_probe_issue.restype = C.c_int
+    props = torch.cuda.get_device_properties(0)
+    cus = props.multi_processor_count
+    clock_ghz = 2.4  # nominal engine clock of the MI355X
+    out = torch.empty(4 * cus * 8 * 64, dtype=torch.int32, device="cuda")
+    kinds = ["v_min3_u32", "v_sad_u32", "v_sub_f32", "v_add_f32 |a|", "v_add_u32"]
+    st = torch.cuda.current_stream()
+    for k, name in enumerate(kinds):
+        for chains in (1, 2, 4):
+            for waves in (1, 2, 3, 4, 8):
+                # 640,000 instructions per SIMD (about a millisecond): the
+                # launch itself is noise
+                iters = 40000 // (waves * chains)
+
+                def run():
+                    rc = lib.sdtw_probe_issue(k, chains, waves, iters, C.c_void_p(out.data_ptr()),
+                                              C.c_void_p(st.cuda_stream))
+                    assert rc == 0, rc
+                ms = _time_ms(torch, run, 3)
+                instr_per_simd = waves * iters * 16 * chains
+                cyc = ms * 1e-3 * clock_ghz * 1e9 / instr_per_simd
+                print(json.dumps({"experiment": "issue", "instruction": name, "chains": chains,
+                                  "waves_per_simd": waves, "ms": round(ms, 3),
+                                  "cycles_per_wave_instr_per_simd": round(cyc, 2),
+                                  "cycles_per_wave_instr_per_wave": round(cyc * waves, 2)}),
+                      flush=True)
+
+
+def lds(args):
+    """LDS cost of the tile switch's operations (libsdtw_probe.so): blocks of
+    8 ds_read_b128 + 8 ds_write_b128 per wave with 1 or 64 lanes active;
+    cycles per LDS instruction per CU by waves per SIMD."""
+    import ctypes as C
+
+    import torch
+    from paper_2211_07340_amd import build as hipbuild
+    lib = C.CDLL(hipbuild.PROBE_LIB)
+    lib.sdtw_probe_lds.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]
+    lib.sdtw_probe_lds.restype = C.c_int
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    clock_ghz = 2.4
+    out = torch.empty(4 * cus * 8 * 64, dtype=torch.int32, device="cuda")
+    st = torch.cuda.current_stream()
+    for lanes in (1, 16, 64):
+        for waves in (1, 2, 4, 8):
+            iters = 8000 // waves
+
+            def run():
+                rc = lib.sdtw_probe_lds(lanes, waves, iters, C.c_void_p(out.data_ptr()),
+                                        C.c_void_p(st.cuda_stream))
+                assert rc == 0, rc
+            ms = _time_ms(torch, run, 3)
+            per_cu = 4 * waves * iters * 16
+            print(json.dumps({"experiment": "lds", "lanes": lanes, "waves_per_simd": waves,
+                              "ms": round(ms, 3),
+                              "cycles_per_lds_instr_per_cu": round(
+                                  ms * 1e-3 * clock_ghz * 1e9 / per_cu, 2),
+                              "cycles_per_block_per_wave": round(
+                                  ms * 1e-3 * clock_ghz * 1e9 / iters, 1)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("experiment",
                     choices=["latency", "scale", "serving", "serving_raw", "decision",
-                             "best_two", "wide", "events"])
+                             "best_two", "wide", "events", "issue", "lds"])
     ap.add_argument("--max-genome", type=int, default=10_000_000)
     ap.add_argument("--genome", type=int, default=5_000_000, help="wide: genome bases")
     ap.add_argument("--cols", type=int, default=0, help="wide: columns per thread (0: auto)")
@@ -387,7 +467,8 @@ def main():
     t0 = time.perf_counter()
     {"latency": latency, "scale": scale, "serving": serving,
      "decision": decision, "best_two": best_two, "wide": wide,
-     "events": events, "serving_raw": serving_raw}[args.experiment](args)
+     "events": events, "serving_raw": serving_raw, "issue": issue,
+     "lds": lds}[args.experiment](args)
     print(json.dumps({"done": args.experiment, "seconds": round(time.perf_counter() - t0, 1)}),
           flush=True)
 

@@ -278,8 +278,9 @@ int sdtw_plan_info(sdtw_plan plan, int32_t* nq, int* dtype, int32_t* max_m);
  *           to fewer chains, and reads with M <= 64 to the one-wave kernel.
  *   bands   waves per read: 1 to 4 (0 = keep the plan's where they fit the
  *           other settings, else 1); 2 or 4 need strip 16 with at most 2
- *           chains or strip 32 with 1 chain, 3 needs strip 16 or 32 with 1
- *           chain.  A read's rows are cut into
+ *           chains or strip 32 with 1 chain (2 also strip 32 with 2
+ *           chains), 3 needs strip 16 or 32 with 1 chain.  A read's rows are
+ *           cut into
  *           up to `bands` row bands of at least 64 * chains + 1 rows each
  *           (Eq. 1: a row depends on the rows above only through the
  *           previous row), one wave per band, pipelined over the
@@ -306,8 +307,13 @@ int sdtw_plan_get_config(sdtw_plan plan, int* strip, int* chains, int* bands,
  * in two passes (the second in reverse order), each a warm-up launch and one
  * timed with HIP events on `stream`; keep the candidate with the fastest of
  * its two times on the plan
- * and remember it for sdtw_plan_use_tuned (keyed by device, dtype, reference
- * length, number of reads, longest read and total rows).
+ * and remember it for sdtw_plan_use_tuned, keyed by the device's
+ * architecture and compute units, the dtype, the reference length and the
+ * batch's shape class (number of reads, median and longest read length,
+ * each in quarter-octave buckets: round(4 log2 v)).  If the environment
+ * variable SDTW_TUNE_CACHE names a file, tuned shapes are also written there
+ * (one per line, the file rewritten after every autotune) and read back by
+ * the first sdtw_plan_autotune or sdtw_plan_use_tuned of a process.
  *   max_columns  time the candidates on the first min(n, max_columns)
  *                reference columns (0 = all); the ranking does not depend on
  *                the reference length beyond the first few tiles.
@@ -319,8 +325,9 @@ int sdtw_plan_autotune(sdtw_ref ref, sdtw_plan plan, const void* q_dev, void* co
                        int32_t* end_dev, int64_t max_columns, void* stream);
 
 /*
- * Apply a configuration sdtw_plan_autotune found earlier in this process for
- * a batch of the same shape against a reference of the same length; *found
+ * Apply a configuration sdtw_plan_autotune found earlier (in this process,
+ * or in the SDTW_TUNE_CACHE file) for a batch of the same shape class against
+ * a reference of the same length on the same kind of device; *found
  * (optional) is set to 1 if there was one, else 0 and the plan is unchanged.
  */
 int sdtw_plan_use_tuned(sdtw_ref ref, sdtw_plan plan, int* found);

@@ -22,6 +22,26 @@ FLAGS = [
 ]
 
 
+PROBE_LIB = os.path.join(HERE, "libsdtw_probe.so")
+PROBE_SOURCES = ["probe_issue.hip"]
+
+
+def build_probe(verbose: bool = False) -> str:
+    """The VALU issue-rate probe (libsdtw_probe.so, measurement tooling)."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    cmd = [hipcc, *FLAGS, "-o", PROBE_LIB + ".tmp",
+           *[os.path.join(CSRC, s) for s in PROBE_SOURCES]]
+    proc = subprocess.run(cmd, capture_output=True, text=True, cwd=HERE)
+    out = "\n".join(l for l in (proc.stdout + proc.stderr).splitlines()
+                    if "packed-fp32-ops" not in l)
+    if proc.returncode != 0:
+        raise RuntimeError(f"hipcc failed ({proc.returncode}):\n{out}")
+    if verbose and out.strip():
+        print(out, file=sys.stderr)
+    os.replace(PROBE_LIB + ".tmp", PROBE_LIB)
+    return PROBE_LIB
+
+
 def build(verbose: bool = False, save_temps: str | None = None) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     cmd = [hipcc, *FLAGS, "-o", LIB + ".tmp", *[os.path.join(CSRC, s) for s in SOURCES]]
@@ -41,3 +61,4 @@ def build(verbose: bool = False, save_temps: str | None = None) -> str:
 
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_probe(verbose=True))

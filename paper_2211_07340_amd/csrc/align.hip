@@ -28,10 +28,12 @@
 // k_align_skew (M >= 65): continuous skew.  Lanes never wait for each other
 // at tile boundaries: lane l enters tile p at step p*M + l, so each period
 // of M steps starts with 64 "switch" steps in which exactly one lane swaps
-// its strip (masked LDS moves: new y from a staged copy of the tile, its
-// finished last row out, zeros in as gamma(0, .)).  The wave runs ntiles*M
-// + 64 steps for ntiles*T*M cells.  Reads are pulled longest-first from a
-// work list by a persistent grid.
+// its strip under a one-lane mask: new y from registers loaded one period
+// ahead, its finished last row out to LDS, gamma(0, .) = 0 in.  A one-lane
+// LDS instruction costs the CU about as much LDS time as any other, so the
+// switch keeps its LDS instructions few.  The wave runs ntiles*M + 64 steps
+// for ntiles*T*M cells.  Reads are pulled longest-first from a work list by
+// a persistent grid.
 //
 // k_align_plain (any M >= 1): synchronised tiles; every tile costs M + 63
 // steps with lanes idle during fill and drain.  Used for reads shorter than
@@ -74,6 +76,15 @@ struct FmtF32 {
     ((float*)cost)[r] = __uint_as_float(v);
   }
 };
+
+// f(integral_constant<int, I>) for I in [B, E), unrolled at compile time
+template <int B, int E, class Fn>
+__device__ __forceinline__ void static_for(Fn&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
 
 __device__ __forceinline__ uint32_t min3u(uint32_t a, uint32_t b, uint32_t c) {
   return min(min(a, b), c);
@@ -131,18 +142,86 @@ __device__ __forceinline__ uint32_t asm_from_left_lane(uint32_t v, uint32_t lane
   return r;
 }
 
+// Four consecutive columns of one chain in one asm statement:
+// n_c = |x - y_c| + min3(u_c, u_{c-1}, n_{c-1}) for c = 0..3, given the
+// diagonal um = u_{-1} and the left value l = n_{-1}.
+template <class F>
+__device__ __forceinline__ void cells4(uint32_t x, uint32_t y0, uint32_t y1, uint32_t y2,
+                                       uint32_t y3, uint32_t u0, uint32_t u1, uint32_t u2,
+                                       uint32_t u3, uint32_t um, uint32_t l, uint32_t& n0,
+                                       uint32_t& n1, uint32_t& n2, uint32_t& n3) {
+  uint32_t t;
+  if constexpr (std::is_same<F, FmtF32>::value) {
+    uint32_t d0, d1, d2, d3;
+    asm volatile(
+        "v_sub_f32 %[d0], %[x], %[y0]\n\t"
+        "v_min3_u32 %[t], %[u0], %[um], %[l]\n\t"
+        "v_sub_f32 %[d1], %[x], %[y1]\n\t"
+        "v_add_f32_e64 %[n0], |%[d0]|, %[t]\n\t"
+        "v_sub_f32 %[d2], %[x], %[y2]\n\t"
+        "v_min3_u32 %[t], %[u1], %[u0], %[n0]\n\t"
+        "v_sub_f32 %[d3], %[x], %[y3]\n\t"
+        "v_add_f32_e64 %[n1], |%[d1]|, %[t]\n\t"
+        "v_min3_u32 %[t], %[u2], %[u1], %[n1]\n\t"
+        "v_add_f32_e64 %[n2], |%[d2]|, %[t]\n\t"
+        "v_min3_u32 %[t], %[u3], %[u2], %[n2]\n\t"
+        "v_add_f32_e64 %[n3], |%[d3]|, %[t]"
+        : [n0] "=&v"(n0), [n1] "=&v"(n1), [n2] "=&v"(n2), [n3] "=&v"(n3), [t] "=&v"(t),
+          [d0] "=&v"(d0), [d1] "=&v"(d1), [d2] "=&v"(d2), [d3] "=&v"(d3)
+        : [x] "v"(x), [y0] "v"(y0), [y1] "v"(y1), [y2] "v"(y2), [y3] "v"(y3), [u0] "v"(u0),
+          [u1] "v"(u1), [u2] "v"(u2), [u3] "v"(u3), [um] "v"(um), [l] "v"(l));
+  } else {
+    asm volatile(
+        "v_min3_u32 %[t], %[u0], %[um], %[l]\n\t"
+        "v_sad_u32 %[n0], %[x], %[y0], %[t]\n\t"
+        "v_min3_u32 %[t], %[u1], %[u0], %[n0]\n\t"
+        "v_sad_u32 %[n1], %[x], %[y1], %[t]\n\t"
+        "v_min3_u32 %[t], %[u2], %[u1], %[n1]\n\t"
+        "v_sad_u32 %[n2], %[x], %[y2], %[t]\n\t"
+        "v_min3_u32 %[t], %[u3], %[u2], %[n2]\n\t"
+        "v_sad_u32 %[n3], %[x], %[y3], %[t]"
+        : [n0] "=&v"(n0), [n1] "=&v"(n1), [n2] "=&v"(n2), [n3] "=&v"(n3), [t] "=&v"(t)
+        : [x] "v"(x), [y0] "v"(y0), [y1] "v"(y1), [y2] "v"(y2), [y3] "v"(y3), [u0] "v"(u0),
+          [u1] "v"(u1), [u2] "v"(u2), [u3] "v"(u3), [um] "v"(um), [l] "v"(l));
+  }
+}
+
 // One row step of K interleaved chains over a lane's strip: chain h owns
 // columns [h*H, (h+1)*H).  nw[c] = gamma(i_h, c) from up[c] = gamma(i_h - 1, c),
 // the diagonal dprev[h] and left[h] = gamma(i_h, first column - 1), where
 // i_h is chain h's row.  Instructions are issued column by column across the
 // chains so that consecutive instructions of one chain are K apart.
-template <class F, int K, int H, int W>
+// after(integral_constant<int, w>) runs once the cells of column w of every
+// chain have been issued (the tile switch issues its LDS operations there).
+struct NoAfter {
+  template <class C>
+  __device__ __forceinline__ void operator()(C) const {}
+};
+template <class F, int K, int H, int W, class After = NoAfter>
 __device__ __forceinline__ void chains_row(const uint32_t (&x)[K], const uint32_t (&y)[W],
                                            const uint32_t (&up)[W], uint32_t (&nw)[W],
                                            const uint32_t (&dprev)[K],
-                                           const uint32_t (&left)[K]) {
-#pragma unroll
-  for (int w = 0; w < H; ++w) {
+                                           const uint32_t (&left)[K], After&& after = After{}) {
+#ifndef SDTW_K1_PLAIN
+#define SDTW_K1_PLAIN 1
+#endif
+  if constexpr (K == 1 && SDTW_K1_PLAIN) {
+    // one chain: four columns per asm statement (the compiler separates
+    // consecutive asm statements with a wait state)
+    static_for<0, H / 4>([&](auto bc) {
+      constexpr int c = 4 * decltype(bc)::value;
+      cells4<F>(x[0], y[c], y[c + 1], y[c + 2], y[c + 3], up[c], up[c + 1], up[c + 2],
+                up[c + 3], c ? up[c > 0 ? c - 1 : 0] : dprev[0],
+                c ? nw[c > 0 ? c - 1 : 0] : left[0], nw[c], nw[c + 1], nw[c + 2], nw[c + 3]);
+      after(std::integral_constant<int, c>{});
+      after(std::integral_constant<int, c + 1>{});
+      after(std::integral_constant<int, c + 2>{});
+      after(std::integral_constant<int, c + 3>{});
+    });
+    return;
+  }
+  static_for<0, H>([&](auto wc) {
+    constexpr int w = decltype(wc)::value;
     uint32_t m[K];
     if constexpr (std::is_same<F, FmtF32>::value) {
       uint32_t d[K];
@@ -164,7 +243,8 @@ __device__ __forceinline__ void chains_row(const uint32_t (&x)[K], const uint32_
 #pragma unroll
       for (int h = 0; h < K; ++h) nw[h * H + w] = asm_sad(x[h], y[h * H + w], m[h]);
     }
-  }
+    after(wc);
+  });
 }
 
 __device__ __forceinline__ void wave_argmin(uint32_t& best, int32_t& bestj) {
@@ -176,15 +256,6 @@ __device__ __forceinline__ void wave_argmin(uint32_t& best, int32_t& bestj) {
       best = ob;
       bestj = oj;
     }
-  }
-}
-
-// f(integral_constant<int, I>) for I in [B, E), unrolled at compile time
-template <int B, int E, class Fn>
-__device__ __forceinline__ void static_for(Fn&& f) {
-  if constexpr (B < E) {
-    f(std::integral_constant<int, B>{});
-    static_for<B + 1, E>(f);
   }
 }
 
@@ -242,21 +313,31 @@ __device__ __forceinline__ void load_strip(uint32_t (&dst)[W], const uint32_t* _
 // STREAM: each work item extends a resident row acc = gamma(m_old, .) by the
 // M rows of one chunk (rows m_old+1 .. m_old+M of the read): when a sub-lane
 // of band 0 enters a tile its previous row is acc's strip (instead of zeros)
-// and its diagonal is acc one column to the left (+inf left of column 0);
-// the last band writes the finished last row of every tile back to acc.  A
-// tile's acc is read at least one period before that tile's write-back, so
-// reads see the row as it was before this extension.
+// and its diagonal is acc one column to the left (+inf left of column 0),
+// both loaded into registers with the tile's reference values; the last band
+// writes the finished last row of every tile back to acc.  A tile's acc is
+// read at least one period before that tile's write-back, so reads see the
+// row as it was before this extension.
 //
 // LDS (uint32 words, every array on 16 bytes): zeros[W] and a +inf cell
-// (4 words); STREAM: acc strips [64W] and the value left of each [64];
-// ring[P-1][2][64W]; edge[P-1][4]; per band: stage[64W] (next tile's strips;
-// in the last band also the finished last rows) and bx.
+// (4 words); ring[P-1][2][64W]; edge[P-1][4]; per band: stage[64W] (in the
+// last band the finished last rows, folded once a period) and bx.
 template <class F, int W, int K, int P, bool STREAM>
 __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
   constexpr int T = 64 * W;
   constexpr int H = W / K;
   constexpr int S = 64 * K;                   // sub-lanes = switch steps per period
   constexpr int U = K > 2 ? K : 2;            // phase-A unroll: chain index compile-time
+  constexpr bool kZeroRow = P == 1 && !STREAM;
+  // Pipelined switches (issued between the previous step's cells) except
+  // with one band and no resident row, where a switch loads nothing from LDS.
+  constexpr bool kPipe = !kZeroRow;
+#ifndef SDTW_SW_GROUP
+#define SDTW_SW_GROUP 4
+#endif
+  // columns per group of a pipelined switch's LDS operations
+  constexpr int kGc = SDTW_SW_GROUP < H ? SDTW_SW_GROUP : H;
+  static_assert(H % kGc == 0 && kGc % 4 == 0, "switch groups are whole uint4 groups");
   static_assert(W % K == 0 && H % 4 == 0, "sub-strips are whole uint4 groups");
   extern __shared__ __align__(16) uint32_t smem[];
   __shared__ int32_t s_item;
@@ -264,14 +345,11 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
   const int wave = P > 1 ? __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6) : 0;
   uint32_t* const zeros = smem;
   uint32_t* const inf_cell = zeros + W;
-  uint32_t* const accst = inf_cell + 4;
-  uint32_t* const accleft = accst + (STREAM ? T : 0);
-  uint32_t* const ring = accleft + (STREAM ? 64 : 0);
+  uint32_t* const ring = inf_cell + 4;
   uint32_t* const edge = ring + (P - 1) * 2 * T;
   uint32_t* const stage = edge + (P - 1) * 4 + wave * skew_band_words(W, K, args.max_band);
   uint2* const bx = (uint2*)(stage + T);
   uint32_t* const my_stage = stage + lane * W;
-  uint32_t* const my_acc = accst + lane * W;
   uint2* const bxl = bx + K * (63 - lane);
   uint32_t* const ring_in = ring + (wave > 0 ? wave - 1 : 0) * 2 * T + lane * W;
   uint32_t* const ring_out = ring + (wave < P - 1 ? wave : 0) * 2 * T + lane * W;
@@ -331,10 +409,11 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
     const int32_t r0 = (wave * M) / Pe;
     const int32_t Mb = ((wave + 1) * M) / Pe - r0;  // this band's rows
     const typename F::qin* __restrict__ qv = (const typename F::qin*)args.q + q0 + r0;
-    // Tiles are loaded from global memory one period before they are staged
-    // in LDS (registers ynext / accnext), so the loads' latency is hidden.
-    // Resident row of tile t (and the value left of the lane's strip); a
-    // fresh read (m_old == 0) has gamma(0, .) = 0.
+    // A lane's strip of the tile it enters next (and, in band 0 when
+    // streaming, the resident row's strip and the value left of it) waits in
+    // registers: loaded from global memory once every lane has entered the
+    // current tile, copied by each lane when it enters the next one.  A fresh
+    // read (m_old == 0) has gamma(0, .) = 0.
     uint32_t ynext[W], accnext[STREAM ? W : 1], accleftnext = F::kInf;
     auto load_acc = [&](int32_t t) {
       if constexpr (STREAM) {
@@ -349,13 +428,6 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
         }
       }
     };
-    auto store_acc = [&]() {
-      if constexpr (STREAM) {
-#pragma unroll
-        for (int w = 0; w < W; ++w) my_acc[w] = accnext[w];
-        accleft[lane] = accleftnext;
-      }
-    };
 
     if (active) {
       for (int k = lane; k < Mb + S; k += 64) {
@@ -364,14 +436,7 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
         bx[k] = make_uint2((uint32_t)F::to_lds(qv[s]), F::kInf);  // gamma(i, 0) = +inf
       }
       load_strip<W>(ynext, args.ref + lane * W);
-#pragma unroll
-      for (int w = 0; w < W; ++w) my_stage[w] = ynext[w];
-      if (ntiles > 1) load_strip<W>(ynext, args.ref + T + lane * W);
-      if (wave == 0) {
-        load_acc(0);
-        store_acc();
-        if (ntiles > 1) load_acc(1);
-      }
+      if (wave == 0) load_acc(0);
     }
     __syncthreads();
 
@@ -417,19 +482,76 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
       if (pend && lane == 63) bxl[pend_i].y = pend_v;
       pend = false;
     };
-    // One row step.  CH >= 0: sub-lane r (lane r / K, chain CH == r % K)
-    // enters its next tile in this step; the edges its right neighbours need
-    // are read before the switch overwrites `up`.
-    auto step = [&](auto ch, int32_t r, uint32_t(&up)[W], uint32_t(&nw)[W], bool write_b,
-                    bool wrap) {
-      constexpr int CH = decltype(ch)::value;
+    // One row step.
+    //   SW >= 0: sub-lane r (lane r / K, chain SW == r % K) enters its next
+    //     tile in this step.  With FULL its whole switch is done here, at the
+    //     top of the step (the first step of a period); otherwise the switch
+    //     was issued during the previous step and only the previous-row
+    //     reload of its last group of four columns is left, done here after
+    //     the edges its right neighbours need have been read from it.
+    //   NX >= 0: sub-lane r + 1 (chain NX) enters its next tile in the next
+    //     step; this step has computed its last row on the old tile, and its
+    //     switch is issued between this step's cells, each group of four
+    //     columns right after the cell that last reads the group's registers:
+    //     new reference values from the stage, the finished row out (the last
+    //     band's fin is the stage itself, so each group is read before it is
+    //     overwritten), the new previous row into the registers just stored
+    //     (zeros, the staged resident row or the band above's ring slot).
+    //     The next step's cells then find their operands in place instead of
+    //     waiting for a round of LDS operations.
+    // Where a sub-lane entering a tile takes its previous row: band 0 from
+    // registers (the resident row's strip when streaming; else gamma(0, .) =
+    // 0, as every other column cleared, which puts a zero in every cell's
+    // minimum once the diagonal left of the sub-strip is 0 too), the other
+    // bands from the band above's ring slot in LDS.
+    // (UR: band 0, whose phase A is compiled apart from the other bands')
+    auto diag_in = [&](auto ur, auto hc) -> uint32_t {  // the value left of sub-strip h
+      constexpr bool UR = decltype(ur)::value;
+      constexpr int h = decltype(hc)::value;
+      if constexpr (UR) {
+        if constexpr (!STREAM)
+          return 0u;
+        else if constexpr (h == 0)
+          return accleftnext;
+        else
+          return accnext[h > 0 ? h * H - 1 : 0];
+      } else if constexpr (h == 0) {
+        return *d0src;
+      } else {
+        return upsrc[h > 0 ? h * H - 1 : 0];
+      }
+    };
+    auto prev_in = [&](auto ur, uint32_t(&dst)[W], int w) {  // columns [w, w + 4)
+      if constexpr (decltype(ur)::value) {
+        if constexpr (STREAM) {
+          dst[w] = accnext[w];
+          dst[w + 1] = accnext[w + 1];
+          dst[w + 2] = accnext[w + 2];
+          dst[w + 3] = accnext[w + 3];
+        } else {
+          dst[w + 1] = 0u;
+          dst[w + 3] = 0u;
+        }
+      } else {
+        const uint4 zv = *(const uint4*)(upsrc + w);
+        dst[w] = zv.x;
+        dst[w + 1] = zv.y;
+        dst[w + 2] = zv.z;
+        dst[w + 3] = zv.w;
+      }
+    };
+    auto step = [&](auto ur, auto sw, auto nx, auto full, int32_t r, uint32_t(&up)[W],
+                    uint32_t(&nw)[W], bool write_b, bool wrap) {
+      constexpr int SW = decltype(sw)::value;
+      constexpr int NX = decltype(nx)::value;
+      constexpr bool FULL = decltype(full)::value;
       const uint2 e0 = nxt0;
       uint32_t xs[K];
 #pragma unroll
       for (int h = 1; h < K; ++h) xs[h] = nxtx[h];
       xs[0] = e0.x;
       uint32_t left[K];
-      if constexpr (K == 1)
+      if constexpr (K == 1 && (NX < 0 || SDTW_K1_PLAIN))
         left[0] = from_left_lane(up[W - 1], e0.y);
       else
         left[0] = asm_from_left_lane(up[W - 1], e0.y);
@@ -440,90 +562,155 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int h = 1; h < K; ++h) left[h] = up[h * H - 1];
-      if constexpr (CH >= 0) {
+      if constexpr (SW >= 0) {
         if (lane == r / K) {
           // the band below needs this tile's last column (lane 63's last
-          // value of the finished row): stored before the groups reload the
-          // registers, so that the last group's loads can go straight into
-          // them and the cells wait for the groups in order
-          if constexpr (P > 1 && CH == K - 1) {
+          // value of the finished row), read before the last group reloads
+          if constexpr (P > 1 && SW == K - 1) {
             if (!last && lane == 63) edge_out[(p - 1) & 3] = up[W - 1];
           }
-          // the diagonal first (the first cell needs it), then per group of
-          // four columns: new reference values, the finished row's values
-          // out (the last band's fin is the stage itself, so each group is
-          // read before it is overwritten), the new previous row's values
-          // into the registers just stored.  The cells of the step wait for
-          // the groups in order, so they start after the first few LDS
-          // operations instead of after all of them.  With one band and no
-          // resident row the previous row is always gamma(0, .) = 0 (and so
-          // is the diagonal), and a cell's minimum is 0 as soon as one of
-          // its operands is (costs are non-negative): the diagonal and
-          // every other column of the strip (offsets 1, 3, ...) are cleared
-          // instead of the row being loaded, a third fewer LDS operations
-          // in the switch; the other registers keep the finished row's
-          // values, which in this step only meet a zero in each minimum.
-          constexpr bool kZeroRow = P == 1 && !STREAM;
-          dprev[CH] = kZeroRow ? 0u : (CH == 0 ? *d0src : upsrc[CH * H - 1]);
+          if constexpr (FULL) {
+            dprev[SW] = diag_in(ur, std::integral_constant<int, SW>{});
 #pragma unroll
-          for (int w = CH * H; w < (CH + 1) * H; w += 4) {
-            const uint4 nv = *(const uint4*)(my_stage + w);
-            y[w] = nv.x;
-            y[w + 1] = nv.y;
-            y[w + 2] = nv.z;
-            y[w + 3] = nv.w;
-            *(uint4*)(fin + w) = make_uint4(up[w], up[w + 1], up[w + 2], up[w + 3]);
-            if constexpr (kZeroRow) {
-              up[w + 1] = 0u;
-              up[w + 3] = 0u;
-            } else {
-              const uint4 zv = *(const uint4*)(upsrc + w);
-              up[w] = zv.x;
-              up[w + 1] = zv.y;
-              up[w + 2] = zv.z;
-              up[w + 3] = zv.w;
+            for (int w = SW * H; w < (SW + 1) * H; w += 4) {
+              y[w] = ynext[w];
+              y[w + 1] = ynext[w + 1];
+              y[w + 2] = ynext[w + 2];
+              y[w + 3] = ynext[w + 3];
+              *(uint4*)(fin + w) = make_uint4(up[w], up[w + 1], up[w + 2], up[w + 3]);
+              prev_in(ur, up, w);
+              __builtin_amdgcn_sched_barrier(0);
+            }
+          } else {
+#pragma unroll
+            for (int w = (SW + 1) * H - kGc; w < (SW + 1) * H; w += 4) prev_in(ur, up, w);
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      // the next sub-lane's switch, issued between the cells
+      [[maybe_unused]] const bool nxt = NX >= 0 && lane == (r + 1) / K;
+      [[maybe_unused]] uint32_t dnext = 0;
+      auto after = [&](auto wc) {
+        if constexpr (NX >= 0) {
+          constexpr int wl = decltype(wc)::value;  // column within the sub-strips
+          // group g of the next sub-strip, once column 4g + 4 (the last cell
+          // reading the group's previous and current row) has been issued;
+          // the last group's reference values and finished row after the
+          // last column, its previous row at the top of the next step
+          constexpr int g = wl == H - 1 ? H / kGc - 1 : wl / kGc - 1;
+          if constexpr ((wl >= kGc && wl % kGc == 0) || wl == H - 1) {
+            __builtin_amdgcn_sched_barrier(0);
+            if (nxt) {
+              // the diagonal left of the next strip, early: the next step's
+              // first cell needs it
+              if constexpr (g == 0) dnext = diag_in(ur, std::integral_constant<int, NX>{});
+#pragma unroll
+              for (int w = NX * H + kGc * g; w < NX * H + kGc * (g + 1); w += 4) {
+                y[w] = ynext[w];
+                y[w + 1] = ynext[w + 1];
+                y[w + 2] = ynext[w + 2];
+                y[w + 3] = ynext[w + 3];
+                *(uint4*)(fin + w) = make_uint4(nw[w], nw[w + 1], nw[w + 2], nw[w + 3]);
+                if constexpr (wl != H - 1) prev_in(ur, nw, w);
+              }
             }
             __builtin_amdgcn_sched_barrier(0);
           }
         }
-      }
-      if constexpr (K == 1)
+      };
+      if constexpr (K == 1 && NX < 0)
         strip_row<F, W>(xs[0], y, up, nw, dprev[0], left[0]);
       else
-        chains_row<F, K, H, W>(xs, y, up, nw, dprev, left);
+        chains_row<F, K, H, W>(xs, y, up, nw, dprev, left, after);
 #pragma unroll
       for (int h = 0; h < K; ++h) dprev[h] = left[h];
+      if constexpr (NX >= 0) {
+        if (nxt) dprev[NX] = dnext;
+      }
       pend = write_b;
       pend_i = wrap ? r + Mb : r;
       pend_v = nw[W - 1];
     };
-    using NoSwitch = std::integral_constant<int, -1>;
+    auto plain = [&](int32_t r, uint32_t(&up)[W], uint32_t(&nw)[W]) {
+      using NoSwitch = std::integral_constant<int, -1>;
+      step(std::false_type{}, NoSwitch{}, NoSwitch{}, std::false_type{}, r, up, nw, true, false);
+    };
 
     const int32_t nglob = ntiles + 1 + 2 * (Pe - 1);
     for (int32_t G = 0; G < nglob; ++G) {
       p = G - 2 * wave;
       if (active && p >= 0 && p <= ntiles) {
         if (wave == 0) {
-          upsrc = STREAM ? my_acc : zeros;
-          d0src = STREAM ? accleft + lane : zeros;
+          upsrc = zeros;  // not read: band 0's previous row comes from registers
+          d0src = zeros;
         } else {
           upsrc = ring_in + (p & 1) * T;
           d0src = lane > 0 ? upsrc - 1 : (p > 0 ? edge_in + ((p - 1) & 3) : inf_cell);
         }
         fin = last ? my_stage : ring_out + ((p - 1) & 1) * T;
-        // phase A: the 64K switch steps
+        // phase A: the 64K switch steps.  Step 0 switches sub-lane 0 at its
+        // top (its previous row may come from the ring slot the band above
+        // wrote in the previous global period); every later switch is issued
+        // one step early, between the cells of the step before.
         const bool first = (p == 0);
         load_entries(0);  // row 0 of the period (entry 64K - 1 + M_g is not kept)
-        for (int32_t r = 0; r < S; r += U) {
-          // chain index of step r + u is (r + u) % K == u % K since U % K == 0
-          static_for<0, U / 2>([&](auto uu) {
-            constexpr int u = 2 * decltype(uu)::value;
-            step(std::integral_constant<int, u % K>{}, r + u, a, b, !first || r + u == S - 1,
-                 r + u != S - 1);
-            step(std::integral_constant<int, (u + 1) % K>{}, r + u + 1, b, a,
-                 !first || r + u + 1 == S - 1, r + u + 1 != S - 1);
-          });
-        }
+        // phase A is compiled twice: band 0 takes its previous row from
+        // registers, the other bands from the ring
+        auto phase_a = [&](auto ur) {
+          if constexpr (kPipe) {
+            using C0 = std::integral_constant<int, 0>;
+            using C1 = std::integral_constant<int, 1 % K>;
+            using Yes = std::true_type;
+            using No = std::false_type;
+            step(ur, C0{}, C1{}, Yes{}, 0, a, b, !first || S == 1, true);
+            // steps 1 .. S - U: blocks of U (step r's sub-lane chain is r % K
+            // and its registers alternate with r's parity; U is even and a
+            // multiple of K)
+            for (int32_t r = 1; r + U - 1 < S; r += U) {
+              static_for<0, U>([&](auto uu) {
+                constexpr int u = decltype(uu)::value;
+                constexpr int sw = (1 + u) % K, nx = (2 + u) % K;
+                using Sw = std::integral_constant<int, sw>;
+                using Nx = std::integral_constant<int, nx>;
+                if constexpr (u % 2 == 0)
+                  step(ur, Sw{}, Nx{}, No{}, r + u, b, a, !first, true);
+                else
+                  step(ur, Sw{}, Nx{}, No{}, r + u, a, b, !first, true);
+              });
+            }
+            // steps S - U + 1 .. S - 1 (the last has no successor to switch)
+            static_for<0, U - 1>([&](auto uu) {
+              constexpr int u = decltype(uu)::value;
+              constexpr int rr = S - U + 1 + u;
+              constexpr int sw = rr % K;
+              using Nx = std::integral_constant<int, rr + 1 < S ? (rr + 1) % K : -1>;
+              if constexpr (rr % 2 == 1)
+                step(ur, std::integral_constant<int, sw>{}, Nx{}, No{}, rr, b, a,
+                     !first || rr == S - 1, rr != S - 1);
+              else
+                step(ur, std::integral_constant<int, sw>{}, Nx{}, No{}, rr, a, b,
+                     !first || rr == S - 1, rr != S - 1);
+            });
+          } else {
+            for (int32_t r = 0; r < S; r += U) {
+              static_for<0, U / 2>([&](auto uu) {
+                constexpr int u = 2 * decltype(uu)::value;
+                using NoNext = std::integral_constant<int, -1>;
+                using Sw0 = std::integral_constant<int, u % K>;
+                using Sw1 = std::integral_constant<int, (u + 1) % K>;
+                step(ur, Sw0{}, NoNext{}, std::true_type{}, r + u, a, b,
+                     !first || r + u == S - 1, r + u != S - 1);
+                step(ur, Sw1{}, NoNext{}, std::true_type{}, r + u + 1, b, a,
+                     !first || r + u + 1 == S - 1, r + u + 1 != S - 1);
+              });
+            }
+          }
+        };
+        if (wave == 0)
+          phase_a(std::true_type{});
+        else if constexpr (P > 1)
+          phase_a(std::false_type{});
         flush();
         // every lane has finished tile p-1: the last band folds its last row
         // (and writes it back as the new resident row); stage tile p+1
@@ -545,29 +732,25 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
           }
         }
         if (p + 1 < ntiles) {
-#pragma unroll
-          for (int w = 0; w < W; ++w) my_stage[w] = ynext[w];
-          if (p + 2 < ntiles) load_strip<W>(ynext, args.ref + (int64_t)(p + 2) * T + lane * W);
-          if (wave == 0) {
-            store_acc();
-            if (p + 2 < ntiles) load_acc(p + 2);
-          }
+          // every lane has copied tile p: fetch tile p + 1
+          load_strip<W>(ynext, args.ref + (int64_t)(p + 1) * T + lane * W);
+          if (wave == 0) load_acc(p + 1);
         }
         if (p < ntiles) {
           // phase B: plain steps, four per iteration
           int32_t r = S;
           for (; r + 3 < Mb; r += 4) {
-            step(NoSwitch{}, r, a, b, true, false);
-            step(NoSwitch{}, r + 1, b, a, true, false);
-            step(NoSwitch{}, r + 2, a, b, true, false);
-            step(NoSwitch{}, r + 3, b, a, true, false);
+            plain(r, a, b);
+            plain(r + 1, b, a);
+            plain(r + 2, a, b);
+            plain(r + 3, b, a);
           }
           for (; r + 1 < Mb; r += 2) {
-            step(NoSwitch{}, r, a, b, true, false);
-            step(NoSwitch{}, r + 1, b, a, true, false);
+            plain(r, a, b);
+            plain(r + 1, b, a);
           }
           if (r < Mb) {
-            step(NoSwitch{}, r, a, b, true, false);
+            plain(r, a, b);
 #pragma unroll
             for (int w = 0; w < W; ++w) a[w] = b[w];
           }
@@ -716,7 +899,7 @@ __global__ void k_reset_counter(int32_t* c) {
 
 template <class F, int W, int K, int P, bool STREAM>
 hipError_t launch_skew_t(int blocks, const AlignArgs& a, hipStream_t st) {
-  const size_t lds = std::max(skew_lds_bytes(W, K, P, a.max_band, STREAM), (size_t)a.lds_bytes);
+  const size_t lds = std::max(skew_lds_bytes(W, K, P, a.max_band), (size_t)a.lds_bytes);
   hipError_t e = hipFuncSetAttribute((const void*)k_align_skew<F, W, K, P, STREAM>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -764,6 +947,7 @@ hipError_t launch_skew_f(int strip, int chains, int bands, int blocks, const Ali
     case (16 * 8 + 2) * 8 + 4: return launch_skew_s<F, 16, 2, 4>(blocks, a, st, stream);
     case (16 * 8 + 1) * 8 + 3: return launch_skew_s<F, 16, 1, 3>(blocks, a, st, stream);
     case (32 * 8 + 1) * 8 + 2: return launch_skew_s<F, 32, 1, 2>(blocks, a, st, stream);
+    case (32 * 8 + 2) * 8 + 2: return launch_skew_s<F, 32, 2, 2>(blocks, a, st, stream);
     case (32 * 8 + 1) * 8 + 3: return launch_skew_s<F, 32, 1, 3>(blocks, a, st, stream);
     case (32 * 8 + 1) * 8 + 4: return launch_skew_s<F, 32, 1, 4>(blocks, a, st, stream);
   }

@@ -2,6 +2,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -12,6 +13,7 @@
 #include <new>
 #include <numeric>
 #include <set>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -472,8 +474,8 @@ static std::vector<LaunchGroup> launch_groups(const sdtw_plan_s* p) {
 
 // Resident waves per CU for a skew launch: whole workgroups of `bands` waves
 // within the CU's 160 KiB of LDS, at most 16 waves (four per SIMD).
-static int skew_waves_per_cu(int strip, int chains, int bands, int max_band, bool stream) {
-  const size_t per = skew_lds_bytes(strip, chains, bands, max_band, stream);
+static int skew_waves_per_cu(int strip, int chains, int bands, int max_band) {
+  const size_t per = skew_lds_bytes(strip, chains, bands, max_band);
   const int groups = (int)std::min<size_t>(16 / bands, (160 * 1024) / std::max<size_t>(per, 1));
   return std::max(groups, 1) * bands;
 }
@@ -522,8 +524,7 @@ static void choose_config(sdtw_plan_s* p) {
   p->band_rows = 0;
   p->waves_per_cu = skew_waves_per_cu(p->strip, p->chains, p->bands,
                                       std::max(skew_band_rows(p->max_m, p->chains, p->bands),
-                                               skew_min_m(p->chains)),
-                                      false);
+                                               skew_min_m(p->chains)));
 }
 
 int sdtw_plan_create(const int64_t* offsets_host, int32_t nq, int dtype, sdtw_plan* out) {
@@ -612,7 +613,9 @@ int sdtw_plan_set_config(sdtw_plan plan, int strip, int chains, int bands, int w
     if (!valid_skew_config(s2, k2, b2) || w2 % b2 != 0) b2 = 1;
   }
   SDTW_REQUIRE(valid_skew_config(s2, k2, b2),
-               "sdtw_plan_set_config: %d bands need strip 16 and at most 2 chains", b2);
+               "sdtw_plan_set_config: strip %d with %d chains and %d bands is not built "
+               "(bands > 1: strip 16 with at most 2 chains, strip 32 with 1 chain, or strip "
+               "32 with 2 chains and 2 bands)", s2, k2, b2);
   SDTW_REQUIRE(w2 % b2 == 0, "sdtw_plan_set_config: waves_per_cu %d is not a multiple of %d bands",
                w2, b2);
   plan->strip = s2;
@@ -672,7 +675,7 @@ static int align_batch_impl(sdtw_ref ref, sdtw_plan plan, const void* q_dev, voi
   const std::vector<LaunchGroup> groups = launch_groups(plan);
   const size_t lds_max = (size_t)max_lds_bytes();
   for (const LaunchGroup& g : groups) {
-    const size_t lds = g.chains ? skew_lds_bytes(plan->strip, g.chains, g.bands, g.max_band, false)
+    const size_t lds = g.chains ? skew_lds_bytes(plan->strip, g.chains, g.bands, g.max_band)
                                 : plain_lds_bytes(plan->dtype, plan->strip, g.max_m);
     SDTW_REQUIRE(lds <= lds_max, "sdtw_align_batch: %zu bytes of LDS needed, %zu available", lds,
                  lds_max);
@@ -695,7 +698,7 @@ static int align_batch_impl(sdtw_ref ref, sdtw_plan plan, const void* q_dev, voi
     if (g.chains) {
       const int groups_per_cu = std::max(plan->waves_per_cu / g.bands, 1);
       const int blocks = (int)std::min<int64_t>((int64_t)plan->cus * groups_per_cu, g.count);
-      a.lds_bytes = spread_lds(skew_lds_bytes(plan->strip, g.chains, g.bands, g.max_band, false),
+      a.lds_bytes = spread_lds(skew_lds_bytes(plan->strip, g.chains, g.bands, g.max_band),
                                blocks, groups_per_cu, plan->cus);
       rc = check_hip(launch_align_skew(plan->dtype, plan->strip, g.chains, g.bands, blocks, a, st),
                      "sdtw_align_batch: launch");
@@ -795,15 +798,22 @@ int sdtw_align_one_wide_noalloc(sdtw_ref ref, const void* q_dev, int32_t M, int 
 // autotuning
 // ---------------------------------------------------------------------------
 
+}  // extern "C"
+
 namespace {
+// Tuned launch shapes are remembered per (architecture and compute units,
+// dtype, reference length, batch shape class); the batch shape class puts
+// the number of reads, the median and the longest read length each into
+// quarter-octave buckets, so batches of about the same shape (a serving
+// loop's ragged batches, a workload drawn again) share a tuned shape.
 struct TuneKey {
-  int device, dtype;
+  std::string arch;
+  int cus, dtype;
   int64_t n;
-  int32_t nq, max_m;
-  int64_t sum_m;
+  int nq_b, med_b, max_b;
   bool operator<(const TuneKey& o) const {
-    return std::tie(device, dtype, n, nq, max_m, sum_m) <
-           std::tie(o.device, o.dtype, o.n, o.nq, o.max_m, o.sum_m);
+    return std::tie(arch, cus, dtype, n, nq_b, med_b, max_b) <
+           std::tie(o.arch, o.cus, o.dtype, o.n, o.nq_b, o.med_b, o.max_b);
   }
 };
 struct TuneVal {
@@ -811,14 +821,75 @@ struct TuneVal {
   int32_t band_rows;
 };
 std::mutex g_tune_mu;
-std::map<TuneKey, TuneVal> g_tuned;  // best configuration per batch shape and reference length
+std::map<TuneKey, TuneVal> g_tuned;  // best configuration per key
+bool g_tune_file_read = false;
+
+int quarter_octave(int64_t v) { return (int)lround(4.0 * log2((double)std::max<int64_t>(v, 1))); }
+
+std::string device_arch(int device) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  for (char& c : a)
+    if (c == ' ') c = '_';
+  return a;
+}
 
 TuneKey tune_key(const sdtw_plan_s* p, int64_t n) {
-  int64_t sum = 0;
-  for (int32_t m : p->sorted_m) sum += m;
-  return {p->device, p->dtype, n, p->nq, p->max_m, sum};
+  return {device_arch(p->device), p->cus, p->dtype, n, quarter_octave(p->nq),
+          quarter_octave(p->sorted_m[p->sorted_m.size() / 2]), quarter_octave(p->max_m)};
+}
+
+// Optional persistence: SDTW_TUNE_CACHE names a text file with one tuned
+// shape per line ("arch cus dtype n nq_b med_b max_b strip chains bands
+// waves_per_cu band_rows"), read once per process and rewritten after every
+// autotune.  Unset or empty: the cache lives in this process only.
+const char* tune_file() {
+  const char* f = getenv("SDTW_TUNE_CACHE");
+  return (f && *f) ? f : nullptr;
+}
+
+void tune_file_read_locked() {
+  if (g_tune_file_read) return;
+  g_tune_file_read = true;
+  const char* path = tune_file();
+  if (!path) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  char arch[256];
+  TuneKey k;
+  TuneVal v;
+  long long n;
+  while (fscanf(f, "%255s %d %d %lld %d %d %d %d %d %d %d %d", arch, &k.cus, &k.dtype, &n,
+                &k.nq_b, &k.med_b, &k.max_b, &v.strip, &v.chains, &v.bands, &v.waves_per_cu,
+                &v.band_rows) == 12) {
+    k.arch = arch;
+    k.n = n;
+    if (valid_skew_config(v.strip, v.chains, v.bands) && v.waves_per_cu >= v.bands &&
+        v.waves_per_cu <= 32 && v.waves_per_cu % v.bands == 0)
+      g_tuned[k] = v;
+  }
+  fclose(f);
+}
+
+void tune_file_write_locked() {
+  const char* path = tune_file();
+  if (!path) return;
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return;
+  for (const auto& kv : g_tuned) {
+    const TuneKey& k = kv.first;
+    const TuneVal& v = kv.second;
+    fprintf(f, "%s %d %d %lld %d %d %d %d %d %d %d %d\n", k.arch.c_str(), k.cus, k.dtype,
+            (long long)k.n, k.nq_b, k.med_b, k.max_b, v.strip, v.chains, v.bands,
+            v.waves_per_cu, (int)v.band_rows);
+  }
+  if (fclose(f) == 0) rename(tmp.c_str(), path);
 }
 }  // namespace
+
+extern "C" {
 
 int sdtw_plan_autotune(sdtw_ref ref, sdtw_plan plan, const void* q_dev, void* cost_dev,
                        int32_t* end_dev, int64_t max_columns, void* stream) {
@@ -853,7 +924,7 @@ int sdtw_plan_autotune(sdtw_ref ref, sdtw_plan plan, const void* q_dev, void* co
         for (int32_t target : targets) {
           const int band_rows = std::max(skew_band_rows(plan->max_m, chains, bands, target),
                                          skew_min_m(chains));
-          const int w = skew_waves_per_cu(strip, chains, bands, band_rows, false);
+          const int w = skew_waves_per_cu(strip, chains, bands, band_rows);
           cand.push_back({strip, chains, bands, w, target});
           if (w / 2 >= bands && (w / 2) % bands == 0)
             cand.push_back({strip, chains, bands, w / 2, target});
@@ -910,15 +981,20 @@ int sdtw_plan_autotune(sdtw_ref ref, sdtw_plan plan, const void* q_dev, void* co
   plan->waves_per_cu = best.waves_per_cu;
   plan->band_rows = best.band_rows;
   if (rc) return rc;
+  const TuneKey key = tune_key(plan, ref->n);
   std::lock_guard<std::mutex> g(g_tune_mu);
-  g_tuned[tune_key(plan, ref->n)] = best;
+  tune_file_read_locked();
+  g_tuned[key] = best;
+  tune_file_write_locked();
   return SDTW_OK;
 }
 
 int sdtw_plan_use_tuned(sdtw_ref ref, sdtw_plan plan, int* found) {
   SDTW_REQUIRE(ref && plan, "sdtw_plan_use_tuned: null reference or plan");
+  const TuneKey key = tune_key(plan, ref->n);
   std::lock_guard<std::mutex> g(g_tune_mu);
-  auto it = g_tuned.find(tune_key(plan, ref->n));
+  tune_file_read_locked();
+  auto it = g_tuned.find(key);
   if (found) *found = it != g_tuned.end();
   if (it != g_tuned.end()) {
     plan->strip = it->second.strip;
@@ -1125,7 +1201,7 @@ int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk
     ++nbig;
   }
   const size_t lds_max = (size_t)max_lds_bytes();
-  SDTW_REQUIRE(skew_lds_bytes(kStrip, kChains, bands, max_band, true) <= lds_max &&
+  SDTW_REQUIRE(skew_lds_bytes(kStrip, kChains, bands, max_band) <= lds_max &&
                    plain_lds_bytes(dtype, kStrip, max_m) <= lds_max,
                "sdtw_stream_extend: chunk of %d rows needs more LDS than available", max_m);
 
@@ -1167,7 +1243,7 @@ int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk
     a.max_band = max_band;
     // no LDS reservation (spread_lds): calls in flight on other HIP streams
     // (other targets, the next batch) must find room on every CU
-    const int wpc = skew_waves_per_cu(kStrip, kChains, bands, max_band, true);
+    const int wpc = skew_waves_per_cu(kStrip, kChains, bands, max_band);
     const int blocks = (int)std::min<int64_t>((int64_t)cus * (wpc / bands), nbig);
     a.lds_bytes = 0;
     rc = check_hip(launch_align_skew(dtype, kStrip, kChains, bands, blocks, a, st, true),

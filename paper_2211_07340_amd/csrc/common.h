@@ -35,13 +35,14 @@ inline bool valid_strip_chains(int strip, int chains) {
 
 // Row bands per workgroup (waves per read): 1 for every (strip, chains)
 // above; 2 or 4 with strip 16 and 1 or 2 chains; 2, 3 or 4 with strip 16 or
-// 32 and 1 chain.
+// 32 and 1 chain; 2 with strip 32 and 2 chains.
 inline bool valid_skew_config(int strip, int chains, int bands) {
   if (!valid_strip_chains(strip, chains)) return false;
   if (bands == 1) return true;
   if (bands == 3) return chains == 1 && (strip == 16 || strip == 32);
   if (bands != 2 && bands != 4) return false;
-  return (strip == 16 && chains <= 2) || (strip == 32 && chains == 1);
+  return (strip == 16 && chains <= 2) || (strip == 32 && chains == 1) ||
+         (strip == 32 && chains == 2 && bands == 2);
 }
 
 // Bands a read of M rows is cut into: as many as allowed (at most `bands`,
@@ -65,15 +66,14 @@ inline int32_t skew_band_rows(int32_t m, int chains, int bands, int32_t target =
   return (m + pe - 1) / pe;
 }
 
-// LDS words of the skew kernel: shared part (zeros and a +inf cell; resident
-// row strips when streaming; the band-to-band rings) and, per band, the tile
-// stage and the query/boundary entries of up to band_rows rows.
+// LDS words of the skew kernel: shared part (zeros and a +inf cell; the
+// band-to-band rings) and, per band, the finished-row stage and the
+// query/boundary entries of up to band_rows rows.
 __host__ __device__ constexpr int skew_band_words(int strip, int chains, int band_rows) {
   return (64 * strip + 2 * (band_rows + 64 * chains) + 3) & ~3;
 }
-inline size_t skew_lds_bytes(int strip, int chains, int bands, int band_rows, bool stream) {
-  const size_t shared = (size_t)strip + 4 + (stream ? (size_t)64 * strip + 64 : 0) +
-                        (size_t)(bands - 1) * (2 * 64 * (size_t)strip + 4);
+inline size_t skew_lds_bytes(int strip, int chains, int bands, int band_rows) {
+  const size_t shared = (size_t)strip + 4 + (size_t)(bands - 1) * (2 * 64 * (size_t)strip + 4);
   return 4 * (shared + (size_t)bands * (size_t)skew_band_words(strip, chains, band_rows));
 }
 

@@ -104,3 +104,27 @@ def test_stream_argument_validation(lib):
     assert lib.sdtw_stream_extend(arr, 1, p, offs.ctypes.data_as(C.c_void_p), p, p, None) == 1
     assert lib.sdtw_set_row_budget(-5) == 1
     assert lib.sdtw_prepare_queries_ex(None, p, 1, 64.0, None, None, p, p, p, None) == 1
+
+
+def test_probe_library_exports_its_header():
+    # include/sdtw_probe.h: the issue-rate and LDS probes (libsdtw_probe.so)
+    from paper_2211_07340_amd import build as hipbuild
+    if not os.path.exists(hipbuild.PROBE_LIB):
+        hipbuild.build_probe()
+    text = open(os.path.join(ROOT, "include", "sdtw_probe.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = sorted(set(re.findall(r"\b(sdtw_\w+)\s*\(", text)))
+    assert names == ["sdtw_probe_issue", "sdtw_probe_lds"]
+    raw = C.CDLL(hipbuild.PROBE_LIB)
+    assert all(hasattr(raw, n) for n in names)
+    # bad arguments are rejected before any device call
+    raw.sdtw_probe_issue.argtypes = [C.c_int] * 4 + [C.c_void_p] * 2
+    raw.sdtw_probe_lds.argtypes = [C.c_int] * 3 + [C.c_void_p] * 2
+    out = C.c_void_p(1)
+    assert raw.sdtw_probe_issue(5, 1, 1, 1, out, None) == 1      # no such kind
+    assert raw.sdtw_probe_issue(0, 3, 1, 1, out, None) == 1      # chains
+    assert raw.sdtw_probe_issue(0, 1, 9, 1, out, None) == 1      # waves per SIMD
+    assert raw.sdtw_probe_issue(0, 1, 1, 1, None, None) == 1     # no output
+    assert raw.sdtw_probe_lds(0, 1, 1, out, None) == 1           # lanes
+    assert raw.sdtw_probe_lds(65, 1, 1, out, None) == 1
+    assert raw.sdtw_probe_lds(1, 1, 0, out, None) == 1           # iterations

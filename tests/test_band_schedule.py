@@ -10,6 +10,18 @@ only through that row), handed over through an LDS ring of two tile slots,
 plus a ring of four values that carries each tile's last column (the
 diagonal that lane 0 needs when it enters the next tile).
 
+Within a period, sub-lane 0 switches at the top of step 0 and every later
+sub-lane's switch is issued during the step before its own (after it has
+computed its last row on the old tile), except the previous-row reload of
+its last group of columns, done at the top of its own step after its right
+neighbours have read their edge from them, as the kernel does.  Where the
+previous row comes from is also the kernel's: band 0 takes gamma(0, .) = 0
+as every other column cleared with the diagonal set to 0, or, streaming,
+the resident row's strip and the value left of it, fetched with the tile's
+reference values once every lane has entered the current tile; the other
+bands read the ring.  The reference values of the next tile are held apart
+from the last band's staged last rows.
+
 Timing: the workgroup runs global periods G = 0, 1, ... with one barrier
 after each; wave g runs its local period p = G - 2g.  Wave g - 1 writes tile
 t's last rows during its switch steps of local period t + 1 (global
@@ -32,7 +44,7 @@ L = 64
 
 
 class Band:
-    def __init__(self, g, P, x_rows, ref, W, K, N, shared, acc=None, last=False):
+    def __init__(self, g, P, x_rows, ref, W, K, N, shared, acc=None, last=False, gc=4):
         self.g, self.P, self.W, self.K, self.N = g, P, W, K, N
         self.T = L * W
         self.H = W // K
@@ -48,7 +60,9 @@ class Band:
         nent = M + S
         self.bxx = np.array([xb[(k - (S - 1)) % M] for k in range(nent)], np.uint64)
         self.bxy = np.full(nent, INF, np.uint64)
-        self.stage = ref[0:self.T].reshape(L, W).copy()
+        self.G = min(gc, self.H)  # columns of the deferred last group
+        self.stage = np.zeros((L, W), np.uint64)              # finished last rows
+        self.ynext = ref[0:self.T].reshape(L, W).copy()       # next tile's reference
         self.y = np.zeros((L, W), np.uint64)
         self.a = np.zeros((L, W), np.uint64)
         self.b = np.zeros((L, W), np.uint64)
@@ -76,8 +90,8 @@ class Band:
         """(up source [L, W], dprev of chain 0 [L]) for sub-lanes entering tile p."""
         W = self.W
         if self.g == 0:
-            if self.acc is None:
-                return np.zeros((L, W), np.uint64), np.zeros(L, np.uint64)
+            if self.acc is None:  # gamma(0, .) = 0: cleared in registers
+                return None, np.zeros(L, np.uint64)
             return self.accst, self.accleft
         ring, edge = self.sh["ring"][self.g - 1], self.sh["edge"][self.g - 1]
         up = ring[p & 1]
@@ -101,18 +115,15 @@ class Band:
             lefts.append(lf)
         if sw:
             l, h = r // K, r % K
-            cols = slice(h * H, (h + 1) * H)
             upsrc, d0 = src
-            nv = self.stage[l, cols].copy()
-            if self.last:
-                self.stage[l, cols] = up[l, cols]
-            else:
-                self.sh["ring"][self.g][(p - 1) & 1][l, cols] = up[l, cols]
-                if h == K - 1 and l == 63:
-                    self.sh["edge"][self.g][(p - 1) & 3] = up[l, W - 1]
-            self.y[l, cols] = nv
-            up[l, cols] = upsrc[l, cols]
-            self.dprev[h][l] = d0[l] if h == 0 else upsrc[l, h * H - 1]
+            if h == K - 1 and l == 63 and not self.last:
+                self.sh["edge"][self.g][(p - 1) & 3] = up[l, W - 1]
+            if r == 0:  # the period's first switch: all of it, here
+                self.switch(p, l, h, up, slice(h * H, (h + 1) * H), src)
+                self.dprev[h][l] = self.diag(l, h, src)
+            else:       # issued in the previous step but for the last group's
+                        # previous row, reloaded after the edges were read
+                self.reload(up, l, slice((h + 1) * H - self.G, (h + 1) * H), upsrc)
         for h in range(K):
             ex = ent[h][0]
             diag, lf = self.dprev[h].copy(), lefts[h].copy()
@@ -125,6 +136,42 @@ class Band:
             self.dprev[h] = lefts[h]
         if write_b:
             self.bxy[r + (M if wrap else 0)] = nw[63, W - 1]
+        if sw and r + 1 < S:
+            # the next sub-lane has computed its last row on the old tile: its
+            # switch is issued now (every group but the last group's previous
+            # row, which its right neighbours still read as their edge)
+            l, h = (r + 1) // K, (r + 1) % K
+            upsrc, d0 = src
+            self.switch(p, l, h, nw, slice(h * H, (h + 1) * H - self.G), src,
+                        cols=slice(h * H, (h + 1) * H))
+            self.dprev[h][l] = self.diag(l, h, src)
+
+    def diag(self, l, h, src):
+        """The value left of sub-strip h in the row sub-lane (l, h) enters with."""
+        upsrc, d0 = src
+        if h == 0:
+            return d0[l]
+        return 0 if upsrc is None else upsrc[l, h * self.H - 1]
+
+    @staticmethod
+    def reload(row, l, cols, upsrc):
+        if upsrc is None:  # the odd columns cleared, as the kernel does
+            row[l, [c for c in range(cols.start, cols.stop) if c % 2 == 1]] = 0
+        else:
+            row[l, cols] = upsrc[l, cols]
+
+    def switch(self, p, l, h, row, reload, src, cols=None):
+        """Sub-lane (l, h) enters tile p: new reference values, its finished
+        row (in `row`) out to the stage (last band) or the ring, the new
+        previous row into the columns `reload`."""
+        cols = reload if cols is None else cols
+        upsrc, _ = src
+        if self.last:
+            self.stage[l, cols] = row[l, cols]
+        else:
+            self.sh["ring"][self.g][(p - 1) & 1][l, cols] = row[l, cols]
+        self.y[l, cols] = self.ynext[l, cols]
+        self.reload(row, l, reload, upsrc)
 
     def period(self, p, ntiles):
         S, M, T, W = self.S, self.M, self.T, self.W
@@ -142,8 +189,8 @@ class Band:
                         self.best[l], self.bestj[l] = self.stage[l, w], j
             if self.acc is not None:
                 self.acc[(p - 1) * T:p * T] = self.stage.reshape(-1)
-        if p + 1 < ntiles:
-            self.stage[:] = self.ref[(p + 1) * T:(p + 2) * T].reshape(L, W)
+        if p + 1 < ntiles:  # every lane has entered tile p: fetch tile p + 1
+            self.ynext[:] = self.ref[(p + 1) * T:(p + 2) * T].reshape(L, W)
             if self.acc is not None and self.g == 0:
                 self.stage_acc(p + 1)
         if p == ntiles:

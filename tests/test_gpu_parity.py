@@ -136,7 +136,8 @@ def _ragged_case(seed, Ms, N, lo=-3000, hi=3000):
 
 @pytest.mark.parametrize("strip,chains,bands,waves", [
     (16, 1, 2, 2), (16, 1, 2, 8), (16, 1, 4, 4), (16, 1, 4, 16), (16, 2, 2, 4), (16, 2, 4, 8),
-    (32, 1, 2, 4), (32, 1, 4, 8), (16, 1, 3, 3), (16, 1, 3, 12), (32, 1, 3, 6)])
+    (32, 1, 2, 4), (32, 1, 4, 8), (16, 1, 3, 3), (16, 1, 3, 12), (32, 1, 3, 6),
+    (32, 2, 2, 4), (32, 2, 2, 8)])
 def test_band_schedule_invariance(dev, strip, chains, bands, waves):
     # row bands (several waves per read): reads whose band count ranges from
     # 1 to 4, band heights at the minimum and ragged, several tiles and a
@@ -166,7 +167,7 @@ def test_band_row_targets(dev, strip, bands, band_rows):
 
 @pytest.mark.parametrize("strip,chains,bands", [(16, 1, 2), (16, 1, 4), (16, 2, 2), (16, 2, 4),
                                                 (32, 1, 2), (32, 1, 4), (16, 1, 3),
-                                                (32, 1, 3)])
+                                                (32, 1, 3), (32, 2, 2)])
 def test_band_boundary_diagonal_on_exact_substrings(dev, strip, chains, bands):
     # each read is an exact substring of the reference whose zero-cost
     # diagonal crosses from band g - 1 into band g exactly at a tile
@@ -352,8 +353,49 @@ def test_autotune_keeps_results_and_is_remembered(dev, small_ref):
     check_i16((cost.cpu().numpy(), end.cpu().numpy()), qc, offs, codes)
     again = sd.Plan(offs, sd.I16)
     assert sd.use_tuned(ref, again) and again.config == cfg
+    # another batch of the same shape class (66 reads of 240-260 rows: the
+    # same quarter-octave buckets of count, median and longest) finds it
+    rng = np.random.default_rng(5)
+    lens = rng.integers(240, 261, size=66)
+    similar = sd.Plan(np.concatenate([[0], np.cumsum(lens)]).astype(np.int64), sd.I16)
+    assert sd.use_tuned(ref, similar) and similar.config == cfg
     other = sd.Plan(offs[:9], sd.I16)
     assert not sd.use_tuned(ref, other)
-    for pl in (plan, again, other):
+    for pl in (plan, again, similar, other):
         pl.close()
     ref.close()
+
+
+def test_autotune_cache_file_is_read_by_a_new_process(tmp_path):
+    # SDTW_TUNE_CACHE: one process tunes and writes the file, a fresh one
+    # applies the shape without tuning
+    import os
+    import subprocess
+    import textwrap
+    path = tmp_path / "tune.txt"
+    code = textwrap.dedent("""
+        import sys, numpy as np, torch
+        sys.path.insert(0, %r)
+        import synth, oracle, paper_2211_07340_amd as sd
+        w = synth.workload(1, nq=64)
+        _, codes, _ = oracle.prepare_reference(w.genome, w.table, w.k)
+        _, qc, _ = oracle.prepare_queries(w.reads.values, w.reads.offsets)
+        dev = torch.device("cuda:0")
+        ref = sd.Reference(torch.from_numpy(codes).to(dev))
+        plan = sd.Plan(w.reads.offsets, sd.I16)
+        if sys.argv[1] == "tune":
+            print(sd.autotune(ref, plan, torch.from_numpy(qc).to(dev), max_columns=4096))
+        else:
+            print(sd.use_tuned(ref, plan), plan.config)
+        torch.cuda.synchronize()
+    """) % os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, SDTW_TUNE_CACHE=str(path))
+    out1 = subprocess.run([sys.executable, "-c", code, "tune"], env=env, capture_output=True,
+                          text=True, timeout=240)
+    assert out1.returncode == 0, out1.stderr[-2000:]
+    assert path.exists() and len(path.read_text().splitlines()) == 1
+    out2 = subprocess.run([sys.executable, "-c", code, "use"], env=env, capture_output=True,
+                          text=True, timeout=240)
+    assert out2.returncode == 0, out2.stderr[-2000:]
+    assert out2.stdout.strip().splitlines()[-1].startswith("True")
+    assert out1.stdout.strip().splitlines()[-1] in out2.stdout

@@ -5,16 +5,21 @@ for K chains per lane (lane l's strip of W columns is cut into K sub-strips
 of W/K columns; sub-strip h of lane l is "sub-lane" s = K l + h and works on
 row t - s at step t, so a lane advances K independent dependency chains per
 step).  It follows the kernel's periods of M steps: the 64K switch steps in
-which sub-lane r enters its next tile (after its outgoing edge has been read
-by its right neighbour), the query/boundary LDS entries at K(63 - l) + r +
-(K - 1 - h) read one step ahead, the boundary writes of the last sub-lane (at
-r, or r + M while its row wraps), the per-tile fold of the staged last rows
-and the lexicographic final reduction.  At a tile switch the previous row is
-cleared the way the kernel clears it (the diagonal and every other column
-only), so the model also checks that a zero among each cell's minimum
-operands is all the first row of a tile needs.  It checks the schedule
-itself against the oracle on the CPU; the GPU parity tests check the
-compiled kernel.
+which sub-lane r enters its next tile -- either every switch at the top of
+its own step (the one-band kernel), or sub-lane 0 there and every later
+sub-lane's switch issued during the step before, once it has computed its
+last row on the old tile, except the previous-row reload of its last group
+of columns, done after its outgoing edge has been read by its right
+neighbour (the kernel with bands or a resident row) -- the query/boundary
+LDS entries at K(63 - l) + r + (K - 1 - h) read one step ahead, the boundary
+writes of the last sub-lane (at r, or r + M while its row wraps), the
+reference values of the next tile held apart from the staged last rows, the
+per-tile fold of the staged last rows and the lexicographic final
+reduction.  At a tile switch the previous row gamma(0, .) = 0 is entered as
+the kernel does it: every other column cleared and the diagonal set to 0,
+so that every cell of the tile's first row has a zero among its minimum's
+operands.  It checks the schedule itself against the oracle on the CPU; the
+GPU parity tests check the compiled kernel.
 """
 import numpy as np
 import pytest
@@ -24,7 +29,7 @@ import oracle
 INF = 0xFFFFFFFF
 
 
-def skew_model(x, yref, W, K=1):
+def skew_model(x, yref, W, K=1, defer_last=True, pipe=True, gc=4, clear_diag=True):
     L = 64
     T = L * W
     H = W // K
@@ -38,8 +43,10 @@ def skew_model(x, yref, W, K=1):
     nent = M + S
     bxx = np.array([xb[(k - (S - 1)) % M] for k in range(nent)], np.uint64)
     bxy = np.full(nent, INF, np.uint64)
-    stage = ref[0:T].reshape(L, W).copy()
+    stage = np.zeros((L, W), np.uint64)       # finished last rows of the tile
+    ynext = ref[0:T].reshape(L, W).copy()     # reference values of the next tile
     y = np.zeros((L, W), np.uint64)
+    G = min(gc, H)                            # columns of the deferred last group
     a = np.zeros((L, W), np.uint64)
     b = np.zeros((L, W), np.uint64)
     dprev = np.full((K, L), INF, np.uint64)
@@ -53,6 +60,18 @@ def skew_model(x, yref, W, K=1):
         return [(bxx[k].copy(), bxy[k].copy()) for k in ks]
 
     st = {"next": None}
+
+    def clear(row, l, c0, c1):
+        # gamma(0, .) = 0 entered as the kernel does: the odd columns cleared
+        row[l, [c for c in range(c0, c1) if c % 2 == 1]] = 0
+
+    def enter(l, h, row, c1):
+        # sub-lane (l, h) enters its next tile: the finished row out, the new
+        # reference values in, the previous row of columns [h H, c1) cleared
+        cols = slice(h * H, (h + 1) * H)
+        stage[l, cols] = row[l, cols]
+        y[l, cols] = ynext[l, cols]
+        clear(row, l, h * H, c1)
 
     def step(r, up, nw, write_b, wrap, sw):
         ent = st["next"]  # read one step earlier
@@ -68,16 +87,15 @@ def skew_model(x, yref, W, K=1):
             lefts.append(lf)
         if sw and r < S:  # sub-lane r enters its next tile
             l, h = r // K, r % K
-            cols = slice(h * H, (h + 1) * H)
-            nv = stage[l, cols].copy()
-            stage[l, cols] = up[l, cols]
-            y[l, cols] = nv
-            # the previous row of a tile is gamma(0, .) = 0; like the kernel,
-            # clear only the diagonal and every other column (offsets 1, 3,
-            # ...) and leave the finished row's values in the others: each
-            # cell's minimum still has a zero operand
-            up[l, h * H + 1:(h + 1) * H:2] = 0
-            dprev[h][l] = 0
+            if r == 0 or not pipe:  # all of the switch, here
+                enter(l, h, up, (h + 1) * H)
+                if clear_diag:
+                    dprev[h][l] = 0
+            elif defer_last:
+                # issued during the previous step, but for the last group's
+                # previous row, cleared now that the right neighbours have
+                # read their edge from it
+                clear(up, l, (h + 1) * H - G, (h + 1) * H)
         for h in range(K):
             ex = ent[h][0]
             diag, lf = dprev[h].copy(), lefts[h].copy()
@@ -90,6 +108,14 @@ def skew_model(x, yref, W, K=1):
             dprev[h] = lefts[h]
         if write_b:
             bxy[r + (M if wrap else 0)] = nw[63, W - 1]
+        if sw and pipe and r + 1 < S:
+            # sub-lane r + 1 has computed its last row on the old tile; its
+            # switch is issued in this step, but for the last group's previous
+            # row (its right neighbours still read their edge there)
+            l, h = (r + 1) // K, (r + 1) % K
+            enter(l, h, nw, (h + 1) * H - (G if defer_last else 0))
+            if clear_diag:
+                dprev[h][l] = 0
 
     p = 0
     while True:
@@ -103,8 +129,8 @@ def skew_model(x, yref, W, K=1):
                     j = (p - 1) * T + l * W + w
                     if j < N and stage[l, w] < best[l]:
                         best[l], bestj[l] = stage[l, w], j
-        if p + 1 < ntiles:
-            stage[:] = ref[(p + 1) * T:(p + 2) * T].reshape(L, W)
+        if p + 1 < ntiles:  # every lane has entered tile p: fetch tile p + 1
+            ynext[:] = ref[(p + 1) * T:(p + 2) * T].reshape(L, W)
         if p == ntiles:
             break
         r = S
@@ -127,11 +153,20 @@ def skew_model(x, yref, W, K=1):
     (4, 2, 129, 1, -2, 2), (4, 2, 129, 300, -3, 3), (8, 2, 130, 1100, -30000, 30000),
     (16, 2, 200, 2049, -5, 5), (8, 2, 257, 600, -40, 40), (8, 4, 257, 900, -3, 3),
 ])
-def test_skew_schedule_matches_oracle(W, K, M, N, lo, hi):
+@pytest.mark.parametrize("pipe", [True, False])
+def test_skew_schedule_matches_oracle(W, K, M, N, lo, hi, pipe):
     rng = np.random.default_rng(W * 1000 + K * 100 + M + N)
     x = rng.integers(lo, hi, size=M).astype(np.int16)
     y = rng.integers(lo, hi, size=N).astype(np.int16)
-    assert skew_model(x, y, W, K) == oracle.sdtw_i64(x, y)
+    assert skew_model(x, y, W, K, pipe=pipe) == oracle.sdtw_i64(x, y)
+
+
+def test_switch_groups_of_eight():
+    rng = np.random.default_rng(8)
+    for W, K, M, N in ((16, 1, 70, 1025), (8, 1, 66, 513), (16, 2, 200, 900)):
+        x = rng.integers(-40, 40, size=M).astype(np.int16)
+        y = rng.integers(-40, 40, size=N).astype(np.int16)
+        assert skew_model(x, y, W, K, gc=8) == oracle.sdtw_i64(x, y)
 
 
 @pytest.mark.parametrize("K", [1, 2, 4])
@@ -145,3 +180,32 @@ def test_prefetch_needs_one_more_row_than_sublanes(K):
     for M in (S, S + 1, S + 7, 3 * S):
         collide = any((r + 1) % M == (r - (S - 1)) % M for r in range(M))
         assert collide == (M == S)
+
+
+def test_clearing_without_the_diagonal_is_caught():
+    # a planted schedule mistake: every other column cleared but the
+    # diagonal left as it was, so a strip's first cell can miss its zero
+    rng = np.random.default_rng(78)
+    bad = 0
+    for _ in range(4):
+        x = rng.integers(-30, 30, size=70).astype(np.int16)
+        y = rng.integers(-30, 30, size=600).astype(np.int16)
+        want = oracle.sdtw_i64(x, y)
+        assert skew_model(x, y, 4, 1) == want
+        bad += skew_model(x, y, 4, 1, clear_diag=False) != want
+    assert bad > 0
+
+
+def test_reloading_the_edge_columns_early_is_caught():
+    # a planted schedule mistake: the whole previous row reloaded during the
+    # step before the switch, so the right neighbour reads a zero as its
+    # edge instead of the finished row's last value
+    rng = np.random.default_rng(77)
+    bad = 0
+    for _ in range(4):
+        x = rng.integers(-30, 30, size=70).astype(np.int16)
+        y = rng.integers(-30, 30, size=600).astype(np.int16)
+        want = oracle.sdtw_i64(x, y)
+        assert skew_model(x, y, 4, 1) == want
+        bad += skew_model(x, y, 4, 1, defer_last=False) != want
+    assert bad > 0
