@@ -48,7 +48,11 @@ if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 8:
     os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
 CUS, SIMDS_PER_CU, CLOCK_GHZ = 256, 4, 2.4
-# SIMD cycles per 64 cells (one wave-wide row of a strip column)
+# SIMD cycles per 64 cells (one wave-wide row of a strip column): int16
+# v_min3_u32 + v_sad_u32, float32 v_sub_f32 + v_min3_u32 + v_add_f32 |.|.
+# Full-rate 32-bit instructions take 4 cycles per 64-lane wave, float32
+# add/subtract 2 (the measured rates: profiles/valu_issue_and_lds_rates_gfx950.md,
+# `python bench_experiments.py issue`).
 SIMD_CYCLES_PER_64_CELLS = {"i16": 4 + 4, "f32": 2 + 4 + 2}
 
 

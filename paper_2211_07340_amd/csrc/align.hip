@@ -202,10 +202,7 @@ __device__ __forceinline__ void chains_row(const uint32_t (&x)[K], const uint32_
                                            const uint32_t (&up)[W], uint32_t (&nw)[W],
                                            const uint32_t (&dprev)[K],
                                            const uint32_t (&left)[K], After&& after = After{}) {
-#ifndef SDTW_K1_PLAIN
-#define SDTW_K1_PLAIN 1
-#endif
-  if constexpr (K == 1 && SDTW_K1_PLAIN) {
+  if constexpr (K == 1) {
     // one chain: four columns per asm statement (the compiler separates
     // consecutive asm statements with a wait state)
     static_for<0, H / 4>([&](auto bc) {
@@ -332,11 +329,9 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
   // Pipelined switches (issued between the previous step's cells) except
   // with one band and no resident row, where a switch loads nothing from LDS.
   constexpr bool kPipe = !kZeroRow;
-#ifndef SDTW_SW_GROUP
-#define SDTW_SW_GROUP 4
-#endif
-  // columns per group of a pipelined switch's LDS operations
-  constexpr int kGc = SDTW_SW_GROUP < H ? SDTW_SW_GROUP : H;
+  // columns per group of a pipelined switch's operations (each group is one
+  // masked block: fewer, larger groups cost fewer exec-mask changes)
+  constexpr int kGc = 8 < H ? 8 : H;
   static_assert(H % kGc == 0 && kGc % 4 == 0, "switch groups are whole uint4 groups");
   static_assert(W % K == 0 && H % 4 == 0, "sub-strips are whole uint4 groups");
   extern __shared__ __align__(16) uint32_t smem[];
@@ -551,7 +546,7 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
       for (int h = 1; h < K; ++h) xs[h] = nxtx[h];
       xs[0] = e0.x;
       uint32_t left[K];
-      if constexpr (K == 1 && (NX < 0 || SDTW_K1_PLAIN))
+      if constexpr (K == 1)
         left[0] = from_left_lane(up[W - 1], e0.y);
       else
         left[0] = asm_from_left_lane(up[W - 1], e0.y);

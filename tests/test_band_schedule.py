@@ -44,7 +44,7 @@ L = 64
 
 
 class Band:
-    def __init__(self, g, P, x_rows, ref, W, K, N, shared, acc=None, last=False, gc=4):
+    def __init__(self, g, P, x_rows, ref, W, K, N, shared, acc=None, last=False, gc=8):
         self.g, self.P, self.W, self.K, self.N = g, P, W, K, N
         self.T = L * W
         self.H = W // K

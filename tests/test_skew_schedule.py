@@ -13,7 +13,8 @@ of columns, done after its outgoing edge has been read by its right
 neighbour (the kernel with bands or a resident row) -- the query/boundary
 LDS entries at K(63 - l) + r + (K - 1 - h) read one step ahead, the boundary
 writes of the last sub-lane (at r, or r + M while its row wraps), the
-reference values of the next tile held apart from the staged last rows, the
+reference values of the next tile held apart from the staged last rows
+(switch groups of 8 columns, as the kernel's), the
 per-tile fold of the staged last rows and the lexicographic final
 reduction.  At a tile switch the previous row gamma(0, .) = 0 is entered as
 the kernel does it: every other column cleared and the diagonal set to 0,
@@ -29,7 +30,7 @@ import oracle
 INF = 0xFFFFFFFF
 
 
-def skew_model(x, yref, W, K=1, defer_last=True, pipe=True, gc=4, clear_diag=True):
+def skew_model(x, yref, W, K=1, defer_last=True, pipe=True, gc=8, clear_diag=True):
     L = 64
     T = L * W
     H = W // K
@@ -161,12 +162,15 @@ def test_skew_schedule_matches_oracle(W, K, M, N, lo, hi, pipe):
     assert skew_model(x, y, W, K, pipe=pipe) == oracle.sdtw_i64(x, y)
 
 
-def test_switch_groups_of_eight():
-    rng = np.random.default_rng(8)
-    for W, K, M, N in ((16, 1, 70, 1025), (8, 1, 66, 513), (16, 2, 200, 900)):
+@pytest.mark.parametrize("gc", [4, 16])
+def test_other_switch_group_sizes(gc):
+    # the kernel issues a switch in groups of 8 columns; the schedule holds
+    # for other group sizes too
+    rng = np.random.default_rng(gc)
+    for W, K, M, N in ((16, 1, 70, 1025), (8, 1, 66, 513), (16, 2, 200, 900), (32, 1, 70, 2100)):
         x = rng.integers(-40, 40, size=M).astype(np.int16)
         y = rng.integers(-40, 40, size=N).astype(np.int16)
-        assert skew_model(x, y, W, K, gc=8) == oracle.sdtw_i64(x, y)
+        assert skew_model(x, y, W, K, gc=gc) == oracle.sdtw_i64(x, y)
 
 
 @pytest.mark.parametrize("K", [1, 2, 4])
