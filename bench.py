@@ -58,18 +58,24 @@ SIMD_CYCLES_PER_64_CELLS = {"i16": 4 + 4, "f32": 2 + 4 + 2}
 
 # HBM bytes per launch of the alignment kernel, from the rocprofv3 FETCH_SIZE
 # and WRITE_SIZE passes summarised in
-# profiles/counters_k_align_skew_i16_w32_k2_b1_4096x250.md (two chains, the
-# shape the autotuner picks) and profiles/counters_k_align_skew_i16_w32_b1_4096x250.md
-# (one chain), each scaled by what the counter reads for a plain copy of known
-# size, keyed by workload and launch shape, valid only while the kernel source
-# is the one measured (sha256 of csrc/align.hip); otherwise `traffic` is null.
-_ALIGN_SHA = "de77b5ff54f947d73d7ee3a8723caf259547a2a29367f97705044ccd4e6a812c"
+# profiles/counters_k_align_skew_i16_w32_b2_1024xU250-500_vs_9999990.md (mean of
+# the timed dispatches), each scaled by what the counter reads for a plain
+# device copy of known size (factors 1.9998 and 1.0000), keyed by workload and
+# launch shape, valid only while the kernel source is the one measured (sha256
+# of csrc/align.hip); otherwise `traffic` is null.
+_ALIGN_SHA = "e0b0817c3dd00b57f770bfbbf74ce9c13655471216cf905d7aa64bd226073dfc"
 MEASURED_TRAFFIC = {
-    ("4096 reads M=250 vs 29,903-base genome", "i16", 32, 2, 1): {
-        "fetch_bytes": 4735866, "write_bytes": 342379, "align_hip_sha256": _ALIGN_SHA},
-    ("4096 reads M=250 vs 29,903-base genome", "i16", 32, 1, 1): {
-        "fetch_bytes": 4737209, "write_bytes": 357504, "align_hip_sha256": _ALIGN_SHA},
+    ("1024 reads M~U[250,500] vs 5,000,000-base genome", "i16", 32, 1, 2): {
+        "fetch_bytes": 20346158444, "write_bytes": 132301, "align_hip_sha256": _ALIGN_SHA},
 }
+
+
+_T0 = time.perf_counter()
+
+
+def progress(msg: str):
+    """One line on stderr per stage (the JSON line alone goes to stdout)."""
+    print(f"bench [{time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def measured_traffic(workload: str, dtype: str, cfg: dict):
@@ -136,6 +142,7 @@ def main():
     nq = reads.nq
     dt = sd.I16 if args.dtype == "i16" else sd.F32
 
+    progress(f"{w.name}: preparing the reference")
     # one-time reference preparation on the device (section 4.1)
     g = torch.from_numpy(w.genome).to(dev)
     tab = torch.from_numpy(w.table).to(dev)
@@ -171,6 +178,7 @@ def main():
         if ev is not None:
             ev[1].record(stream)
 
+    progress(f"launch shape {plan.config}; {args.warmup} warm-up and {args.steps} timed steps")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -214,6 +222,7 @@ def main():
                      "traffic": measured_traffic(w.name, args.dtype, pcfg)},
     }
 
+    progress(f"{kern_ms:.2f} ms per alignment launch ({kern_tcups / peak:.3f} of the roof)")
     if not args.no_extras:
         out["extras"] = extras(sd, torch, dev, w, reads, zref, cref, args, stream)
         # about two seconds of replays each
@@ -223,12 +232,15 @@ def main():
                                                  reps)
 
     if args.serve_seconds > 0:
+        progress("serving")
         out["serving"] = serving(torch, dev, args.serve_seconds, args.serve_warmup,
                                  args.serve_channels, args.serve_recompute_seconds,
                                  large=not args.serve_small_only)
 
     if not args.no_cpu_baseline:
+        progress("CPU baseline (the oracle)")
         out["cpu_baseline"] = cpu_baseline(w, reads, args)
+    progress("done")
     print(json.dumps(out), flush=True)
 
 
@@ -377,6 +389,7 @@ def extras(sd, torch, dev, w, reads, zref, cref, args, stream):
     accuracy-against-scale sweep."""
     res = {}
     other = "f32" if args.dtype == "i16" else "i16"
+    progress(f"extras: {other}")
     dt = sd.F32 if other == "f32" else sd.I16
     ref = sd.Reference(zref if dt == sd.F32 else cref)
     raw = torch.from_numpy(reads.values).to(dev)
@@ -394,8 +407,12 @@ def extras(sd, torch, dev, w, reads, zref, cref, args, stream):
                   **plan.config}
     plan.close()
     # the other batch workloads, both number formats
-    res["workloads"] = [workload_leg(sd, torch, dev, c, stream) for c in (1, 2, 3)
-                        if c != args.config]
+    res["workloads"] = []
+    for c in (1, 2, 3):
+        if c != args.config:
+            progress(f"extras: workload {c}")
+            res["workloads"].append(workload_leg(sd, torch, dev, c, stream))
+    progress("extras: one read per launch, whole device, event detection, scales")
     # one read per launch with the single-wave kernel, on the main dtype
     dt0 = sd.I16 if args.dtype == "i16" else sd.F32
     ref0 = sd.Reference(cref if dt0 == sd.I16 else zref)

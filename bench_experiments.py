@@ -46,6 +46,9 @@ issue    VALU issue rates on gfx950 (libsdtw_probe.so): cycles per 64-lane
          v_add_f32 |a| and v_add_u32, by independent chains per wave (1, 2,
          4) and waves per SIMD (1-8), at the nominal 2.4 GHz clock: the basis
          of the cycles per cell of the roof in bench.py.
+placement Where the hardware places the batch alignment's workgroups and
+         waves (XCC, shader engine, CU, SIMD) against the order in which
+         they take their first read.
 lds      LDS cost of the tile switch's operations (libsdtw_probe.so): blocks
          of 8 ds_read_b128 + 8 ds_write_b128 per wave with 1, 16 or 64 lanes
          active, cycles per LDS instruction per CU by waves per SIMD.
@@ -54,7 +57,7 @@ best_two The runner-up search alone (sdtw_stream_best_two) over 1 to 256
          device time and the rate at which it reads the rows (4 bytes per
          column per row, the bound being HBM at 8 TB/s).
 
-Usage: python bench_experiments.py latency|scale|serving|serving_raw|decision|best_two|wide|events|issue|lds
+Usage: python bench_experiments.py latency|scale|serving|serving_raw|decision|best_two|wide|events|issue|lds|placement
                                    [--max-genome BASES] [--genome BASES] [--cols C]
                                    [--reps R]
 """
@@ -452,15 +455,63 @@ def lds(args):
                                   ms * 1e-3 * clock_ghz * 1e9 / iters, 1)}), flush=True)
 
 
+def placement(args):
+    """Where the hardware places the batch alignment's workgroups
+    (libsdtw_probe.so): the 2-band launch of workload 3 (1,024 workgroups of
+    128 threads with the same dynamic LDS) and the 1-band one (1,024 of 64),
+    each workgroup's first ticket (the persistent kernel's first read) and
+    the XCC, shader engine, CU and SIMD of each of its waves."""
+    import collections
+    import ctypes as C
+
+    import torch
+    from paper_2211_07340_amd import build as hipbuild
+    lib = C.CDLL(hipbuild.PROBE_LIB)
+    lib.sdtw_probe_placement.argtypes = [C.c_int] * 4 + [C.c_void_p] * 2
+    lib.sdtw_probe_placement.restype = C.c_int
+    st = torch.cuda.current_stream()
+    for blocks, threads, lds in ((1024, 128, 37968), (1024, 64, 40960)):
+        wpb = threads // 64
+        o32 = torch.zeros(4 + 4 * blocks * wpb, dtype=torch.int32, device="cuda")
+        rc = lib.sdtw_probe_placement(blocks, threads, lds, 2000, C.c_void_p(o32.data_ptr()),
+                                      C.c_void_p(st.cuda_stream))
+        assert rc == 0, rc
+        torch.cuda.synchronize()
+        rec = o32[4:].view(blocks, wpb, 4).cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+        cus, simds = collections.Counter(), collections.Counter()
+        rows = []
+        for b in range(blocks):
+            locs = []
+            for wv in range(wpb):
+                t, hw, xcc = int(rec[b, wv, 0]), int(rec[b, wv, 1]), int(rec[b, wv, 2])
+                cu = (xcc & 0xF, (hw >> 13) & 7, (hw >> 12) & 1, (hw >> 8) & 15)
+                simd = cu + ((hw >> 4) & 3,)
+                cus[cu] += 1
+                simds[simd] += 1
+                locs.append(list(simd))
+            rows.append({"block": b, "ticket": int(rec[b, 0, 0]), "waves": locs})
+        print(json.dumps({"experiment": "placement", "blocks": blocks, "threads": threads,
+                          "lds_bytes": lds, "cus_used": len(cus),
+                          "waves_per_cu": sorted(collections.Counter(cus.values()).items()),
+                          "simds_used": len(simds),
+                          "waves_per_simd": sorted(collections.Counter(simds.values()).items()),
+                          "same_simd_workgroups": sum(
+                              1 for r in rows if len({tuple(w) for w in r["waves"]}) < wpb),
+                          "first_blocks": rows[:12]}), flush=True)
+        with open(os.path.join(args.out_dir, f"placement_{threads}.json"), "w") as f:
+            json.dump(rows, f)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("experiment",
                     choices=["latency", "scale", "serving", "serving_raw", "decision",
-                             "best_two", "wide", "events", "issue", "lds"])
+                             "best_two", "wide", "events", "issue", "lds", "placement"])
     ap.add_argument("--max-genome", type=int, default=10_000_000)
     ap.add_argument("--genome", type=int, default=5_000_000, help="wide: genome bases")
     ap.add_argument("--cols", type=int, default=0, help="wide: columns per thread (0: auto)")
     ap.add_argument("--reps", type=int, default=20, help="wide: timed calls")
+    ap.add_argument("--out-dir", default="gpurun_out", help="placement: where the records go")
     ap.add_argument("--off", default="noise,genomic",
                     help="decision: off-target read kinds to run, in order")
     args = ap.parse_args()
@@ -468,7 +519,7 @@ def main():
     {"latency": latency, "scale": scale, "serving": serving,
      "decision": decision, "best_two": best_two, "wide": wide,
      "events": events, "serving_raw": serving_raw, "issue": issue,
-     "lds": lds}[args.experiment](args)
+     "lds": lds, "placement": placement}[args.experiment](args)
     print(json.dumps({"done": args.experiment, "seconds": round(time.perf_counter() - t0, 1)}),
           flush=True)
 

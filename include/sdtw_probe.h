@@ -43,6 +43,19 @@ int sdtw_probe_issue(int kind, int chains, int waves_per_simd, int iters, void* 
  */
 int sdtw_probe_lds(int lanes, int waves_per_simd, int iters, void* out_dev, void* stream);
 
+/*
+ * Workgroup placement of a launch of `blocks` workgroups of `threads` threads
+ * (a multiple of 64, at most 1024) with `lds_bytes` of dynamic LDS: wave 0 of
+ * each workgroup takes a ticket from the counter out_dev[0] (zero it first),
+ * as the persistent alignment kernel takes its first read; every wave w of
+ * workgroup b writes (ticket, HW_ID, XCC_ID, 0) at out_dev[4 + 4 (b x
+ * waves + w)], then sleeps `spin` (<= 100,000) bounded rounds so that the
+ * workgroups are resident together.  out_dev: 4 + 4 x blocks x waves
+ * uint32.  Returns 0, 1 for bad arguments, 4 for a launch error.
+ */
+int sdtw_probe_placement(int blocks, int threads, int lds_bytes, int spin, void* out_dev,
+                         void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -166,7 +166,48 @@ __global__ __launch_bounds__(64) void k_lds(uint32_t* out, int iters, uint64_t m
   out[(size_t)blockIdx.x * 64 + lane] = acc.x ^ acc.y ^ acc.z ^ acc.w;
 }
 
+// Placement probe: where the hardware puts the workgroups of a launch shaped
+// like the batch alignment's (blocks of `threads` threads with `lds` bytes of
+// dynamic LDS).  Wave 0 of each workgroup takes a ticket from a counter as
+// the persistent kernel takes its first read; every wave records (ticket,
+// HW_ID, XCC_ID) and then sleeps for `spin` bounded rounds so that the
+// launch's workgroups are resident together.
+__global__ void k_placement(uint32_t* out, int spin) {
+  extern __shared__ uint32_t dyn[];
+  __shared__ uint32_t s_ticket;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = threadIdx.x >> 6;
+  const uint32_t wpb = blockDim.x >> 6;
+  if (wave == 0) {
+    uint32_t t = atomicAdd(out, lane == 0 ? 1u : 0u);
+    t = __builtin_amdgcn_readfirstlane(t);
+    if (lane == 0) s_ticket = t;
+  }
+  __syncthreads();
+  uint32_t hw, xcc;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_HW_ID)" : "=s"(hw));
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+  if (lane == 0) {
+    uint32_t* rec = out + 4 + 4 * ((size_t)blockIdx.x * wpb + wave);
+    rec[0] = s_ticket;
+    rec[1] = hw;
+    rec[2] = xcc;
+    rec[3] = dyn[0] & 0u;  // the dynamic LDS is only reserved
+  }
+  for (int i = 0; i < spin; ++i) __builtin_amdgcn_s_sleep(8);
+}
+
 }  // namespace
+
+extern "C" int sdtw_probe_placement(int blocks, int threads, int lds_bytes, int spin,
+                                    void* out_dev, void* stream) {
+  if (blocks < 1 || threads < 64 || threads > 1024 || threads % 64 || lds_bytes < 0 ||
+      lds_bytes > 160 * 1024 || spin < 0 || spin > 100000 || !out_dev)
+    return 1;
+  hipLaunchKernelGGL(k_placement, dim3((unsigned)blocks), dim3((unsigned)threads),
+                     (size_t)lds_bytes, (hipStream_t)stream, (uint32_t*)out_dev, spin);
+  return hipGetLastError() == hipSuccess ? 0 : 4;
+}
 
 extern "C" int sdtw_probe_lds(int lanes, int waves_per_simd, int iters, void* out_dev,
                               void* stream) {
