@@ -458,46 +458,53 @@ def lds(args):
 def placement(args):
     """Where the hardware places the batch alignment's workgroups
     (libsdtw_probe.so): the 2-band launch of workload 3 (1,024 workgroups of
-    128 threads with the same dynamic LDS) and the 1-band one (1,024 of 64),
-    each workgroup's first ticket (the persistent kernel's first read) and
-    the XCC, shader engine, CU and SIMD of each of its waves."""
+    128 threads, 230 vector registers per wave and the same dynamic LDS) and
+    the 1-band one (1,024 of 64 threads, 150 registers, the LDS share that
+    spreads four over every compute unit), each workgroup's first ticket (the
+    persistent kernel's first read), the XCC, shader engine, CU and SIMD of
+    each of its waves, and whether every wave was resident at once."""
     import collections
     import ctypes as C
 
     import torch
     from paper_2211_07340_amd import build as hipbuild
     lib = C.CDLL(hipbuild.PROBE_LIB)
-    lib.sdtw_probe_placement.argtypes = [C.c_int] * 4 + [C.c_void_p] * 2
+    lib.sdtw_probe_placement.argtypes = [C.c_int] * 5 + [C.c_void_p] * 2
     lib.sdtw_probe_placement.restype = C.c_int
     st = torch.cuda.current_stream()
-    for blocks, threads, lds in ((1024, 128, 37968), (1024, 64, 40960)):
+    for blocks, threads, lds, vgprs in ((1024, 128, 37968, 230), (1024, 64, 39936, 150)):
         wpb = threads // 64
-        o32 = torch.zeros(4 + 4 * blocks * wpb, dtype=torch.int32, device="cuda")
-        rc = lib.sdtw_probe_placement(blocks, threads, lds, 2000, C.c_void_p(o32.data_ptr()),
-                                      C.c_void_p(st.cuda_stream))
+        o32 = torch.zeros(8 + 8 * blocks * wpb, dtype=torch.int32, device="cuda")
+        rc = lib.sdtw_probe_placement(blocks, threads, lds, vgprs, 2000,
+                                      C.c_void_p(o32.data_ptr()), C.c_void_p(st.cuda_stream))
         assert rc == 0, rc
         torch.cuda.synchronize()
-        rec = o32[4:].view(blocks, wpb, 4).cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+        rec = o32[8:].view(blocks, wpb, 8).cpu().numpy().astype(np.int64) & 0xFFFFFFFF
         cus, simds = collections.Counter(), collections.Counter()
         rows = []
         for b in range(blocks):
             locs = []
             for wv in range(wpb):
-                t, hw, xcc = int(rec[b, wv, 0]), int(rec[b, wv, 1]), int(rec[b, wv, 2])
+                hw, xcc = int(rec[b, wv, 1]), int(rec[b, wv, 2])
                 cu = (xcc & 0xF, (hw >> 13) & 7, (hw >> 12) & 1, (hw >> 8) & 15)
                 simd = cu + ((hw >> 4) & 3,)
                 cus[cu] += 1
                 simds[simd] += 1
                 locs.append(list(simd))
-            rows.append({"block": b, "ticket": int(rec[b, 0, 0]), "waves": locs})
+            rows.append({"block": b, "ticket": int(rec[b, 0, 0]), "waves": locs,
+                         "t0": int(rec[b, 0, 3]), "t1": int(rec[b, 0, 4])})
+        t0 = rec[:, :, 3].astype(np.int64)
+        t1 = rec[:, :, 4].astype(np.int64)
         print(json.dumps({"experiment": "placement", "blocks": blocks, "threads": threads,
-                          "lds_bytes": lds, "cus_used": len(cus),
+                          "lds_bytes": lds, "vgprs": vgprs, "cus_used": len(cus),
                           "waves_per_cu": sorted(collections.Counter(cus.values()).items()),
                           "simds_used": len(simds),
                           "waves_per_simd": sorted(collections.Counter(simds.values()).items()),
                           "same_simd_workgroups": sum(
                               1 for r in rows if len({tuple(w) for w in r["waves"]}) < wpb),
-                          "first_blocks": rows[:12]}), flush=True)
+                          "all_resident_together": bool(t0.max() < t1.min()),
+                          "start_spread_us": float(t0.max() - t0.min()) / 100.0,
+                          "first_blocks": rows[:8]}), flush=True)
         with open(os.path.join(args.out_dir, f"placement_{threads}.json"), "w") as f:
             json.dump(rows, f)
 

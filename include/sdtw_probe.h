@@ -45,16 +45,19 @@ int sdtw_probe_lds(int lanes, int waves_per_simd, int iters, void* out_dev, void
 
 /*
  * Workgroup placement of a launch of `blocks` workgroups of `threads` threads
- * (a multiple of 64, at most 1024) with `lds_bytes` of dynamic LDS: wave 0 of
- * each workgroup takes a ticket from the counter out_dev[0] (zero it first),
- * as the persistent alignment kernel takes its first read; every wave w of
- * workgroup b writes (ticket, HW_ID, XCC_ID, 0) at out_dev[4 + 4 (b x
- * waves + w)], then sleeps `spin` (<= 100,000) bounded rounds so that the
- * workgroups are resident together.  out_dev: 4 + 4 x blocks x waves
- * uint32.  Returns 0, 1 for bad arguments, 4 for a launch error.
+ * (a multiple of 64, at most 1024) with `lds_bytes` of dynamic LDS, each wave
+ * holding `vgprs` vector registers (0, 150 or 230: those of the alignment
+ * kernels whose placement it stands for): wave 0 of each workgroup takes a
+ * ticket from the counter out_dev[0] (zero it first), as the persistent
+ * alignment kernel takes its first read; every wave w of workgroup b writes
+ * (ticket, HW_ID, XCC_ID, start and end of its residency in s_memrealtime
+ * ticks, 0, 0, 0) at out_dev[8 + 8 (b x waves + w)], sleeping `spin`
+ * (<= 100,000) bounded rounds in between so that the workgroups are resident
+ * together.  out_dev: 8 + 8 x blocks x waves uint32.  Returns 0, 1 for bad
+ * arguments, 4 for a launch error.
  */
-int sdtw_probe_placement(int blocks, int threads, int lds_bytes, int spin, void* out_dev,
-                         void* stream);
+int sdtw_probe_placement(int blocks, int threads, int lds_bytes, int vgprs, int spin,
+                         void* out_dev, void* stream);
 
 #ifdef __cplusplus
 }

@@ -358,23 +358,72 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
   const int32_t N = (int32_t)args.n;
   const int32_t ntiles = (N + T - 1) / T;
 
+  // Batch launches: where this wave runs.  A SIMD slot from the hardware ids
+  // (XCC, shader engine, shader array, CU, SIMD) and the wave's place among
+  // the launch's waves on that SIMD (j).  With two waves on a SIMD each
+  // publishes the work its read has left once a period and takes the higher
+  // issue priority while it has more left than the other: the SIMD then
+  // finishes both together instead of running the longer one alone at the
+  // end (one wave issues slower than two).  When a launch of two-wave
+  // workgroups has no more reads than workgroups (each takes one, so no later
+  // pull evens the load out), half the workgroups take theirs from the back
+  // of the longest-first list: the dispatcher places the four workgroups of
+  // a CU with their two waves on SIMDs (0, 2), (1, 3), (2, 1) and (3, 0), so
+  // those whose first wave runs on SIMD 2 or 3 taking short reads pairs a
+  // short read with a long one on every SIMD.  (Placement decides nothing
+  // but speed: any placement gets every read exactly once.)
+  [[maybe_unused]] uint32_t* rem_mine = nullptr;
+  [[maybe_unused]] const uint32_t* rem_other = nullptr;
+  [[maybe_unused]] uint32_t rem_seen = 0u;
+  [[maybe_unused]] bool back = false;
+  if constexpr (!STREAM) {
+    uint32_t hw, xcc;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_HW_ID)" : "=s"(hw));
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+    const uint32_t simd = (hw >> 4) & 3u;
+    const uint32_t slot = (((((xcc & 7u) << 3 | ((hw >> 13) & 7u)) << 1 | ((hw >> 12) & 1u))
+                            << 4 | ((hw >> 8) & 15u)) << 2) | simd;
+    uint32_t* const cnt = args.sched + kSchedHead;
+    uint32_t j = atomicAdd(cnt + slot, lane == 0 ? 1u : 0u);
+    j = __builtin_amdgcn_readfirstlane(j);
+    if (j < 2) {
+      rem_mine = cnt + kSchedSimds + 2 * slot + j;
+      rem_other = cnt + kSchedSimds + 2 * slot + (1 - j);
+    }
+    if (args.nwork <= (int32_t)gridDim.x) back = P > 1 && simd >= 2;
+  }
+  // Work pull without a divergent branch around the atomic: every lane of
+  // the pulling wave takes part and only lane 0 adds, so lane 0's return
+  // value is the item whatever order the lanes are serviced in.  (Guarding
+  // the atomic with `if (lane == 0)` lets the loop structurizer split the
+  // wave around the readfirstlane, leaving lanes 1..63 a stale item.)  A
+  // batch pull takes the next item from the front or the back of the list
+  // in one 64-bit add: the list is exhausted once front + back reaches its
+  // length, so every item is taken exactly once.
+  auto pull = [&]() -> int32_t {
+    if constexpr (STREAM) {
+      return __builtin_amdgcn_readfirstlane(atomicAdd(args.counter, lane == 0 ? 1 : 0));
+    } else {
+      const unsigned long long inc = back ? 1ull << 32 : 1ull;
+      const unsigned long long old =
+          atomicAdd((unsigned long long*)args.sched, lane == 0 ? inc : 0ull);
+      const uint32_t f = __builtin_amdgcn_readfirstlane((uint32_t)old);
+      const uint32_t b = __builtin_amdgcn_readfirstlane((uint32_t)(old >> 32));
+      if (f + b >= (uint32_t)args.nwork) return args.nwork;
+      return back ? args.nwork - 1 - (int32_t)b : (int32_t)f;
+    }
+  };
+
   for (;;) {
-    // Work pull without a divergent branch around the atomic: every lane of
-    // the pulling wave takes part and only lane 0 adds 1, so lane 0's return
-    // value is the item whatever order the lanes are serviced in.  (Guarding
-    // the atomic with `if (lane == 0)` lets the loop structurizer split the
-    // wave around the readfirstlane, leaving lanes 1..63 a stale item.)
     int32_t item;
     if constexpr (P == 1) {
-      item = atomicAdd(args.counter, lane == 0 ? 1 : 0);
-      item = __builtin_amdgcn_readfirstlane(item);
+      item = pull();
       if (item >= args.nwork) break;
       __syncthreads();  // previous read's LDS use is complete
     } else {
       __syncthreads();  // every wave is done with the previous item and its LDS
       if (wave == 0) {
-        int32_t it = atomicAdd(args.counter, lane == 0 ? 1 : 0);
-        it = __builtin_amdgcn_readfirstlane(it);
+        const int32_t it = pull();
         if (lane == 0) s_item = it;
       }
       __syncthreads();
@@ -751,6 +800,21 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
           }
           flush();
         }
+        if constexpr (!STREAM) {
+          if (rem_mine) {
+            const uint32_t rem =
+                (uint32_t)std::min<int64_t>((int64_t)(ntiles - p) * Mb, 0xFFFFFFFFll);
+            if (rem > rem_seen)
+              __builtin_amdgcn_s_setprio(1);
+            else
+              __builtin_amdgcn_s_setprio(0);
+            if (lane == 0) __hip_atomic_store(rem_mine, rem, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+            // read now, used at the end of the next period
+            rem_seen = __builtin_amdgcn_readfirstlane(
+                __hip_atomic_load(rem_other, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+          }
+        }
       }
       if constexpr (P > 1) __syncthreads();
     }
@@ -892,13 +956,21 @@ __global__ void k_reset_counter(int32_t* c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
 }
 
+__global__ void k_reset_sched(uint32_t* s) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kSchedWords; i += gridDim.x * blockDim.x)
+    s[i] = 0u;
+}
+
 template <class F, int W, int K, int P, bool STREAM>
 hipError_t launch_skew_t(int blocks, const AlignArgs& a, hipStream_t st) {
   const size_t lds = std::max(skew_lds_bytes(W, K, P, a.max_band), (size_t)a.lds_bytes);
   hipError_t e = hipFuncSetAttribute((const void*)k_align_skew<F, W, K, P, STREAM>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, a.counter);
+  if (STREAM)
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, a.counter);
+  else
+    hipLaunchKernelGGL(k_reset_sched, dim3(kSchedWords / 1024), dim3(256), 0, st, a.sched);
   hipLaunchKernelGGL((k_align_skew<F, W, K, P, STREAM>), dim3(blocks), dim3(64 * P), lds, st, a);
   return hipGetLastError();
 }

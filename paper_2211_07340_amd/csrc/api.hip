@@ -56,7 +56,7 @@ struct sdtw_plan_s {
   std::vector<int32_t> sorted_m;  // read lengths, longest first (order_dev's order)
   int64_t* offs_dev;              // [nq+1]
   int32_t* order_dev;             // [nq]: read indices, longest first
-  int32_t* counter_dev;           // [1]
+  uint32_t* sched_dev;            // [kSchedWords]: pull and placement state of a launch
   int strip;                      // columns per lane
   int chains;                     // most chains per lane (K) the long reads use
   int bands;                      // waves per read (row bands) of the skew kernel
@@ -562,7 +562,7 @@ int sdtw_plan_create(const int64_t* offsets_host, int32_t nq, int dtype, sdtw_pl
                      "sdtw_plan_create: alloc");
   if (!rc) rc = check_hip(hipMalloc((void**)&p->order_dev, sizeof(int32_t) * (size_t)nq),
                           "sdtw_plan_create: alloc");
-  if (!rc) rc = check_hip(hipMalloc((void**)&p->counter_dev, sizeof(int32_t)),
+  if (!rc) rc = check_hip(hipMalloc((void**)&p->sched_dev, sizeof(uint32_t) * kSchedWords),
                           "sdtw_plan_create: alloc");
   if (!rc) rc = check_hip(hipMemcpy(p->offs_dev, offsets_host, sizeof(int64_t) * (size_t)(nq + 1),
                                     hipMemcpyHostToDevice), "sdtw_plan_create: copy");
@@ -571,7 +571,7 @@ int sdtw_plan_create(const int64_t* offsets_host, int32_t nq, int dtype, sdtw_pl
   if (rc) {
     (void)hipFree(p->offs_dev);
     (void)hipFree(p->order_dev);
-    (void)hipFree(p->counter_dev);
+    (void)hipFree(p->sched_dev);
     delete p;
     return rc;
   }
@@ -641,7 +641,7 @@ int sdtw_plan_destroy(sdtw_plan plan) {
   SDTW_REQUIRE(plan, "sdtw_plan_destroy: null plan");
   hipError_t e1 = hipFree(plan->offs_dev);
   hipError_t e2 = hipFree(plan->order_dev);
-  hipError_t e3 = hipFree(plan->counter_dev);
+  hipError_t e3 = hipFree(plan->sched_dev);
   delete plan;
   if (e1 != hipSuccess) return check_hip(e1, "sdtw_plan_destroy");
   if (e2 != hipSuccess) return check_hip(e2, "sdtw_plan_destroy");
@@ -685,7 +685,7 @@ static int align_batch_impl(sdtw_ref ref, sdtw_plan plan, const void* q_dev, voi
   a.n = n;
   a.q = q_dev;
   a.offs = plan->offs_dev;
-  a.counter = plan->counter_dev;
+  a.sched = plan->sched_dev;
   a.cost = cost_dev;
   a.end = end_dev;
   for (const LaunchGroup& g : groups) {

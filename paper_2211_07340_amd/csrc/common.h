@@ -117,12 +117,23 @@ struct AlignArgs {
   int32_t lds_bytes;     // skew kernel: LDS to reserve per workgroup if more than it needs
                          // (caps the workgroups a compute unit takes, spreading a short
                          // work list over every compute unit)
-  int32_t* counter;      // persistent work counter (device, reset by launcher)
+  int32_t* counter;      // streaming launches: persistent work counter (reset by launcher)
+  uint32_t* sched;       // batch launches: kSchedWords words of pull and placement state
+                         // (device, reset by launcher)
   void* cost;            // int32[nq] or float[nq]
   int32_t* end;          // int32[nq]
   int32_t single_m;      // used when offs == nullptr: one read of this length
   const StreamItem* items;  // streaming launches: work item descriptors
 };
+// Pull and placement state of a batch launch of the continuous-skew kernel:
+// a 64-bit pull word (items taken from the front of the work list in the low
+// half, from the back in the high half), then per SIMD slot (XCC, shader
+// engine, shader array, CU, SIMD: 3 + 3 + 1 + 4 + 2 bits of the hardware ids)
+// the number of the launch's waves that run on it, then per slot the work
+// left to the first two of them.
+constexpr int kSchedHead = 4;  // words before the per-SIMD counts
+constexpr int kSchedSimds = 1 << 13;
+constexpr int kSchedWords = kSchedHead + 3 * kSchedSimds;
 // Continuous-skew persistent kernel: `bands` waves per workgroup (one read per
 // workgroup, cut into row bands), `chains` chains per lane; every read in the
 // list must have M >= skew_min_m(chains) and a.max_band must bound

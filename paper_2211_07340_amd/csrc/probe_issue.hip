@@ -168,10 +168,13 @@ __global__ __launch_bounds__(64) void k_lds(uint32_t* out, int iters, uint64_t m
 
 // Placement probe: where the hardware puts the workgroups of a launch shaped
 // like the batch alignment's (blocks of `threads` threads with `lds` bytes of
-// dynamic LDS).  Wave 0 of each workgroup takes a ticket from a counter as
-// the persistent kernel takes its first read; every wave records (ticket,
-// HW_ID, XCC_ID) and then sleeps for `spin` bounded rounds so that the
-// launch's workgroups are resident together.
+// dynamic LDS, waves holding VG vector registers, as the alignment kernels
+// of 150 and 230 registers do).  Wave 0 of each workgroup takes a ticket
+// from a counter as the persistent kernel takes its first read; every wave
+// records (ticket, HW_ID, XCC_ID, start and end of its residency in
+// s_memrealtime ticks) and sleeps `spin` bounded rounds in between so that
+// the launch's workgroups are resident together.
+template <int VG>
 __global__ void k_placement(uint32_t* out, int spin) {
   extern __shared__ uint32_t dyn[];
   __shared__ uint32_t s_ticket;
@@ -184,28 +187,47 @@ __global__ void k_placement(uint32_t* out, int spin) {
     if (lane == 0) s_ticket = t;
   }
   __syncthreads();
+  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
   uint32_t hw, xcc;
   asm volatile("s_getreg_b32 %0, hwreg(HW_REG_HW_ID)" : "=s"(hw));
   asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+  // hold VG vector registers, as the kernel whose placement this stands for
+  if constexpr (VG == 150)
+    asm volatile("; holds v149" ::: "v149");
+  else if constexpr (VG == 230)
+    asm volatile("; holds v229" ::: "v229");
+  for (int i = 0; i < spin; ++i) __builtin_amdgcn_s_sleep(8);
+  const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
   if (lane == 0) {
-    uint32_t* rec = out + 4 + 4 * ((size_t)blockIdx.x * wpb + wave);
+    uint32_t* rec = out + 8 + 8 * ((size_t)blockIdx.x * wpb + wave);
     rec[0] = s_ticket;
     rec[1] = hw;
     rec[2] = xcc;
-    rec[3] = dyn[0] & 0u;  // the dynamic LDS is only reserved
+    rec[3] = (uint32_t)t0;
+    rec[4] = (uint32_t)t1;
+    rec[5] = dyn[0] & 0u;  // the dynamic LDS is only reserved
+    rec[6] = 0u;
+    rec[7] = 0u;
   }
-  for (int i = 0; i < spin; ++i) __builtin_amdgcn_s_sleep(8);
 }
 
 }  // namespace
 
-extern "C" int sdtw_probe_placement(int blocks, int threads, int lds_bytes, int spin,
-                                    void* out_dev, void* stream) {
+extern "C" int sdtw_probe_placement(int blocks, int threads, int lds_bytes, int vgprs,
+                                    int spin, void* out_dev, void* stream) {
   if (blocks < 1 || threads < 64 || threads > 1024 || threads % 64 || lds_bytes < 0 ||
-      lds_bytes > 160 * 1024 || spin < 0 || spin > 100000 || !out_dev)
+      lds_bytes > 160 * 1024 || (vgprs != 0 && vgprs != 150 && vgprs != 230) || spin < 0 ||
+      spin > 100000 || !out_dev)
     return 1;
-  hipLaunchKernelGGL(k_placement, dim3((unsigned)blocks), dim3((unsigned)threads),
-                     (size_t)lds_bytes, (hipStream_t)stream, (uint32_t*)out_dev, spin);
+  const dim3 g((unsigned)blocks), b((unsigned)threads);
+  hipStream_t st = (hipStream_t)stream;
+  uint32_t* out = (uint32_t*)out_dev;
+  if (vgprs == 150)
+    hipLaunchKernelGGL(k_placement<150>, g, b, (size_t)lds_bytes, st, out, spin);
+  else if (vgprs == 230)
+    hipLaunchKernelGGL(k_placement<230>, g, b, (size_t)lds_bytes, st, out, spin);
+  else
+    hipLaunchKernelGGL(k_placement<0>, g, b, (size_t)lds_bytes, st, out, spin);
   return hipGetLastError() == hipSuccess ? 0 : 4;
 }
 

@@ -120,7 +120,7 @@ def test_probe_library_exports_its_header():
     # bad arguments are rejected before any device call
     raw.sdtw_probe_issue.argtypes = [C.c_int] * 4 + [C.c_void_p] * 2
     raw.sdtw_probe_lds.argtypes = [C.c_int] * 3 + [C.c_void_p] * 2
-    raw.sdtw_probe_placement.argtypes = [C.c_int] * 4 + [C.c_void_p] * 2
+    raw.sdtw_probe_placement.argtypes = [C.c_int] * 5 + [C.c_void_p] * 2
     out = C.c_void_p(1)
     assert raw.sdtw_probe_issue(5, 1, 1, 1, out, None) == 1      # no such kind
     assert raw.sdtw_probe_issue(0, 3, 1, 1, out, None) == 1      # chains
@@ -129,6 +129,7 @@ def test_probe_library_exports_its_header():
     assert raw.sdtw_probe_lds(0, 1, 1, out, None) == 1           # lanes
     assert raw.sdtw_probe_lds(65, 1, 1, out, None) == 1
     assert raw.sdtw_probe_lds(1, 1, 0, out, None) == 1           # iterations
-    assert raw.sdtw_probe_placement(16, 96, 0, 0, out, None) == 1  # not whole waves
-    assert raw.sdtw_probe_placement(16, 128, 200000, 0, out, None) == 1  # LDS
-    assert raw.sdtw_probe_placement(16, 128, 0, 0, None, None) == 1
+    assert raw.sdtw_probe_placement(16, 96, 0, 0, 0, out, None) == 1  # not whole waves
+    assert raw.sdtw_probe_placement(16, 128, 200000, 0, 0, out, None) == 1  # LDS
+    assert raw.sdtw_probe_placement(16, 128, 0, 100, 0, out, None) == 1  # registers
+    assert raw.sdtw_probe_placement(16, 128, 0, 0, 0, None, None) == 1

@@ -153,6 +153,21 @@ def test_band_schedule_invariance(dev, strip, chains, bands, waves):
                         bands), zq.astype(np.float32), zoffs, zref)
 
 
+@pytest.mark.parametrize("per_cu,extra", [(1, 0), (1, 37), (2, -5)])
+def test_band_pulls_from_both_ends(dev, per_cu, extra):
+    # two-wave workgroups (per_cu of them on every compute unit): with no more
+    # reads than workgroups half of them take their read from the back of the
+    # longest-first list, chosen by the SIMD their first wave runs on; with
+    # more, every pull takes the front; either way every read exactly once
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    n = per_cu * cus + extra
+    rng = np.random.default_rng(n)
+    Ms = [int(m) for m in rng.integers(130, 601, size=n)]
+    ref, q, offs = _ragged_case(n, Ms, 2500)
+    note(f"both ends: {n} reads, {per_cu} two-band workgroups per CU on {cus} CUs")
+    check_i16(gpu_batch(dev, ref, q, offs, sd.I16, 32, 2 * per_cu, 1, 2), q, offs, ref)
+
+
 @pytest.mark.parametrize("strip,bands,band_rows", [(16, 4, 100), (32, 4, 125), (32, 3, 70),
                                                    (16, 2, 300)])
 def test_band_row_targets(dev, strip, bands, band_rows):
