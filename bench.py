@@ -63,10 +63,10 @@ SIMD_CYCLES_PER_64_CELLS = {"i16": 4 + 4, "f32": 2 + 4 + 2}
 # device copy of known size (factors 1.9998 and 1.0000), keyed by workload and
 # launch shape, valid only while the kernel source is the one measured (sha256
 # of csrc/align.hip); otherwise `traffic` is null.
-_ALIGN_SHA = "e0b0817c3dd00b57f770bfbbf74ce9c13655471216cf905d7aa64bd226073dfc"
+_ALIGN_SHA = "19e9c9395b74872761dcbc64e5ab2ba1b54c2a521395391e0c1404fc3aedbca9"
 MEASURED_TRAFFIC = {
     ("1024 reads M~U[250,500] vs 5,000,000-base genome", "i16", 32, 1, 2): {
-        "fetch_bytes": 20346158444, "write_bytes": 132301, "align_hip_sha256": _ALIGN_SHA},
+        "fetch_bytes": 11626733043, "write_bytes": 320294976, "align_hip_sha256": _ALIGN_SHA},
 }
 
 
