@@ -23,8 +23,10 @@ decision The two decision rules of the server (per-event cost threshold and
          the mapping-quality score from best and runner-up ends, section 5.1)
          on both targets at 512 channels, with off-target reads that are
          i.i.d. noise and, harder, pore signal of a 1,000,000-base background
-         genome: accuracy, on-target reads kept, off-target reads rejected,
-         mean events read before the decision, reads/s and latency.
+         genome, every read at one noise level and (--noise-spread) each read
+         at its own, 1x to 4x: accuracy, on-target reads kept, off-target
+         reads rejected, mean events read before the decision, reads/s and
+         latency.
 events   Pre-processing on the device (section 4.1's event detection, prefix
          trimming and normalisation) against alignment, for 4,096 simulated
          raw reads (30 adaptor levels, then 320 bases; 50% on-target) and the
@@ -231,13 +233,15 @@ def decision(args):
     dev = torch.device("cuda:0")
     table = synth.make_level_table()
     background = synth.make_genome(1_000_000, 1_000_003)
-    for off in args.off.split(","):
+    for off, spread in ((o, float(sp)) for sp in args.noise_spread.split(",")
+                        for o in args.off.split(",")):
         specs = []
         for i, (name, L) in enumerate((("29,903-base", synth.SMALL_GENOME),
                                        ("5,000,000-base", synth.LARGE_GENOME))):
             genome = synth.make_genome(L, L)
             rd = synth.simulate_reads(genome, table, np.full(512, 2000), 0.5, 4400 + i,
-                                      off_genome=background if off == "genomic" else None)
+                                      off_genome=background if off == "genomic" else None,
+                                      noise_spread=spread)
             raws = [rd.values[rd.offsets[r]:rd.offsets[r + 1]] for r in range(512)]
             specs.append((name, genome, table, raws, rd.on_target))
         targets = srv.make_targets(specs, dev)
@@ -247,7 +251,7 @@ def decision(args):
             server.calibrate()
             r = server.run(8.0, 3.0)
             print(json.dumps({"experiment": "decision rule", "off_target_reads": off,
-                              "rule": rule,
+                              "noise_spread": spread, "rule": rule,
                               **{k: r[k] for k in ("reads_per_s", "decision_accuracy",
                                                    "on_target_kept", "off_target_rejected",
                                                    "mean_events_at_decision", "tau", "q_min",
@@ -521,6 +525,9 @@ def main():
     ap.add_argument("--out-dir", default="gpurun_out", help="placement: where the records go")
     ap.add_argument("--off", default="noise,genomic",
                     help="decision: off-target read kinds to run, in order")
+    ap.add_argument("--noise-spread", default="1,4",
+                    help="decision: per-read noise spreads to run (1: every read at the "
+                         "same noise level; s: each read's noise 1x to s x, log-uniform)")
     args = ap.parse_args()
     t0 = time.perf_counter()
     {"latency": latency, "scale": scale, "serving": serving,

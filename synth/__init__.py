@@ -17,6 +17,8 @@ would hand to the method, in raw units.
   emission with additive N(0, 0.3 x 12 pA) noise.  An off-target read is
   i.i.d. N(90, 12) pA, or (``off_genome``) the same pore simulation run on
   another genome, the harder case of reads from a background organism.
+  ``noise_spread`` gives each read its own noise level (1x to spread x,
+  log-uniform), as reads from different pores would have.
   Lengths follow the workload.
 
 The sizes mirror the paper's workloads (Table 2: the 29,903-base SARS-CoV-2
@@ -104,13 +106,24 @@ def _genomic_events(genome: np.ndarray, table: np.ndarray, M: int, k: int,
 def simulate_reads(genome: np.ndarray, table: np.ndarray, lengths,
                    frac_on: float, seed: int, k: int = K,
                    noise_sd: float = NOISE_SD_PA,
-                   off_genome: np.ndarray | None = None) -> Reads:
+                   off_genome: np.ndarray | None = None,
+                   noise_spread: float = 1.0) -> Reads:
     """Raw event streams for reads of the given lengths (see module doc).
 
     ``off_genome``: off-target reads are drawn from this other genome the
     way on-target reads are drawn from ``genome`` (pore signal of a random
-    strand and start), instead of i.i.d. N(90, 12) pA values."""
+    strand and start), instead of i.i.d. N(90, 12) pA values.
+
+    ``noise_spread`` > 1: every read's event noise is ``noise_sd`` times
+    spread**u, u ~ U(0, 1) per read (log-uniform between 1x and spread x),
+    drawn from a generator of its own so that the rest of the draws, and the
+    reads of spread 1, stay the same."""
     rng = np.random.default_rng(seed)
+    if noise_spread < 1.0:
+        raise ValueError("noise_spread must be >= 1")
+    mult = np.ones(len(np.atleast_1d(lengths)))
+    if noise_spread != 1.0:
+        mult = noise_spread ** np.random.default_rng(seed + 104729).random(mult.size)
     lengths = np.asarray(lengths, dtype=np.int64)
     nq = lengths.size
     offsets = np.zeros(nq + 1, dtype=np.int64)
@@ -126,13 +139,15 @@ def simulate_reads(genome: np.ndarray, table: np.ndarray, lengths,
         M = int(lengths[r])
         a, b = int(offsets[r]), int(offsets[r + 1])
         if on[r] and nk >= M:
-            values[a:b], s, p, used = _genomic_events(genome, table, M, k, noise_sd, rng)
+            values[a:b], s, p, used = _genomic_events(genome, table, M, k,
+                                                      noise_sd * float(mult[r]), rng)
             strand[r] = s
             start[r] = p
             end_true[r] = s * nk + p + used
         elif nk_off >= M:
             on[r] = False
-            values[a:b] = _genomic_events(off_genome, table, M, k, noise_sd, rng)[0]
+            values[a:b] = _genomic_events(off_genome, table, M, k, noise_sd * float(mult[r]),
+                                          rng)[0]
         else:
             on[r] = False
             values[a:b] = rng.normal(LEVEL_MEAN_PA, LEVEL_SD_PA, size=M).astype(np.float32)

@@ -41,3 +41,31 @@ def test_on_target_reads_map_to_their_origin():
     assert cost[on].max() < cost[~on].min()
     ci, ei, _ = oracle.batch(oracle.I64, qc, w.reads.offsets, codes)
     assert np.all(np.abs(ei[on] - w.reads.end_true[on]) <= 10)
+
+
+def test_noise_spread_scales_each_reads_noise_and_changes_nothing_else():
+    # per-read noise between 1x and spread x (log-uniform), from a generator
+    # of its own: spread 1 reproduces the default reads exactly, and a spread
+    # changes only the noise of the genomic reads, not which reads are on
+    # target or where they start
+    genome = synth.make_genome(20_000, 5)
+    table = synth.make_level_table()
+    L = np.full(64, 300)
+    base = synth.simulate_reads(genome, table, L, 0.5, 11)
+    same = synth.simulate_reads(genome, table, L, 0.5, 11, noise_spread=1.0)
+    assert np.array_equal(base.values, same.values)
+    wide = synth.simulate_reads(genome, table, L, 0.5, 11, noise_spread=4.0)
+    assert np.array_equal(base.on_target, wide.on_target)
+    assert np.array_equal(base.start, wide.start) and np.array_equal(base.strand, wide.strand)
+    # same strand, start and dwell draws: the difference of two reads is the
+    # difference of their noise, whose sd ratio is the read's multiplier
+    ratios = []
+    for r in np.nonzero(base.on_target)[0]:
+        a, b = base.offsets[r], base.offsets[r + 1]
+        d = (wide.values[a:b].astype(np.float64) - base.values[a:b]) / synth.NOISE_SD_PA
+        ratios.append(d.std())
+    ratios = np.array(ratios)
+    # (mult - 1) x N(0, 1): between 0 and 3 in sd, spread over the range
+    assert ratios.min() < 0.5 and ratios.max() > 2.0 and ratios.max() < 3.3
+    with np.testing.assert_raises(ValueError):
+        synth.simulate_reads(genome, table, L, 0.5, 11, noise_spread=0.5)
