@@ -206,20 +206,27 @@ def serving(args):
     dev = torch.device("cuda:0")
     small = bench.serving_targets(torch, dev, large=False)
     both = bench.serving_targets(torch, dev, large=True)
-    runs = [("29,903-base only", small, ch, 64 << 30) for ch in (512, 1024, 2048)]
-    runs += [("both targets", both, ch, 64 << 30) for ch in (64, 128, 256, 512)]
-    runs += [("both targets", both, 256, 4 << 30)]  # about 100 large-target rows
-    for name, targets, ch, budget in runs:
-        cfg = srv.ServerConfig(channels=ch, row_budget_bytes=budget)
+    chans = lambda v: [int(x) for x in v.split(",") if x]  # noqa: E731
+    wides = [int(x) for x in args.wide_chunks.split(",")]
+    runs = [("29,903-base only", small, ch, 64 << 30, w) for ch in chans(args.small_channels)
+            for w in wides]
+    runs += [("both targets", both, ch, 64 << 30, w) for ch in chans(args.both_channels)
+             for w in wides]
+    if args.budget_run:
+        runs += [("both targets", both, 256, 4 << 30, wides[0])]  # about 100 large rows
+    for name, targets, ch, budget, wide in runs:
+        cfg = srv.ServerConfig(channels=ch, row_budget_bytes=budget, wide_chunks=wide)
         server = srv.ReadUntilServer(targets, cfg, mode="extend")
-        server.calibrate()
+        cal = server.calibrate()
         r = server.run(8.0, 3.0)
         print(json.dumps({"experiment": "serving", "targets": name, "channels": ch,
-                          "row_budget_gib": budget >> 30,
+                          "row_budget_gib": budget >> 30, "wide_chunks_setting": wide,
+                          "wide_max": {k: v["wide_max"] for k, v in cal.items()},
                           **{k: r[k] for k in ("reads_per_s", "chunks_per_s", "gcups",
                                                "decision_latency_p50_ms",
                                                "decision_latency_p99_ms", "admission_waits",
-                                               "max_waiting_chunks", "decision_accuracy")},
+                                               "max_waiting_chunks", "decision_accuracy",
+                                               "wide_chunks")},
                           "per_target": r["per_target"]}), flush=True)
     for t in small + both:
         t.ref.close()
@@ -525,6 +532,15 @@ def main():
     ap.add_argument("--out-dir", default="gpurun_out", help="placement: where the records go")
     ap.add_argument("--off", default="noise,genomic",
                     help="decision: off-target read kinds to run, in order")
+    ap.add_argument("--small-channels", default="512,1024,2048",
+                    help="serving: channel counts with the 29,903-base target alone")
+    ap.add_argument("--both-channels", default="64,128,256,512",
+                    help="serving: channel counts with both targets")
+    ap.add_argument("--wide-chunks", default="-1",
+                    help="serving: ServerConfig.wide_chunks settings to run (-1: calibrated, "
+                         "0: batched launches only)")
+    ap.add_argument("--budget-run", type=int, default=1,
+                    help="serving: also run 256 channels with a 4 GiB row budget")
     ap.add_argument("--noise-spread", default="1,4",
                     help="decision: per-read noise spreads to run (1: every read at the "
                          "same noise level; s: each read's noise 1x to s x, log-uniform)")

@@ -469,6 +469,30 @@ int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk
                        void* stream);
 
 /*
+ * Extend one stream by one chunk over the whole device (section 2.2's
+ * per-chunk decision, Eq. 1 continued from the resident row): the chunk's
+ * rows as row scans across tiles of 256 x cols columns, as
+ * sdtw_align_one_wide does for a whole read, starting from the stream's
+ * resident row and writing the new last row back over it.  For a few
+ * chunks against a long reference, whose batched extension is bounded by
+ * one chunk's four waves, this answers in milliseconds; it uses the whole
+ * device per chunk, so batches of many chunks belong to sdtw_stream_extend.
+ * The two may extend the same stream in turn (one resident row format).
+ *   chunk_dev  M int16 values (device); the stream's rows plus M must stay
+ *              <= SDTW_MAX_QUERY (EINVAL otherwise; sdtw_stream_extend
+ *              takes longer streams).
+ *   cols       columns per thread: 0 (automatic), 8, 16, 32 or 64.
+ *   cost_dev, end_dev  one int32 each (device): the new last row's cost and
+ *              0-based end, as sdtw_align_batch; -1 and -1 if a wait in the
+ *              launch ran out (a defect), the resident row then undefined.
+ * int16 references only (EINVAL otherwise).  The stream's row count
+ * advances when the call returns; calls on one stream are ordered as for
+ * sdtw_stream_extend.
+ */
+int sdtw_stream_extend_wide(sdtw_stream s, const void* chunk_dev, int32_t M, int cols,
+                            void* cost_dev, int32_t* end_dev, void* stream);
+
+/*
  * Best and runner-up ends of the resident rows of `ns` streams on one
  * reference: the two mapped positions and scores a mapping quality is
  * computed from (section 5.1).  best = the first column with the row's

@@ -76,6 +76,7 @@ def load_library():
         "sdtw_stream_close": ([p], C.c_int),
         "sdtw_stream_copy_row": ([p, p, p], C.c_int),
         "sdtw_stream_extend": ([p, i32, p, p, p, p, p], C.c_int),
+        "sdtw_stream_extend_wide": ([p, p, i32, C.c_int, p, p, p], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -516,6 +517,17 @@ class Stream:
             self.close()
         except Exception:
             pass
+
+
+def stream_extend_wide(s, chunk, cols: int = 0, cost=None, end=None, stream=None):
+    """sdtw_stream_extend_wide: extend one int16 stream by one chunk (device
+    int16 tensor) over the whole device; returns (cost, end) device tensors."""
+    torch = _torch()
+    cost, end = _outputs(1, s.ref.dtype, chunk.device, cost, end)
+    _check(load_library().sdtw_stream_extend_wide(
+        s.handle, _dev(chunk, torch.int16, "chunk"), chunk.numel(), int(cols), _dev(cost),
+        _dev(end, torch.int32, "end"), _stream(stream)))
+    return cost, end
 
 
 def stream_extend(streams, chunks, offsets, cost=None, end=None, stream=None):

@@ -1267,6 +1267,45 @@ int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk
   return SDTW_OK;
 }
 
+int sdtw_stream_extend_wide(sdtw_stream s, const void* chunk_dev, int32_t M, int cols,
+                            void* cost_dev, int32_t* end_dev, void* stream) {
+  SDTW_REQUIRE(s && chunk_dev && cost_dev && end_dev, "sdtw_stream_extend_wide: null pointer");
+  const sdtw_ref ref = s->ref;
+  SDTW_REQUIRE(ref->dtype == SDTW_I16, "sdtw_stream_extend_wide: int16 references only");
+  SDTW_REQUIRE(M >= 1 && (int64_t)s->rows + M <= SDTW_MAX_QUERY,
+               "sdtw_stream_extend_wide: %d rows folded in plus a chunk of %d exceed %d", s->rows,
+               M, SDTW_MAX_QUERY);
+  SDTW_REQUIRE(cols == 0 || cols == 8 || cols == 16 || cols == 32 || cols == 64,
+               "sdtw_stream_extend_wide: cols=%d not in {0, 8, 16, 32, 64}", cols);
+  if (int rc = require_device(ref->device, "sdtw_stream_extend_wide")) return rc;
+  if (cols == 0) cols = wide_pick_cols(ref->n, ref->device);
+  SDTW_REQUIRE(wide_tiles(ref->n, cols) <= (int64_t)INT32_MAX,
+               "sdtw_stream_extend_wide: reference too long for %d columns per thread", cols);
+  const int dev = ref->device;
+  DescRing& ring = g_ring[dev >= 0 && dev < kMaxDevices ? dev : 0];
+  std::lock_guard<std::mutex> g(ring.mu);
+  DescSlot* pick = nullptr;
+  int rc = acquire_slot(ring, 1, &pick, "sdtw_stream_extend_wide");
+  if (rc) return rc;
+  DescSlot& sl = *pick;
+  rc = ensure_part(sl, wide_scratch_words(ref->n, M, cols));
+  if (rc) return rc;
+  auto tok = std::make_shared<CallToken>();
+  tok->ev = event_get();
+  if (!tok->ev) return set_error(SDTW_EDEVICE, "sdtw_stream_extend_wide: event creation failed");
+  hipStream_t st = (hipStream_t)stream;
+  rc = check_hip(launch_align_wide(ref->data, ref->n, (const int16_t*)chunk_dev, M, cols, sl.part,
+                                   (int32_t*)cost_dev, end_dev, st, s->row, s->rows > 0),
+                 "sdtw_stream_extend_wide: launch");
+  const int rc_ev = check_hip(hipEventRecord(tok->ev, st), "sdtw_stream_extend_wide: record");
+  if (!rc_ev) sl.last = tok;
+  if (!rc) rc = rc_ev;
+  if (rc) return rc;
+  s->rows += M;
+  s->last = tok;
+  return SDTW_OK;
+}
+
 int sdtw_stream_best_two(const sdtw_stream* streams, int32_t ns, int32_t window,
                          void* best_cost_dev, int32_t* best_end_dev, void* second_cost_dev,
                          int32_t* second_end_dev, void* stream) {

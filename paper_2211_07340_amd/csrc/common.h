@@ -180,7 +180,10 @@ hipError_t launch_events_continue(const float* raw, const int64_t* ranges, const
 // One int16 query over every compute unit: row scans with look-back between
 // tiles of 256 * cols columns (cols in {8, 16, 32, 64}).  `scratch` holds
 // wide_scratch_words(n, m, cols) 64-bit words, used only by this launch
-// (cleared by it, in order on `st`).
+// (cleared by it, in order on `st`).  `row` (n values, optional): the last
+// row is written there; with `row_in` the rows extend it (it holds the row
+// before the first of the m rows, at most 4,096 rows in all) instead of
+// starting from the free-start zeros.
 int64_t wide_tiles(int64_t n, int cols);
 int64_t wide_scratch_words(int64_t n, int32_t m, int cols);
 int wide_pick_cols(int64_t n, int device);  // columns per thread for sdtw_align_one_wide(cols=0)
@@ -191,6 +194,6 @@ int64_t wide_noalloc_words();
 hipError_t wide_noalloc_scratch(int device, uint64_t** out);
 hipError_t launch_align_wide(const uint32_t* ref, int64_t n, const int16_t* q, int32_t m,
                              int cols, uint64_t* scratch, int32_t* cost, int32_t* end,
-                             hipStream_t st);
+                             hipStream_t st, uint32_t* row = nullptr, bool row_in = false);
 
 }  // namespace sdtw

@@ -24,6 +24,12 @@
 //      gamma(i, first column - 1); the tile publishes its own last value;
 //   4. every thread applies its map prefix to that value and sweeps its C
 //      cells again, producing the row.
+// Extending a resident row (a stream: the row gamma(m_old, .) of the rows
+// folded in so far), the tile starts from that row instead of the free-start
+// zeros and writes its last row back over it.  A tile's first thread needs
+// the old value left of the tile, which the tile to its left may already
+// have overwritten (tiles beyond those resident run later), so the clearing
+// kernel takes a copy of every tile's left neighbour value first.
 // Tiles take their index from an atomic ticket, so a tile waits only on
 // tiles that started before it; a tile that waits far too long (about a
 // second; only a defect could cause it) raises an abort flag that ends every
@@ -274,7 +280,8 @@ template <int C, bool LowReg>
 __global__ __launch_bounds__(kWideThreads) void k_align_wide(
     const uint32_t* __restrict__ ref, int64_t n, int32_t ntiles, const int16_t* __restrict__ q,
     int32_t m, uint64_t* __restrict__ flags, uint64_t* __restrict__ tile_key,
-    uint32_t* __restrict__ ctrl) {
+    uint32_t* __restrict__ ctrl, uint32_t* __restrict__ row, int row_in,
+    const uint64_t* __restrict__ left_of_tile) {
   constexpr int T = kWideThreads * C;
   __shared__ uint32_t sa[kWideThreads / 64], sd[kWideThreads / 64];
   __shared__ uint32_t lastcol[2][kWideThreads];
@@ -291,14 +298,22 @@ __global__ __launch_bounds__(kWideThreads) void k_align_wide(
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     y[c] = col0 + c < n ? ref[col0 + c] : 0u;
-    prev[c] = 0u;  // gamma(0, j) = 0
+    prev[c] = row_in && col0 + c < n ? row[col0 + c] : 0u;  // gamma(0, j) = 0, or the row
   }
-  uint32_t xprev = 0u;  // gamma(i-1, first column of the tile - 1); row 0: 0
+  // gamma(i-1, first column of the tile - 1); row 0: 0, or the resident
+  // row's value left of the tile (+inf left of column 0)
+  uint32_t xprev = 0u;
+  // the first row's diagonal of this thread's first cell
+  uint32_t left_first = 0u;
+  if (row_in) {
+    xprev = tile == 0 ? kInf : (uint32_t)left_of_tile[tile];
+    if (threadIdx.x > 0 && col0 - 1 < n) left_first = row[col0 - 1];  // in this tile
+  }
 
   for (int32_t i = 0; i < m; ++i) {
     const uint32_t x = (uint32_t)((int32_t)q[i] + (int32_t)kI16Bias);
     const uint32_t left0 =
-        threadIdx.x == 0 ? xprev : (i == 0 ? 0u : lastcol[(i - 1) & 1][threadIdx.x - 1]);
+        threadIdx.x == 0 ? xprev : (i == 0 ? left_first : lastcol[(i - 1) & 1][threadIdx.x - 1]);
 
     // 1. this thread's map
     Map mine{kInf, 0};
@@ -345,6 +360,14 @@ __global__ __launch_bounds__(kWideThreads) void k_align_wide(
     __syncthreads();
   }
 
+  // the new resident row (every thread of the tile has read its old values:
+  // the loop's barriers lie between)
+  if (row) {
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+      if (col0 + c < n) row[col0 + c] = prev[c];
+  }
+
   // last row: the first column with the minimum in this tile
   uint64_t k = ~0ull;
 #pragma unroll
@@ -369,12 +392,15 @@ __global__ __launch_bounds__(kWideThreads) void k_align_wide(
 }
 
 // Flags and the ticket cleared for the next launch (a kernel, not a memset,
-// so that the call can be captured in a graph).
+// so that the call can be captured in a graph); when a resident row is
+// extended, the old value left of every tile (T columns each) copied aside.
 __global__ void k_wide_clear(uint64_t* __restrict__ flags, int64_t nflags,
-                             uint32_t* __restrict__ ctrl) {
+                             uint32_t* __restrict__ ctrl, const uint32_t* __restrict__ row,
+                             int64_t T, int32_t ntiles, uint64_t* __restrict__ left_of_tile) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nflags) flags[i] = 0;
   if (i < 2) ctrl[i] = 0;
+  if (row && i < ntiles) left_of_tile[i] = i > 0 ? row[i * T - 1] : 0u;
 }
 
 __global__ __launch_bounds__(kWideThreads) void k_wide_final(const uint64_t* __restrict__ tile_key,
@@ -414,7 +440,8 @@ int resident_tiles(const void* fn) {
 
 template <int C, bool LowReg>
 hipError_t launch_c(const uint32_t* ref, int64_t n, const int16_t* q, int32_t m,
-                    uint64_t* scratch, int32_t* cost, int32_t* end, hipStream_t st) {
+                    uint64_t* scratch, int32_t* cost, int32_t* end, hipStream_t st,
+                    uint32_t* row, bool row_in) {
   const int64_t T = (int64_t)kWideThreads * C;
   const int32_t ntiles = (int32_t)((n + T - 1) / T);
   const int64_t ngroups = (ntiles + kLookback - 1) / kLookback;
@@ -422,10 +449,13 @@ hipError_t launch_c(const uint32_t* ref, int64_t n, const int16_t* q, int32_t m,
   uint64_t* flags = scratch;
   uint64_t* tile_key = flags + nflags;
   uint32_t* ctrl = (uint32_t*)(tile_key + ntiles);
+  uint64_t* left_of_tile = tile_key + ntiles + 1;  // after the two control words
+  // (nflags >= 2 * ntiles: the clearing grid covers every tile)
   hipLaunchKernelGGL(k_wide_clear, dim3((unsigned)((nflags + 255) / 256)), dim3(256), 0, st,
-                     flags, nflags, ctrl);
+                     flags, nflags, ctrl, row_in ? row : nullptr, T, ntiles, left_of_tile);
   hipLaunchKernelGGL((k_align_wide<C, LowReg>), dim3((unsigned)ntiles), dim3(kWideThreads), 0,
-                     st, ref, n, ntiles, q, m, flags, tile_key, ctrl);
+                     st, ref, n, ntiles, q, m, flags, tile_key, ctrl, row, row_in ? 1 : 0,
+                     left_of_tile);
   hipLaunchKernelGGL(k_wide_final, dim3(1), dim3(kWideThreads), 0, st, tile_key, ntiles, ctrl,
                      cost, end);
   return hipGetLastError();
@@ -474,23 +504,26 @@ int64_t wide_tiles(int64_t n, int cols) { return (n + (int64_t)kWideThreads * co
 int64_t wide_scratch_words(int64_t n, int32_t m, int cols) {
   const int64_t t = wide_tiles(n, cols);
   const int64_t g = (t + kLookback - 1) / kLookback;
-  return 2 * (int64_t)m * t + (int64_t)m * g + t + 1;  // flags, tile keys, two control words
+  // flags, tile keys, two control words, the resident row's values left of
+  // every tile
+  return 2 * (int64_t)m * t + (int64_t)m * g + t + 1 + t;
 }
 
 hipError_t launch_align_wide(const uint32_t* ref, int64_t n, const int16_t* q, int32_t m,
                              int cols, uint64_t* scratch, int32_t* cost, int32_t* end,
-                             hipStream_t st) {
-  if (n < 1 || m < 1 || wide_tiles(n, cols) > INT_MAX) return hipErrorInvalidValue;
+                             hipStream_t st, uint32_t* row, bool row_in) {
+  if (n < 1 || m < 1 || wide_tiles(n, cols) > INT_MAX || (row_in && !row))
+    return hipErrorInvalidValue;
   switch (cols) {
-    case 8: return launch_c<8, false>(ref, n, q, m, scratch, cost, end, st);
-    case 16: return launch_c<16, false>(ref, n, q, m, scratch, cost, end, st);
+    case 8: return launch_c<8, false>(ref, n, q, m, scratch, cost, end, st, row, row_in);
+    case 16: return launch_c<16, false>(ref, n, q, m, scratch, cost, end, st, row, row_in);
     case 32: {
       // the low-register form when the plain one would run in more rounds
       if (wide_tiles(n, 32) > resident_tiles((const void*)k_align_wide<32, false>))
-        return launch_c<32, true>(ref, n, q, m, scratch, cost, end, st);
-      return launch_c<32, false>(ref, n, q, m, scratch, cost, end, st);
+        return launch_c<32, true>(ref, n, q, m, scratch, cost, end, st, row, row_in);
+      return launch_c<32, false>(ref, n, q, m, scratch, cost, end, st, row, row_in);
     }
-    case 64: return launch_c<64, false>(ref, n, q, m, scratch, cost, end, st);
+    case 64: return launch_c<64, false>(ref, n, q, m, scratch, cost, end, st, row, row_in);
     default: return hipErrorInvalidValue;
   }
 }

@@ -44,6 +44,15 @@ This module simulates the channels and runs the decisions through the C ABI:
 ``mode="recompute"`` aligns every chunk's whole prefix from scratch instead
 (a fresh stream extended by the full prefix), for comparison.
 
+Few chunks against a long reference.  A batched extension's time is that of
+one chunk on its few waves (about 0.18 s for 400 events against 10 M
+columns) however few chunks it holds, while sdtw_stream_extend_wide extends
+one chunk over the whole device in a few milliseconds.  A batch of at most
+``wide_chunks`` chunks (per target, by default the number whose whole-device
+calls take no longer than one batched launch, measured at calibration) is
+extended chunk by chunk over the whole device (``wide_chunks`` in the
+report counts them).
+
 Faults.  A read must be decided while most of the molecule is still in the
 pore (section 2.2); a lost or late decision only costs sequencing time, so
 the loop gives such reads up rather than stalling:
@@ -89,6 +98,9 @@ import numpy as np
 from . import binding as sd
 
 
+WIDE_MAX_ROWS = 4096  # rows a stream may hold for sdtw_stream_extend_wide (SDTW_MAX_QUERY)
+
+
 @dataclass
 class ServerConfig:
     channels: int = 512
@@ -109,6 +121,9 @@ class ServerConfig:
     chunk_samples: int = 2400          # raw mode: samples per channel per chunk period
     trim_events: int = 50              # raw mode: adaptor events dropped at a read's start
     chunk_timeout_s: float | None = None  # give up a read whose chunk waits longer (None: never)
+    wide_chunks: int = -1              # batches of at most this many chunks extend chunk by
+                                       # chunk over the whole device (int16 targets); -1: per
+                                       # target at calibration, 0: never
 
 
 @dataclass
@@ -126,6 +141,8 @@ class Target:
     raw_offs: object = None            # raw mode: int64 offsets of the pool's reads
     ev_states: object = None           # raw mode: detector state per channel (set by the server)
     ev_buf: object = None              # raw mode: [channels, max_events] detected events
+    wide_max: int = 0                  # batches of at most this many chunks go over the whole
+                                       # device (set by the serving config or calibration)
 
 
 @dataclass
@@ -178,6 +195,7 @@ class ServerStats:
     timeouts: int = 0                  # reads given up after a chunk timeout
     ended: int = 0                     # reads that ended before a decision (end_read)
     restarts: int = 0                  # reads restarted on a new row after theirs was lost
+    wide_chunks: int = 0               # chunks extended over the whole device
 
 
 def _median(x):
@@ -345,7 +363,41 @@ class ReadUntilServer:
             q = mapq(cost, second)
             t.tau = 0.5 * (_median(s[on]) + _median(s[~on]))
             t.q_min = 0.5 * (_median(q[on]) + _median(q[~on]))
-        return {t.name: {"tau": t.tau, "q_min": t.q_min} for t in self.targets}
+            t.wide_max = self._wide_max(t, raw_d[:M], dev)
+        return {t.name: {"tau": t.tau, "q_min": t.q_min, "wide_max": t.wide_max}
+                for t in self.targets}
+
+    def _wide_max(self, t, chunk_raw, dev):
+        """Chunks per batch up to which whole-device extensions (one per
+        chunk) finish no later than one batched launch: the configured
+        number, or the ratio of the two times for one chunk of
+        ``chunk_events`` rows (second chunk of a stream; best of two)."""
+        if self.cfg.wide_chunks >= 0 or t.ref.dtype != sd.I16:
+            return max(self.cfg.wide_chunks, 0) if t.ref.dtype == sd.I16 else 0
+        torch = self.torch
+        M = self.cfg.chunk_events
+        offs = torch.tensor([0, M], dtype=torch.int64, device=dev)
+        _, codes, _ = sd.prepare_queries(chunk_raw, offs, self.cfg.scale)
+        offs_np = np.array([0, M], np.int64)
+        times = {"batch": [], "wide": []}
+        st = sd.Stream(t.ref)
+        try:
+            sd.stream_extend([st], codes, offs_np)
+            for way in ("batch", "wide") * 2:
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record()
+                if way == "batch":
+                    sd.stream_extend([st], codes, offs_np)
+                else:
+                    sd.stream_extend_wide(st, codes)
+                b.record()
+                b.synchronize()
+                times[way].append(a.elapsed_time(b))
+        finally:
+            torch.cuda.synchronize()
+            st.close()
+        return int(min(times["batch"]) // max(min(times["wide"]), 1e-3))
 
     # ------------------------------------------------------------------
     def _new_read(self, now: float) -> _Read:
@@ -628,6 +680,7 @@ class ReadUntilServer:
             "timeouts": stats.timeouts,
             "ended": stats.ended,
             "restarts": stats.restarts,
+            "wide_chunks": stats.wide_chunks,
             "tau": {t.name: round(t.tau, 4) for t in self.targets},
             "q_min": {t.name: round(t.q_min, 2) for t in self.targets},
             "host_loop_ms": {k: {"total": round(v[0] * 1e3, 1), "max": round(v[1] * 1e3, 2),
@@ -640,6 +693,25 @@ class ReadUntilServer:
                                                             == ti], 99)}
                 for ti, t in enumerate(self.targets)},
         }
+
+    def _extend(self, t, handles, codes, offs_np, hs):
+        """Extend a batch's rows on HIP stream ``hs``: one batched launch, or
+        for at most t.wide_max chunks one whole-device call per chunk (rows
+        of at most WIDE_MAX_ROWS in all); (cost, end) device tensors."""
+        lens = np.diff(offs_np)
+        k = len(handles)
+        if 1 <= k <= t.wide_max and all(h.rows + int(m) <= WIDE_MAX_ROWS
+                                        for h, m in zip(handles, lens)):
+            torch = self.torch
+            cost = torch.empty(k, dtype=torch.int32, device=codes.device)
+            end = torch.empty(k, dtype=torch.int32, device=codes.device)
+            for i, h in enumerate(handles):
+                sd.stream_extend_wide(h, codes[int(offs_np[i]):int(offs_np[i + 1])],
+                                      cost=cost[i:i + 1], end=end[i:i + 1], stream=hs)
+            if self._loop is not None:
+                self._loop.stats.wide_chunks += k
+            return cost, end
+        return sd.stream_extend(handles, codes, offs_np, stream=hs)
 
     def _free_slot(self, ti, inflight):
         """Index of one of target ti's HIP streams with no batch in flight."""
@@ -715,7 +787,7 @@ class ReadUntilServer:
             offs_np = np.zeros(len(lens) + 1, np.int64)
             np.cumsum(lens, out=offs_np[1:])
             handles = [rd.handle for _, rd, _, _, _ in order]
-            cost, end = sd.stream_extend(handles, codes, offs_np, stream=hs)
+            cost, end = self._extend(t, handles, codes, offs_np, hs)
             pinned = [cost, end]
             if cfg.decision == "mapq":
                 _, _, c2, e2 = sd.stream_best_two(handles, cfg.mapq_window, stream=hs)
@@ -838,7 +910,7 @@ class ReadUntilServer:
             offs_np = np.zeros(len(lens) + 1, np.int64)
             np.cumsum(lens, out=offs_np[1:])
             handles = [rd.handle for _, rd, _, _ in entries]
-            cost, end = sd.stream_extend(handles, codes, offs_np, stream=hs)
+            cost, end = self._extend(t, handles, codes, offs_np, hs)
             pinned = [cost, end]
             if cfg.decision == "mapq":
                 _, _, c2, e2 = sd.stream_best_two(handles, cfg.mapq_window, stream=hs)

@@ -163,24 +163,29 @@ def _targets(dev, lengths, pool, seed):
     return targets, codes_of, raws_of
 
 
-def test_large_target_served_results_match_oracle():
+@pytest.mark.parametrize("wide", [-1, 0])
+def test_large_target_served_results_match_oracle(wide):
     # the serving workload's two targets at their full sizes: the 29,903-base
     # genome and the 5,000,000-base genome (9,999,990 columns, 40 MB resident
     # rows); 32 served results of the large target and 16 of the small one
-    # equal the oracle
+    # equal the oracle, with small batches extended over the whole device
+    # (wide=-1, the calibrated default) and with batched launches only
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2211_07340_amd import server as srv
     dev = torch.device("cuda:0")
     targets, codes_of, raws_of = _targets(dev, (synth.SMALL_GENOME, synth.LARGE_GENOME), 32, 95)
     rec = []
-    server = srv.ReadUntilServer(targets, srv.ServerConfig(channels=32, row_budget_bytes=8 << 30),
+    server = srv.ReadUntilServer(targets, srv.ServerConfig(channels=32, row_budget_bytes=8 << 30,
+                                                           wide_chunks=wide),
                                  record=rec)
-    server.calibrate(n_each=8)
+    cal = server.calibrate(n_each=8)
     res = server.run(4.0, 0.5)
-    print("large target", {k: res[k] for k in ("decisions", "decision_accuracy", "per_target")},
+    print("large target", wide, cal,
+          {k: res[k] for k in ("decisions", "decision_accuracy", "wide_chunks", "per_target")},
           flush=True)
     assert res["decision_accuracy"] > 0.9, res
+    assert (res["wide_chunks"] > 0) == (wide != 0), res
     n1, m1 = _check_records(rec, 1, raws_of[1], codes_of[1], 32, 5)
     n0, m0 = _check_records(rec, 0, raws_of[0], codes_of[0], 16, 6)
     print(f"checked {n1} of {m1} large-target and {n0} of {m0} small-target records",

@@ -288,3 +288,90 @@ def test_budget_and_state_errors(dev, prepared):
         sd.set_row_budget(budget0)
     other.close()
     ref.close()
+
+
+def _wide_rounds(dev, ref_np, chunks, ways, cols):
+    """One stream extended chunk by chunk, each chunk by the whole-device scan
+    ("wide") or the batched kernel ("batch"); after every chunk the cost, the
+    end and the whole resident row equal the oracle's on the prefix."""
+    ref = sd.Reference(torch.from_numpy(ref_np).to(dev))
+    s = sd.Stream(ref)
+    done = []
+    try:
+        for k, (ck, way) in enumerate(zip(chunks, ways)):
+            note(f"wide extension: chunk {k} ({ck.size} rows) by {way}, cols={cols}, "
+                 f"N={ref_np.size}")
+            q = torch.from_numpy(ck).to(dev)
+            if way == "wide":
+                cost, end = sd.stream_extend_wide(s, q, cols)
+            else:
+                cost, end = sd.stream_extend([s], q, np.array([0, ck.size], np.int64))
+            row = s.copy_row()
+            torch.cuda.synchronize()
+            done.append(ck)
+            want_c, want_e, want_row = oracle.sdtw_i64(np.concatenate(done), ref_np,
+                                                       lastrow=True)
+            assert (int(cost.item()), int(end.item())) == (want_c, want_e), (k, way)
+            assert np.array_equal(row.cpu().numpy().astype(np.int64), want_row), (k, way)
+            assert s.rows == sum(c.size for c in done)
+    finally:
+        torch.cuda.synchronize()
+        s.close()
+        ref.close()
+
+
+@pytest.mark.parametrize("cols", [0, 8, 16, 32, 64])
+def test_extend_wide_matches_oracle(dev, cols):
+    # three chunks over one or many tiles and a ragged last tile; the
+    # first starts from the free-start row, the others from the resident row
+    rng = np.random.default_rng(40 + cols)
+    ref_np = rng.integers(-3000, 3000, size=37_001).astype(np.int16)
+    chunks = [rng.integers(-3000, 3000, size=m).astype(np.int16) for m in (150, 1, 97)]
+    _wide_rounds(dev, ref_np, chunks, ["wide"] * 3, cols)
+
+
+def test_extend_wide_and_batched_take_turns(dev):
+    # one resident row format: the two paths extend the same stream in turn
+    rng = np.random.default_rng(41)
+    ref_np = rng.integers(-3000, 3000, size=20_000).astype(np.int16)
+    chunks = [rng.integers(-3000, 3000, size=m).astype(np.int16) for m in (200, 130, 300, 70)]
+    _wide_rounds(dev, ref_np, chunks, ["batch", "wide", "batch", "wide"], 16)
+
+
+def test_extend_wide_more_tiles_than_resident(dev):
+    # 5,000,000 columns at 8 per thread: 2,442 tiles, more than the device
+    # holds at once, so later tiles start after earlier ones have written
+    # their new rows back (each tile's left value is taken aside first)
+    rng = np.random.default_rng(42)
+    ref_np = rng.integers(-3000, 3000, size=5_000_000).astype(np.int16)
+    chunks = [rng.integers(-3000, 3000, size=m).astype(np.int16) for m in (60, 45)]
+    _wide_rounds(dev, ref_np, chunks, ["wide", "wide"], 8)
+
+
+def test_extend_wide_rejections(dev):
+    rng = np.random.default_rng(43)
+    ref = sd.Reference(torch.from_numpy(rng.integers(-99, 99, size=3000).astype(np.int16))
+                       .to(dev))
+    s = sd.Stream(ref)
+    try:
+        big = torch.from_numpy(rng.integers(-99, 99, size=4000).astype(np.int16)).to(dev)
+        sd.stream_extend_wide(s, big[:4000])
+        with pytest.raises(sd.SdtwError) as e:  # 4,000 + 97 rows > 4,096
+            sd.stream_extend_wide(s, big[:97])
+        assert e.value.code == "EINVAL"
+        with pytest.raises(sd.SdtwError):
+            sd.stream_extend_wide(s, big[:5], cols=12)
+        assert s.rows == 4000
+    finally:
+        torch.cuda.synchronize()
+        s.close()
+        ref.close()
+    fref = sd.Reference(torch.from_numpy(rng.normal(size=3000).astype(np.float32)).to(dev))
+    fs = sd.Stream(fref)
+    try:
+        with pytest.raises(sd.SdtwError) as e:
+            sd.stream_extend_wide(fs, torch.zeros(10, dtype=torch.int16, device=dev))
+        assert e.value.code == "EINVAL"
+    finally:
+        fs.close()
+        fref.close()

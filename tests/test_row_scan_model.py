@@ -83,7 +83,11 @@ def look_back(t, agg, inc, gag, GT, GW, rng, cap, dbits):
         gbase -= GW
 
 
-def row_scan_sdtw(q, ref, C, TH, GT, GW, seed, cap=(1 << 30) - 1, dbits=30):
+def row_scan_sdtw(q, ref, C, TH, GT, GW, seed, cap=(1 << 30) - 1, dbits=30, row=None,
+                  return_row=False, left_of_tile=None):
+    """(cost, end) of q against ref; with ``row`` (a resident row, the last
+    row of the rows before q) the rows of q extend it.  ``return_row``: the
+    new last row as well, (cost, end, row)."""
     rng = np.random.default_rng(seed)
     x_all = q.astype(np.int64) + 32768
     y = ref.astype(np.int64) + 32768
@@ -93,6 +97,14 @@ def row_scan_sdtw(q, ref, C, TH, GT, GW, seed, cap=(1 << 30) - 1, dbits=30):
     ycols[:n] = y
     prev = np.zeros((ntiles, T), np.int64)   # gamma(0, j) = 0
     xprev = np.zeros(ntiles, np.int64)        # gamma(i-1, first column - 1)
+    if row is not None:
+        # the old row, and the old value left of each tile (+inf left of
+        # column 0), as the clearing kernel takes it aside
+        prev.reshape(-1)[:n] = row
+        xprev[0] = INF
+        xprev[1:] = [row[t * T - 1] for t in range(1, ntiles)]
+        if left_of_tile is not None:  # (a planted mistake's values)
+            xprev[1:] = left_of_tile[1:]
     for x in x_all:
         d = np.abs(int(x) - ycols.reshape(ntiles, T))
         left = np.concatenate([xprev[:, None], prev[:, :-1]], axis=1)
@@ -128,6 +140,8 @@ def row_scan_sdtw(q, ref, C, TH, GT, GW, seed, cap=(1 << 30) - 1, dbits=30):
             xprev[t] = xin[t]
     last = prev.reshape(-1)[:n]
     j = int(np.argmin(last))
+    if return_row:
+        return int(last[j]), j, last.copy()
     return int(last[j]), j
 
 
@@ -141,6 +155,50 @@ def test_model_matches_oracle(case):
     ref = rng.integers(-lo, lo, size=n).astype(np.int16)
     q = rng.integers(-lo, lo, size=m).astype(np.int16)
     assert row_scan_sdtw(q, ref, C, TH, GT, GW, case) == oracle.sdtw_i64(q, ref)
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_model_extends_a_resident_row(case):
+    # chunk by chunk from the resident row: cost, end and the row after each
+    # chunk equal the oracle's on the concatenated prefix
+    rng = np.random.default_rng(500 + case)
+    n = int(rng.integers(1, 200))
+    C, TH = int(rng.choice([1, 2, 3])), int(rng.choice([1, 2, 4]))
+    GT, GW = int(rng.choice([1, 2, 4])), int(rng.choice([1, 2]))
+    ref = rng.integers(-300, 300, size=n).astype(np.int16)
+    chunks = [rng.integers(-300, 300, size=int(m)).astype(np.int16)
+              for m in rng.integers(1, 5, size=3)]
+    row = None  # the first chunk starts from the free-start zeros
+    for k, ck in enumerate(chunks):
+        c, e, row = row_scan_sdtw(ck, ref, C, TH, GT, GW, case + k, row=row, return_row=True)
+        pre = np.concatenate(chunks[:k + 1])
+        want_c, want_e, want_row = oracle.sdtw_i64(pre, ref, lastrow=True)
+        assert (c, e) == (want_c, want_e)
+        assert np.array_equal(row, want_row)
+
+
+def test_resident_row_diagonal_left_of_a_tile_matters():
+    # the first new row's diagonal at a tile's first column is the old row's
+    # value left of the tile; taking the new value there instead (as a tile
+    # that starts after its left neighbour wrote back would) changes results
+    rng = np.random.default_rng(7)
+    bad = 0
+    for s in range(20):
+        ref = rng.integers(-300, 300, size=48).astype(np.int16)
+        a = rng.integers(-300, 300, size=3).astype(np.int16)
+        b = rng.integers(-300, 300, size=3).astype(np.int16)
+        _, _, row_a = oracle.sdtw_i64(a, ref, lastrow=True)
+        _, _, row_ab = oracle.sdtw_i64(np.concatenate([a, b]), ref, lastrow=True)
+        _, _, row = row_scan_sdtw(b, ref, 2, 2, 2, 2, s, row=row_a, return_row=True)
+        assert np.array_equal(row, row_ab)
+        # the planted mistake: each tile's left value (tiles of 4 columns)
+        # read from the row as its left neighbour wrote it back
+        _, _, row_new = oracle.sdtw_i64(np.concatenate([a, b[:1]]), ref, lastrow=True)
+        lefts = [0] + [int(row_new[t * 4 - 1]) for t in range(1, 12)]
+        _, _, row2 = row_scan_sdtw(b[:1], ref, 2, 2, 2, 2, s, row=row_a, return_row=True,
+                                   left_of_tile=np.array(lefts))
+        bad += not np.array_equal(row2, row_new)
+    assert bad > 0
 
 
 def test_saturated_sums_do_not_change_results():
