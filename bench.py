@@ -125,6 +125,9 @@ def parse():
     ap.add_argument("--serve-warmup", type=float, default=5.0)
     ap.add_argument("--serve-channels", type=int, default=512)
     ap.add_argument("--serve-recompute-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-low-channels", type=int, default=64,
+                    help="serving: a second, low-load incremental run at this many channels, "
+                         "8 s after 3 s (0: none)")
     ap.add_argument("--serve-small-only", action="store_true",
                     help="serve the 29,903-base target only")
     return ap.parse_args()
@@ -240,7 +243,8 @@ def main():
         progress("serving")
         out["serving"] = serving(torch, dev, args.serve_seconds, args.serve_warmup,
                                  args.serve_channels, args.serve_recompute_seconds,
-                                 large=not args.serve_small_only)
+                                 large=not args.serve_small_only,
+                                 low_channels=args.serve_low_channels)
 
     if not args.no_cpu_baseline:
         progress("CPU baseline (the oracle)")
@@ -493,8 +497,10 @@ def serving_targets(torch, dev, pool: int = 512, seed: int = 4400, large: bool =
 
 
 def serving(torch, dev, seconds: float, warmup: float, channels: int, recompute_s: float,
-            large: bool = True):
-    """Streaming Read Until: incremental extension, then recompute from scratch."""
+            large: bool = True, low_channels: int = 0):
+    """Streaming Read Until: incremental extension, then recompute from
+    scratch; then incremental extension at a low load, where small batches
+    of long-reference chunks go over the whole device one chunk at a time."""
     from paper_2211_07340_amd import server as srv
     targets = serving_targets(torch, dev, large=large)
     cfg = srv.ServerConfig(channels=channels, row_budget_bytes=64 << 30)
@@ -507,6 +513,14 @@ def serving(torch, dev, seconds: float, warmup: float, channels: int, recompute_
     if recompute_s > 0:
         rec = srv.ReadUntilServer(targets, cfg, mode="recompute")
         out["recompute"] = rec.run(recompute_s, min(warmup, 2.0))
+    if low_channels > 0:
+        low = srv.ReadUntilServer(
+            targets, srv.ServerConfig(channels=low_channels, row_budget_bytes=64 << 30),
+            mode="extend")
+        cal = low.calibrate()
+        out["low_load"] = {"channels": low_channels,
+                           "wide_max": {k: v["wide_max"] for k, v in cal.items()},
+                           "incremental": low.run(8.0, 3.0)}
     for t in targets:
         t.ref.close()
     return out
