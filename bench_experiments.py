@@ -58,8 +58,11 @@ best_two The runner-up search alone (sdtw_stream_best_two) over 1 to 256
          resident rows of the 5,000,000-base target (9,999,990 columns):
          device time and the rate at which it reads the rows (4 bytes per
          column per row, the bound being HBM at 8 TB/s).
+stream_wide Extending 1 to 64 streams by one 400-event chunk each against
+         the 5,000,000-base target: one batched launch against one
+         whole-device call per chunk (sdtw_stream_extend_wide).
 
-Usage: python bench_experiments.py latency|scale|serving|serving_raw|decision|best_two|wide|events|issue|lds|placement
+Usage: python bench_experiments.py latency|scale|serving|serving_raw|decision|best_two|wide|events|issue|lds|placement|stream_wide
                                    [--max-genome BASES] [--genome BASES] [--cols C]
                                    [--reps R]
 """
@@ -230,6 +233,53 @@ def serving(args):
                           "per_target": r["per_target"]}), flush=True)
     for t in small + both:
         t.ref.close()
+
+
+def stream_wide(args):
+    """Extending k streams by one 400-event chunk each against the
+    9,999,990-column reference: one batched launch (sdtw_stream_extend)
+    against k whole-device calls (sdtw_stream_extend_wide); HIP events, best
+    of two, after each stream's first chunk."""
+    import torch
+
+    import synth
+    import paper_2211_07340_amd as sd
+    dev = torch.device("cuda:0")
+    w = synth.workload(3, nq=1)
+    g = torch.from_numpy(w.genome).to(dev)
+    t = torch.from_numpy(w.table).to(dev)
+    _, cref, _ = sd.prepare_reference(g, t, 6, 64.0)
+    ref = sd.Reference(cref)
+    sd.set_row_budget(64 << 30)
+    rng = np.random.default_rng(5)
+    M = 400
+    for k in [int(v) for v in args.chunks.split(",")]:
+        streams = [sd.Stream(ref) for _ in range(k)]
+        offs = np.arange(k + 1, dtype=np.int64) * M
+        q = torch.from_numpy(rng.integers(-300, 300, size=k * M).astype(np.int16)).to(dev)
+        sd.stream_extend(streams, q, offs)  # first chunk
+        torch.cuda.synchronize()
+        res = {"batch": [], "wide": []}
+        for way in ("batch", "wide") * 2:
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            if way == "batch":
+                sd.stream_extend(streams, q, offs)
+            else:
+                for i in range(k):
+                    sd.stream_extend_wide(streams[i], q[i * M:(i + 1) * M])
+            b.record()
+            b.synchronize()
+            res[way].append(a.elapsed_time(b))
+        bm, wm = min(res["batch"]), min(res["wide"])
+        print(json.dumps({"experiment": "stream extension, batched against whole device",
+                          "chunks": k, "rows": M, "reference_values": ref.n,
+                          "batch_ms": round(bm, 2), "wide_ms": round(wm, 2),
+                          "wide_ms_per_chunk": round(wm / k, 3)}), flush=True)
+        torch.cuda.synchronize()
+        for s_ in streams:
+            s_.close()
+    ref.close()
 
 
 def decision(args):
@@ -524,7 +574,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("experiment",
                     choices=["latency", "scale", "serving", "serving_raw", "decision",
-                             "best_two", "wide", "events", "issue", "lds", "placement"])
+                             "best_two", "wide", "events", "issue", "lds", "placement",
+                             "stream_wide"])
     ap.add_argument("--max-genome", type=int, default=10_000_000)
     ap.add_argument("--genome", type=int, default=5_000_000, help="wide: genome bases")
     ap.add_argument("--cols", type=int, default=0, help="wide: columns per thread (0: auto)")
@@ -532,6 +583,8 @@ def main():
     ap.add_argument("--out-dir", default="gpurun_out", help="placement: where the records go")
     ap.add_argument("--off", default="noise,genomic",
                     help="decision: off-target read kinds to run, in order")
+    ap.add_argument("--chunks", default="1,4,16,64",
+                    help="stream_wide: numbers of streams extended per call")
     ap.add_argument("--small-channels", default="512,1024,2048",
                     help="serving: channel counts with the 29,903-base target alone")
     ap.add_argument("--both-channels", default="64,128,256,512",
@@ -549,7 +602,7 @@ def main():
     {"latency": latency, "scale": scale, "serving": serving,
      "decision": decision, "best_two": best_two, "wide": wide,
      "events": events, "serving_raw": serving_raw, "issue": issue,
-     "lds": lds, "placement": placement}[args.experiment](args)
+     "lds": lds, "placement": placement, "stream_wide": stream_wide}[args.experiment](args)
     print(json.dumps({"done": args.experiment, "seconds": round(time.perf_counter() - t0, 1)}),
           flush=True)
 
