@@ -276,8 +276,10 @@ __device__ uint32_t look_back(int32_t tile, int32_t ntiles, int32_t i, int32_t m
   }
 }
 
-template <int C, bool LowReg>
-__global__ __launch_bounds__(kWideThreads) void k_align_wide(
+// ROW: a resident row to extend (row_in) or to write (compiled apart, so
+// that the single-query form keeps its registers and so its tiles per CU).
+template <int C, bool LowReg, bool ROW>
+__global__ __launch_bounds__(kWideThreads, LowReg ? 3 : 1) void k_align_wide(
     const uint32_t* __restrict__ ref, int64_t n, int32_t ntiles, const int16_t* __restrict__ q,
     int32_t m, uint64_t* __restrict__ flags, uint64_t* __restrict__ tile_key,
     uint32_t* __restrict__ ctrl, uint32_t* __restrict__ row, int row_in,
@@ -298,16 +300,32 @@ __global__ __launch_bounds__(kWideThreads) void k_align_wide(
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     y[c] = col0 + c < n ? ref[col0 + c] : 0u;
-    prev[c] = row_in && col0 + c < n ? row[col0 + c] : 0u;  // gamma(0, j) = 0, or the row
+    prev[c] = 0u;  // gamma(0, j) = 0
   }
   // gamma(i-1, first column of the tile - 1); row 0: 0, or the resident
   // row's value left of the tile (+inf left of column 0)
   uint32_t xprev = 0u;
   // the first row's diagonal of this thread's first cell
   uint32_t left_first = 0u;
-  if (row_in) {
-    xprev = tile == 0 ? kInf : (uint32_t)left_of_tile[tile];
-    if (threadIdx.x > 0 && col0 - 1 < n) left_first = row[col0 - 1];  // in this tile
+  if constexpr (ROW) {
+    if (row_in) {
+      if (col0 + C <= n) {  // the whole strip: 16-byte loads (col0 is a multiple of 8)
+#pragma unroll
+        for (int c = 0; c < C; c += 4) {
+          const uint4 v = *(const uint4*)(row + col0 + c);
+          prev[c] = v.x;
+          prev[c + 1] = v.y;
+          prev[c + 2] = v.z;
+          prev[c + 3] = v.w;
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+          if (col0 + c < n) prev[c] = row[col0 + c];
+      }
+      xprev = tile == 0 ? kInf : (uint32_t)left_of_tile[tile];
+      if (threadIdx.x > 0 && col0 - 1 < n) left_first = row[col0 - 1];  // in this tile
+    }
   }
 
   for (int32_t i = 0; i < m; ++i) {
@@ -362,7 +380,7 @@ __global__ __launch_bounds__(kWideThreads) void k_align_wide(
 
   // the new resident row (every thread of the tile has read its old values:
   // the loop's barriers lie between)
-  if (row) {
+  if constexpr (ROW) {
 #pragma unroll
     for (int c = 0; c < C; ++c)
       if (col0 + c < n) row[col0 + c] = prev[c];
@@ -438,7 +456,7 @@ int resident_tiles(const void* fn) {
   return per_cu * cus;
 }
 
-template <int C, bool LowReg>
+template <int C, bool LowReg, bool ROW>
 hipError_t launch_c(const uint32_t* ref, int64_t n, const int16_t* q, int32_t m,
                     uint64_t* scratch, int32_t* cost, int32_t* end, hipStream_t st,
                     uint32_t* row, bool row_in) {
@@ -453,7 +471,7 @@ hipError_t launch_c(const uint32_t* ref, int64_t n, const int16_t* q, int32_t m,
   // (nflags >= 2 * ntiles: the clearing grid covers every tile)
   hipLaunchKernelGGL(k_wide_clear, dim3((unsigned)((nflags + 255) / 256)), dim3(256), 0, st,
                      flags, nflags, ctrl, row_in ? row : nullptr, T, ntiles, left_of_tile);
-  hipLaunchKernelGGL((k_align_wide<C, LowReg>), dim3((unsigned)ntiles), dim3(kWideThreads), 0,
+  hipLaunchKernelGGL((k_align_wide<C, LowReg, ROW>), dim3((unsigned)ntiles), dim3(kWideThreads), 0,
                      st, ref, n, ntiles, q, m, flags, tile_key, ctrl, row, row_in ? 1 : 0,
                      left_of_tile);
   hipLaunchKernelGGL(k_wide_final, dim3(1), dim3(kWideThreads), 0, st, tile_key, ntiles, ctrl,
@@ -509,23 +527,35 @@ int64_t wide_scratch_words(int64_t n, int32_t m, int cols) {
   return 2 * (int64_t)m * t + (int64_t)m * g + t + 1 + t;
 }
 
+namespace {
+
+template <bool ROW>
+hipError_t launch_row(const uint32_t* ref, int64_t n, const int16_t* q, int32_t m, int cols,
+                      uint64_t* scratch, int32_t* cost, int32_t* end, hipStream_t st,
+                      uint32_t* row, bool row_in) {
+  switch (cols) {
+    case 8: return launch_c<8, false, ROW>(ref, n, q, m, scratch, cost, end, st, row, row_in);
+    case 16: return launch_c<16, false, ROW>(ref, n, q, m, scratch, cost, end, st, row, row_in);
+    case 32: {
+      // the low-register form when the plain one would run in more rounds
+      if (wide_tiles(n, 32) > resident_tiles((const void*)k_align_wide<32, false, ROW>))
+        return launch_c<32, true, ROW>(ref, n, q, m, scratch, cost, end, st, row, row_in);
+      return launch_c<32, false, ROW>(ref, n, q, m, scratch, cost, end, st, row, row_in);
+    }
+    case 64: return launch_c<64, false, ROW>(ref, n, q, m, scratch, cost, end, st, row, row_in);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
 hipError_t launch_align_wide(const uint32_t* ref, int64_t n, const int16_t* q, int32_t m,
                              int cols, uint64_t* scratch, int32_t* cost, int32_t* end,
                              hipStream_t st, uint32_t* row, bool row_in) {
   if (n < 1 || m < 1 || wide_tiles(n, cols) > INT_MAX || (row_in && !row))
     return hipErrorInvalidValue;
-  switch (cols) {
-    case 8: return launch_c<8, false>(ref, n, q, m, scratch, cost, end, st, row, row_in);
-    case 16: return launch_c<16, false>(ref, n, q, m, scratch, cost, end, st, row, row_in);
-    case 32: {
-      // the low-register form when the plain one would run in more rounds
-      if (wide_tiles(n, 32) > resident_tiles((const void*)k_align_wide<32, false>))
-        return launch_c<32, true>(ref, n, q, m, scratch, cost, end, st, row, row_in);
-      return launch_c<32, false>(ref, n, q, m, scratch, cost, end, st, row, row_in);
-    }
-    case 64: return launch_c<64, false>(ref, n, q, m, scratch, cost, end, st, row, row_in);
-    default: return hipErrorInvalidValue;
-  }
+  return row ? launch_row<true>(ref, n, q, m, cols, scratch, cost, end, st, row, row_in)
+             : launch_row<false>(ref, n, q, m, cols, scratch, cost, end, st, row, row_in);
 }
 
 }  // namespace sdtw
