@@ -51,7 +51,9 @@ one chunk over the whole device in a few milliseconds.  A batch of at most
 ``wide_chunks`` chunks (per target, by default the number whose whole-device
 calls take no longer than one batched launch, measured at calibration) is
 extended chunk by chunk over the whole device (``wide_chunks`` in the
-report counts them).
+report counts them), alternating between two HIP streams; ``wide_burst_ms``
+caps such a batch's duration, since the whole device is its meanwhile and
+other targets' batches wait.
 
 Faults.  A read must be decided while most of the molecule is still in the
 pore (section 2.2); a lost or late decision only costs sequencing time, so
@@ -124,6 +126,8 @@ class ServerConfig:
     wide_chunks: int = -1              # batches of at most this many chunks extend chunk by
                                        # chunk over the whole device (int16 targets); -1: per
                                        # target at calibration, 0: never
+    wide_burst_ms: float = 40.0        # calibration: at most this long per such batch (the
+                                       # whole device is theirs meanwhile; other targets wait)
 
 
 @dataclass
@@ -143,6 +147,7 @@ class Target:
     ev_buf: object = None              # raw mode: [channels, max_events] detected events
     wide_max: int = 0                  # batches of at most this many chunks go over the whole
                                        # device (set by the serving config or calibration)
+    wide_aux: object = None            # second HIP stream of those (set by the server)
 
 
 @dataclass
@@ -284,6 +289,11 @@ class ReadUntilServer:
         k = max(1, self.cfg.streams_per_target)
         for i, t in enumerate(self.targets):
             t.streams = _server_streams(torch, i * k, k)
+        # one more per target: whole-device extensions of a batch alternate
+        # between the batch's stream and this one, so that one chunk's
+        # look-back waits overlap another chunk's rows
+        for i, t in enumerate(self.targets):
+            t.wide_aux = _server_streams(torch, len(self.targets) * k + i, 1)[0]
         if self.cfg.row_budget_bytes is not None:
             sd.set_row_budget(self.cfg.row_budget_bytes)
         if self.cfg.raw:
@@ -369,35 +379,44 @@ class ReadUntilServer:
 
     def _wide_max(self, t, chunk_raw, dev):
         """Chunks per batch up to which whole-device extensions (one per
-        chunk) finish no later than one batched launch: the configured
-        number, or the ratio of the two times for one chunk of
-        ``chunk_events`` rows (second chunk of a stream; best of two)."""
+        chunk, alternating between two HIP streams) finish no later than one
+        batched launch and within ``wide_burst_ms``: the configured number,
+        or those times over the time per chunk, measured on two chunks of
+        ``chunk_events`` rows (second chunks of two streams; best of two)."""
         if self.cfg.wide_chunks >= 0 or t.ref.dtype != sd.I16:
             return max(self.cfg.wide_chunks, 0) if t.ref.dtype == sd.I16 else 0
         torch = self.torch
         M = self.cfg.chunk_events
-        offs = torch.tensor([0, M], dtype=torch.int64, device=dev)
-        _, codes, _ = sd.prepare_queries(chunk_raw, offs, self.cfg.scale)
-        offs_np = np.array([0, M], np.int64)
+        offs = torch.tensor([0, M, 2 * M], dtype=torch.int64, device=dev)
+        _, codes, _ = sd.prepare_queries(torch.cat([chunk_raw, chunk_raw]), offs,
+                                         self.cfg.scale)
+        offs_np = np.array([0, M, 2 * M], np.int64)
         times = {"batch": [], "wide": []}
-        st = sd.Stream(t.ref)
+        sts = [sd.Stream(t.ref), sd.Stream(t.ref)]
+        main, aux = torch.cuda.current_stream(), t.wide_aux or torch.cuda.current_stream()
         try:
-            sd.stream_extend([st], codes, offs_np)
+            sd.stream_extend(sts, codes, offs_np)
             for way in ("batch", "wide") * 2:
+                torch.cuda.synchronize()
                 a = torch.cuda.Event(enable_timing=True)
                 b = torch.cuda.Event(enable_timing=True)
                 a.record()
                 if way == "batch":
-                    sd.stream_extend([st], codes, offs_np)
+                    sd.stream_extend(sts, codes, offs_np)
                 else:
-                    sd.stream_extend_wide(st, codes)
+                    aux.wait_stream(main)
+                    sd.stream_extend_wide(sts[0], codes[:M])
+                    sd.stream_extend_wide(sts[1], codes[M:], stream=aux)
+                    main.wait_stream(aux)
                 b.record()
                 b.synchronize()
-                times[way].append(a.elapsed_time(b))
+                times[way].append(a.elapsed_time(b) / (1 if way == "batch" else 2))
         finally:
             torch.cuda.synchronize()
-            st.close()
-        return int(min(times["batch"]) // max(min(times["wide"]), 1e-3))
+            for st in sts:
+                st.close()
+        budget = min(min(times["batch"]), self.cfg.wide_burst_ms)
+        return int(budget // max(min(times["wide"]), 1e-3))
 
     # ------------------------------------------------------------------
     def _new_read(self, now: float) -> _Read:
@@ -705,9 +724,18 @@ class ReadUntilServer:
             torch = self.torch
             cost = torch.empty(k, dtype=torch.int32, device=codes.device)
             end = torch.empty(k, dtype=torch.int32, device=codes.device)
+            # chunks alternate between hs and the target's second stream,
+            # which first waits for hs's work so far (the chunks' codes) and
+            # which hs waits for at the end (the batch's results)
+            aux = t.wide_aux if (k > 1 and t.wide_aux is not None) else hs
+            if aux is not hs:
+                aux.wait_stream(hs)
             for i, h in enumerate(handles):
                 sd.stream_extend_wide(h, codes[int(offs_np[i]):int(offs_np[i + 1])],
-                                      cost=cost[i:i + 1], end=end[i:i + 1], stream=hs)
+                                      cost=cost[i:i + 1], end=end[i:i + 1],
+                                      stream=hs if i % 2 == 0 else aux)
+            if aux is not hs:
+                hs.wait_stream(aux)
             if self._loop is not None:
                 self._loop.stats.wide_chunks += k
             return cost, end
