@@ -51,9 +51,12 @@ one chunk over the whole device in a few milliseconds.  A batch of at most
 ``wide_chunks`` chunks (per target, by default the number whose whole-device
 calls take no longer than one batched launch, measured at calibration) is
 extended chunk by chunk over the whole device (``wide_chunks`` in the
-report counts them), alternating between two HIP streams; ``wide_burst_ms``
-caps such a batch's duration, since the whole device is its meanwhile and
-other targets' batches wait.
+report counts them); ``wide_burst_ms`` caps such a batch's duration, since
+the whole device is its meanwhile and other targets' batches wait.  With
+``wide_streams=2`` the chunks alternate between two HIP streams (one
+chunk's look-back waits overlap the other's rows), which pays only where
+the second stream has a hardware queue of its own: one shared with the
+target's other stream serialises the two.
 
 Faults.  A read must be decided while most of the molecule is still in the
 pore (section 2.2); a lost or late decision only costs sequencing time, so
@@ -128,6 +131,8 @@ class ServerConfig:
                                        # target at calibration, 0: never
     wide_burst_ms: float = 40.0        # calibration: at most this long per such batch (the
                                        # whole device is theirs meanwhile; other targets wait)
+    wide_streams: int = 1              # HIP streams such a batch's chunks alternate over (1, 2;
+                                       # 2 needs a hardware queue for the second, see above)
 
 
 @dataclass
@@ -379,7 +384,7 @@ class ReadUntilServer:
 
     def _wide_max(self, t, chunk_raw, dev):
         """Chunks per batch up to which whole-device extensions (one per
-        chunk, alternating between two HIP streams) finish no later than one
+        chunk, on ``wide_streams`` HIP streams) finish no later than one
         batched launch and within ``wide_burst_ms``: the configured number,
         or those times over the time per chunk, measured on two chunks of
         ``chunk_events`` rows (second chunks of two streams; best of two)."""
@@ -393,7 +398,8 @@ class ReadUntilServer:
         offs_np = np.array([0, M, 2 * M], np.int64)
         times = {"batch": [], "wide": []}
         sts = [sd.Stream(t.ref), sd.Stream(t.ref)]
-        main, aux = torch.cuda.current_stream(), t.wide_aux or torch.cuda.current_stream()
+        main = torch.cuda.current_stream()
+        aux = t.wide_aux if (t.wide_aux is not None and self.cfg.wide_streams > 1) else main
         try:
             sd.stream_extend(sts, codes, offs_np)
             for way in ("batch", "wide") * 2:
@@ -404,10 +410,12 @@ class ReadUntilServer:
                 if way == "batch":
                     sd.stream_extend(sts, codes, offs_np)
                 else:
-                    aux.wait_stream(main)
+                    if aux is not main:
+                        aux.wait_stream(main)
                     sd.stream_extend_wide(sts[0], codes[:M])
                     sd.stream_extend_wide(sts[1], codes[M:], stream=aux)
-                    main.wait_stream(aux)
+                    if aux is not main:
+                        main.wait_stream(aux)
                 b.record()
                 b.synchronize()
                 times[way].append(a.elapsed_time(b) / (1 if way == "batch" else 2))
@@ -727,7 +735,8 @@ class ReadUntilServer:
             # chunks alternate between hs and the target's second stream,
             # which first waits for hs's work so far (the chunks' codes) and
             # which hs waits for at the end (the batch's results)
-            aux = t.wide_aux if (k > 1 and t.wide_aux is not None) else hs
+            aux = t.wide_aux if (k > 1 and t.wide_aux is not None and
+                                 self.cfg.wide_streams > 1) else hs
             if aux is not hs:
                 aux.wait_stream(hs)
             for i, h in enumerate(handles):

@@ -1,9 +1,10 @@
 """Which extension the server issues for a batch (CPU only): one batched
 launch (sdtw_stream_extend), or for at most a target's ``wide_max`` chunks
-one whole-device call per chunk (sdtw_stream_extend_wide), alternating
-between the batch's HIP stream and the target's second one, which waits for
-the batch's stream first and is waited for at the end.  The binding calls
-are replaced by recorders; no device is touched."""
+one whole-device call per chunk (sdtw_stream_extend_wide), on the batch's
+HIP stream, or with ``wide_streams=2`` alternating between it and the
+target's second one, which waits for the batch's stream first and is
+waited for at the end.  The binding calls are replaced by recorders; no
+device is touched."""
 import numpy as np
 import pytest
 
@@ -64,11 +65,20 @@ def _batch(lens, rows=0):
     return [Handle(rows) for _ in lens], codes, offs
 
 
-def test_small_batches_go_over_the_whole_device_on_two_streams(calls):
+def test_small_batches_go_over_the_whole_device(calls):
+    t = Target(4, calls)
+    handles, codes, offs = _batch([400, 300, 200])
+    cost, end = Server()._extend(t, handles, codes, offs, FakeStream("hs", calls))
+    assert [(c[0], c[2], c[3]) for c in calls] == [("wide", 400, "hs"), ("wide", 300, "hs"),
+                                                   ("wide", 200, "hs")]
+    assert cost.tolist() == [400, 300, 200] and end.tolist() == [-400, -300, -200]
+
+
+def test_small_batches_on_two_streams(calls):
     t = Target(4, calls)
     hs = FakeStream("hs", calls)
     handles, codes, offs = _batch([400, 300, 200])
-    cost, end = Server()._extend(t, handles, codes, offs, hs)
+    cost, end = Server(srv.ServerConfig(wide_streams=2))._extend(t, handles, codes, offs, hs)
     assert calls[0] == ("wait", "aux", "hs")
     assert [c[0] for c in calls[1:4]] == ["wide"] * 3
     assert [c[3] for c in calls[1:4]] == ["hs", "aux", "hs"]  # alternating
@@ -80,7 +90,8 @@ def test_small_batches_go_over_the_whole_device_on_two_streams(calls):
 def test_one_chunk_stays_on_its_stream(calls):
     t = Target(4, calls)
     handles, codes, offs = _batch([400])
-    Server()._extend(t, handles, codes, offs, FakeStream("hs", calls))
+    Server(srv.ServerConfig(wide_streams=2))._extend(t, handles, codes, offs,
+                                                      FakeStream("hs", calls))
     assert calls == [("wide", id(handles[0]), 400, "hs")]
 
 
