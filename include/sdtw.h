@@ -345,7 +345,10 @@ int sdtw_plan_destroy(sdtw_plan plan);
  *
  * Only kernels are enqueued (no allocation, no host synchronisation), so the
  * call may be captured in a hipGraph.  Two calls with the same plan must not
- * overlap in time (the plan holds the work counter).
+ * overlap in time (the plan holds the work-pull and placement words the
+ * launch clears and uses).  Where the launch runs (which SIMD a workgroup
+ * lands on) decides which reads share a SIMD and their issue priority, never
+ * the results.
  */
 int sdtw_align_batch(sdtw_ref ref, sdtw_plan plan, const void* q_dev,
                      void* cost_dev, int32_t* end_dev, void* stream);
