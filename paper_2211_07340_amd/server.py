@@ -397,7 +397,16 @@ class ReadUntilServer:
                                          self.cfg.scale)
         offs_np = np.array([0, M, 2 * M], np.int64)
         times = {"batch": [], "wide": []}
-        sts = [sd.Stream(t.ref), sd.Stream(t.ref)]
+        sts = []
+        try:
+            for _ in range(2):
+                sts.append(sd.Stream(t.ref))
+        except sd.SdtwError as e:  # no room for two more rows: batched launches only
+            for st in sts:
+                st.close()
+            if e.code == "EBUDGET":
+                return 0
+            raise
         main = torch.cuda.current_stream()
         aux = t.wide_aux if (t.wide_aux is not None and self.cfg.wide_streams > 1) else main
         try:
