@@ -392,11 +392,6 @@ class ReadUntilServer:
             return max(self.cfg.wide_chunks, 0) if t.ref.dtype == sd.I16 else 0
         torch = self.torch
         M = self.cfg.chunk_events
-        offs = torch.tensor([0, M, 2 * M], dtype=torch.int64, device=dev)
-        _, codes, _ = sd.prepare_queries(torch.cat([chunk_raw, chunk_raw]), offs,
-                                         self.cfg.scale)
-        offs_np = np.array([0, M, 2 * M], np.int64)
-        times = {"batch": [], "wide": []}
         sts = []
         try:
             for _ in range(2):
@@ -407,9 +402,14 @@ class ReadUntilServer:
             if e.code == "EBUDGET":
                 return 0
             raise
+        offs = torch.tensor([0, M, 2 * M], dtype=torch.int64, device=dev)
+        offs_np = np.array([0, M, 2 * M], np.int64)
+        times = {"batch": [], "wide": []}
         main = torch.cuda.current_stream()
         aux = t.wide_aux if (t.wide_aux is not None and self.cfg.wide_streams > 1) else main
         try:
+            _, codes, _ = sd.prepare_queries(torch.cat([chunk_raw, chunk_raw]), offs,
+                                             self.cfg.scale)
             sd.stream_extend(sts, codes, offs_np)
             for way in ("batch", "wide") * 2:
                 torch.cuda.synchronize()

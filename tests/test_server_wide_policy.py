@@ -116,3 +116,14 @@ def test_configured_counts_need_no_device():
     assert s._wide_max(Target(0, log, dtype=sd.F32), None, None) == 0
     s = Server(srv.ServerConfig(wide_chunks=-1))
     assert s._wide_max(Target(0, log, dtype=sd.F32), None, None) == 0
+
+
+def test_no_room_for_the_timing_rows_means_batched_only(monkeypatch):
+    # calibration opens two rows to time both paths; a budget without room
+    # for them leaves the target on batched launches
+    class Full:
+        def __init__(self, ref):
+            raise sd.SdtwError(3, "budget")  # SDTW_EBUDGET
+    monkeypatch.setattr(sd, "Stream", Full)
+    s = Server(srv.ServerConfig(wide_chunks=-1))
+    assert s._wide_max(Target(0, []), None, None) == 0
