@@ -531,8 +531,8 @@ def cpu_baseline(w, reads, args):
     import oracle
     z, codes, _ = oracle.prepare_reference(w.genome, w.table, w.k)
     qz, qc, _ = oracle.prepare_queries(reads.values, reads.offsets)
-    # the host share of one GPU on the GPU machines is 16 cores, whatever the
-    # affinity mask shows
+    # a one-GPU host here gives each GPU 16 cores, whatever the affinity
+    # mask shows
     cores = min(16, len(os.sched_getaffinity(0)))
     kind = oracle.I64 if args.dtype == "i16" else oracle.F32
     q = qc if args.dtype == "i16" else qz

@@ -580,7 +580,7 @@ def main():
     ap.add_argument("--genome", type=int, default=5_000_000, help="wide: genome bases")
     ap.add_argument("--cols", type=int, default=0, help="wide: columns per thread (0: auto)")
     ap.add_argument("--reps", type=int, default=20, help="wide: timed calls")
-    ap.add_argument("--out-dir", default="gpurun_out", help="placement: where the records go")
+    ap.add_argument("--out-dir", default=".", help="placement: where the records go")
     ap.add_argument("--off", default="noise,genomic",
                     help="decision: off-target read kinds to run, in order")
     ap.add_argument("--chunks", default="1,4,16,64",
