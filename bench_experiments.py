@@ -61,8 +61,15 @@ best_two The runner-up search alone (sdtw_stream_best_two) over 1 to 256
 stream_wide Extending 1 to 64 streams by one 400-event chunk each against
          the 5,000,000-base target: one batched launch against one
          whole-device call per chunk (sdtw_stream_extend_wide).
+stream_batch The batched stream extension alone: --stream-chunks resident
+         rows (default 256) extended by a 400-event chunk each against the
+         5,000,000-base target, by launch shape (--stream-shapes, strip:bands,
+         0:0 for the library's choice): one batch alone (HIP events) and two
+         such batches issued at once on two HIP streams (host clock around
+         both), as the server keeps two batches per target in flight; the
+         fraction of the VALU roof of each.
 
-Usage: python bench_experiments.py latency|scale|serving|serving_raw|decision|best_two|wide|events|issue|lds|placement|stream_wide
+Usage: python bench_experiments.py latency|scale|serving|serving_raw|decision|best_two|wide|events|issue|lds|placement|stream_wide|stream_batch
                                    [--max-genome BASES] [--genome BASES] [--cols C]
                                    [--reps R]
 """
@@ -279,6 +286,64 @@ def stream_wide(args):
         torch.cuda.synchronize()
         for s_ in streams:
             s_.close()
+    ref.close()
+
+
+def stream_batch(args):
+    import torch
+
+    import synth
+    import paper_2211_07340_amd as sd
+    dev = torch.device("cuda:0")
+    w = synth.workload(3, nq=1)
+    g = torch.from_numpy(w.genome).to(dev)
+    t = torch.from_numpy(w.table).to(dev)
+    _, cref, _ = sd.prepare_reference(g, t, 6, 64.0)
+    ref = sd.Reference(cref)
+    sd.set_row_budget(64 << 30)
+    rng = np.random.default_rng(5)
+    M, k = 400, args.stream_chunks
+    hs = [torch.cuda.Stream(), torch.cuda.Stream()]
+    roof = bench.valu_peak_tcups("i16")
+    for shape in args.stream_shapes.split(","):
+        strip, bands = (int(v) for v in shape.split(":"))
+        sd.set_stream_config(strip, bands, ref=ref)
+        streams = [sd.Stream(ref) for _ in range(2 * k)]
+        offs = np.arange(k + 1, dtype=np.int64) * M
+        q = torch.from_numpy(rng.integers(-300, 300, size=k * M).astype(np.int16)).to(dev)
+        with torch.cuda.stream(hs[0]):
+            sd.stream_extend(streams[:k], q, offs, stream=hs[0])  # first chunk of each row
+            sd.stream_extend(streams[k:], q, offs, stream=hs[0])
+        torch.cuda.synchronize()
+        one, two = [], []
+        # each rep extends the first k rows twice: stay within 4,096 rows
+        for _ in range(max(1, min(args.reps, (4096 // M - 1) // 2))):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(hs[0])
+            sd.stream_extend(streams[:k], q, offs, stream=hs[0])
+            b.record(hs[0])
+            b.synchronize()
+            one.append(a.elapsed_time(b))
+            if not args.stream_two:
+                continue
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sd.stream_extend(streams[:k], q, offs, stream=hs[0])
+            sd.stream_extend(streams[k:], q, offs, stream=hs[1])
+            torch.cuda.synchronize()
+            two.append((time.perf_counter() - t0) * 1e3)
+        cells = k * M * ref.n
+        o = min(one)
+        rec = {"experiment": "stream_batch", "chunks": k, "rows": M,
+               "reference_values": ref.n, "strip": strip, "bands": bands,
+               "one_batch_ms": round(o, 2), "frac_one": round(cells / o / 1e9 / roof, 3)}
+        if two:
+            rec.update(two_batches_ms=round(min(two), 2),
+                       frac_two=round(2 * cells / min(two) / 1e9 / roof, 3))
+        print(json.dumps(rec), flush=True)
+        for s_ in streams:
+            s_.close()
+    sd.set_stream_config(0, 0, ref=ref)
     ref.close()
 
 
@@ -575,7 +640,7 @@ def main():
     ap.add_argument("experiment",
                     choices=["latency", "scale", "serving", "serving_raw", "decision",
                              "best_two", "wide", "events", "issue", "lds", "placement",
-                             "stream_wide"])
+                             "stream_wide", "stream_batch"])
     ap.add_argument("--max-genome", type=int, default=10_000_000)
     ap.add_argument("--genome", type=int, default=5_000_000, help="wide: genome bases")
     ap.add_argument("--cols", type=int, default=0, help="wide: columns per thread (0: auto)")
@@ -585,6 +650,12 @@ def main():
                     help="decision: off-target read kinds to run, in order")
     ap.add_argument("--chunks", default="1,4,16,64",
                     help="stream_wide: numbers of streams extended per call")
+    ap.add_argument("--stream-chunks", type=int, default=256,
+                    help="stream_batch: resident rows extended per batch")
+    ap.add_argument("--stream-shapes", default="0:0,32:4,32:2,16:4",
+                    help="stream_batch: launch shapes strip:bands (0:0: the library's)")
+    ap.add_argument("--stream-two", type=int, default=1,
+                    help="stream_batch: also time two batches issued at once (0: one only)")
     ap.add_argument("--small-channels", default="512,1024,2048",
                     help="serving: channel counts with the 29,903-base target alone")
     ap.add_argument("--both-channels", default="64,128,256,512",
@@ -602,7 +673,8 @@ def main():
     {"latency": latency, "scale": scale, "serving": serving,
      "decision": decision, "best_two": best_two, "wide": wide,
      "events": events, "serving_raw": serving_raw, "issue": issue,
-     "lds": lds, "placement": placement, "stream_wide": stream_wide}[args.experiment](args)
+     "lds": lds, "placement": placement, "stream_wide": stream_wide,
+     "stream_batch": stream_batch}[args.experiment](args)
     print(json.dumps({"done": args.experiment, "seconds": round(time.perf_counter() - t0, 1)}),
           flush=True)
 

@@ -525,8 +525,8 @@ int sdtw_stream_best_two(const sdtw_stream* streams, int32_t ns, int32_t window,
  *   strip  columns per lane, 16 or 32; 0 (default) = 32 for references of
  *          2^20 columns or more, else 16.
  *   bands  waves per chunk (the row bands of sdtw_plan_set_config), 1 to 4;
- *          0 (default) = 4 for at most one chunk per compute unit, 2 for
- *          fewer than four, else 1 (a chunk of M rows uses at most M / 65).
+ *          0 (default) = 4 for at most two chunks per compute unit, 2 for
+ *          at most four, else 1 (a chunk of M rows uses at most M / 65).
  * Results never depend on it.  EINVAL for other values.
  */
 int sdtw_stream_set_config(sdtw_ref ref, int strip, int bands);

@@ -311,16 +311,22 @@ __device__ __forceinline__ void load_strip(uint32_t (&dst)[W], const uint32_t* _
 // M rows of one chunk (rows m_old+1 .. m_old+M of the read): when a sub-lane
 // of band 0 enters a tile its previous row is acc's strip (instead of zeros)
 // and its diagonal is acc one column to the left (+inf left of column 0),
-// both loaded into registers with the tile's reference values; the last band
-// writes the finished last row of every tile back to acc.  A tile's acc is
-// read at least one period before that tile's write-back, so reads see the
-// row as it was before this extension.
+// both copied into LDS a period ahead (the tile's reference values go to
+// registers); the last band writes the finished last row of every tile back
+// to acc.  A tile's acc is read at least one period before that tile's
+// write-back, so reads see the row as it was before this extension.
 //
 // LDS (uint32 words, every array on 16 bytes): zeros[W] and a +inf cell
-// (4 words); ring[P-1][2][64W]; edge[P-1][4]; per band: stage[64W] (in the
-// last band the finished last rows, folded once a period) and bx.
+// (4 words); ring[P-1][2][64W]; edge[P-1][4]; then per band stage[64W] (in
+// the last band the finished last rows, folded once a period) and bx; or,
+// for STREAM, one stage[64W] (used by a read's last band alone), acc's
+// next tile for band 0 (64W, after a 4-word block whose last word is the
+// value left of the tile) and per band bx.  With the shared stage and no
+// registers held for acc, two workgroups of four bands fit on a CU, so a
+// launch of one chunk per CU (one wave per SIMD) leaves room for the next
+// launch, of the same reference or another, to run beside it.
 template <class F, int W, int K, int P, bool STREAM>
-__global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
+__global__ __launch_bounds__(64 * P, STREAM ? 2 : 1) void k_align_skew(AlignArgs args) {
   constexpr int T = 64 * W;
   constexpr int H = W / K;
   constexpr int S = 64 * K;                   // sub-lanes = switch steps per period
@@ -342,8 +348,15 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
   uint32_t* const inf_cell = zeros + W;
   uint32_t* const ring = inf_cell + 4;
   uint32_t* const edge = ring + (P - 1) * 2 * T;
-  uint32_t* const stage = edge + (P - 1) * 4 + wave * skew_band_words(W, K, args.max_band);
-  uint2* const bx = (uint2*)(stage + T);
+  // the last band's finished rows: one stage per band, or when extending
+  // resident rows one for every band, followed by the first band's copy of
+  // the resident row's next tile (a strip per lane) after a word holding
+  // the value left of it
+  uint32_t* const stage =
+      edge + (P - 1) * 4 + (STREAM ? 0 : wave * skew_band_words(W, K, args.max_band));
+  [[maybe_unused]] uint32_t* const accst = stage + T + 4;
+  uint2* const bx = STREAM ? (uint2*)(accst + T + wave * skew_entry_words(K, args.max_band))
+                           : (uint2*)(stage + T);
   uint32_t* const my_stage = stage + lane * W;
   uint2* const bxl = bx + K * (63 - lane);
   uint32_t* const ring_in = ring + (wave > 0 ? wave - 1 : 0) * 2 * T + lane * W;
@@ -453,22 +466,29 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
     const int32_t r0 = (wave * M) / Pe;
     const int32_t Mb = ((wave + 1) * M) / Pe - r0;  // this band's rows
     const typename F::qin* __restrict__ qv = (const typename F::qin*)args.q + q0 + r0;
-    // A lane's strip of the tile it enters next (and, in band 0 when
-    // streaming, the resident row's strip and the value left of it) waits in
-    // registers: loaded from global memory once every lane has entered the
-    // current tile, copied by each lane when it enters the next one.  A fresh
-    // read (m_old == 0) has gamma(0, .) = 0.
-    uint32_t ynext[W], accnext[STREAM ? W : 1], accleftnext = F::kInf;
+    // A lane's strip of the tile it enters next waits in registers: loaded
+    // from global memory once every lane has entered the current tile,
+    // copied by each lane when it enters the next one.  When a resident row
+    // is extended (m_old > 0), band 0's previous row of the next tile goes
+    // from global memory straight into LDS (accst, no registers: the copies
+    // land while the band computes) and the value left of the tile into one
+    // register, which lane 0 stores in front of the copy before the tile's
+    // switch steps.  A fresh read (m_old == 0) has gamma(0, .) = 0.
+    uint32_t ynext[W];
+    [[maybe_unused]] uint32_t accleftnext = F::kInf;
+    [[maybe_unused]] const bool resident = STREAM && m_old > 0;
     auto load_acc = [&](int32_t t) {
       if constexpr (STREAM) {
-        const int64_t c0 = (int64_t)t * T + lane * W;
-        accleftnext = F::kInf;
-        if (m_old > 0) {
-          load_strip<W>(accnext, acc + c0);
-          if (c0 > 0) accleftnext = acc[c0 - 1];
-        } else {
+        if (resident) {
+          // 64 lanes x 16 bytes per copy, lane l's bytes at 16 l: copy c of
+          // the tile's 4 T bytes covers words [256 c, 256 c + 256)
+          const uint32_t* src = acc + (int64_t)t * T + 4 * lane;
 #pragma unroll
-          for (int w = 0; w < W; ++w) accnext[w] = 0u;
+          for (int c = 0; c < T / 256; ++c)
+            __builtin_amdgcn_global_load_lds(
+                (const __attribute__((address_space(1))) void*)(src + 256 * c),
+                (__attribute__((address_space(3))) void*)(accst + 256 * c), 16, 0, 0);
+          accleftnext = t > 0 ? acc[(int64_t)t * T - 1] : F::kInf;
         }
       }
     };
@@ -543,22 +563,17 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
     //     (zeros, the staged resident row or the band above's ring slot).
     //     The next step's cells then find their operands in place instead of
     //     waiting for a round of LDS operations.
-    // Where a sub-lane entering a tile takes its previous row: band 0 from
-    // registers (the resident row's strip when streaming; else gamma(0, .) =
-    // 0, as every other column cleared, which puts a zero in every cell's
-    // minimum once the diagonal left of the sub-strip is 0 too), the other
-    // bands from the band above's ring slot in LDS.
-    // (UR: band 0, whose phase A is compiled apart from the other bands')
+    // Where a sub-lane entering a tile takes its previous row: band 0 of a
+    // fresh read from registers (gamma(0, .) = 0, as every other column
+    // cleared, which puts a zero in every cell's minimum once the diagonal
+    // left of the sub-strip is 0 too), band 0 of a resident row from its LDS
+    // copy, the other bands from the band above's ring slot in LDS.
+    // (UR: band 0 of a fresh read, whose phase A is compiled apart)
     auto diag_in = [&](auto ur, auto hc) -> uint32_t {  // the value left of sub-strip h
       constexpr bool UR = decltype(ur)::value;
       constexpr int h = decltype(hc)::value;
       if constexpr (UR) {
-        if constexpr (!STREAM)
-          return 0u;
-        else if constexpr (h == 0)
-          return accleftnext;
-        else
-          return accnext[h > 0 ? h * H - 1 : 0];
+        return 0u;
       } else if constexpr (h == 0) {
         return *d0src;
       } else {
@@ -567,15 +582,8 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
     };
     auto prev_in = [&](auto ur, uint32_t(&dst)[W], int w) {  // columns [w, w + 4)
       if constexpr (decltype(ur)::value) {
-        if constexpr (STREAM) {
-          dst[w] = accnext[w];
-          dst[w + 1] = accnext[w + 1];
-          dst[w + 2] = accnext[w + 2];
-          dst[w + 3] = accnext[w + 3];
-        } else {
-          dst[w + 1] = 0u;
-          dst[w + 3] = 0u;
-        }
+        dst[w + 1] = 0u;
+        dst[w + 3] = 0u;
       } else {
         const uint4 zv = *(const uint4*)(upsrc + w);
         dst[w] = zv.x;
@@ -686,8 +694,18 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
       p = G - 2 * wave;
       if (active && p >= 0 && p <= ntiles) {
         if (wave == 0) {
-          upsrc = zeros;  // not read: band 0's previous row comes from registers
+          upsrc = zeros;  // not read: a fresh read's previous row is cleared registers
           d0src = zeros;
+          if constexpr (STREAM) {
+            if (resident) {
+              // the copies of tile p (issued a period earlier, or for tile 0
+              // when the read was taken) have landed
+              asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+              if (lane == 0) accst[-1] = accleftnext;
+              upsrc = accst + lane * W;
+              d0src = upsrc - 1;  // lane 0: the value left of the tile
+            }
+          }
         } else {
           upsrc = ring_in + (p & 1) * T;
           d0src = lane > 0 ? upsrc - 1 : (p > 0 ? edge_in + ((p - 1) & 3) : inf_cell);
@@ -751,9 +769,9 @@ __global__ __launch_bounds__(64 * P) void k_align_skew(AlignArgs args) {
             }
           }
         };
-        if (wave == 0)
+        if (wave == 0 && !resident)
           phase_a(std::true_type{});
-        else if constexpr (P > 1)
+        else if constexpr (P > 1 || STREAM)
           phase_a(std::false_type{});
         flush();
         // every lane has finished tile p-1: the last band folds its last row
@@ -963,7 +981,7 @@ __global__ void k_reset_sched(uint32_t* s) {
 
 template <class F, int W, int K, int P, bool STREAM>
 hipError_t launch_skew_t(int blocks, const AlignArgs& a, hipStream_t st) {
-  const size_t lds = std::max(skew_lds_bytes(W, K, P, a.max_band), (size_t)a.lds_bytes);
+  const size_t lds = std::max(skew_lds_bytes(W, K, P, a.max_band, STREAM), (size_t)a.lds_bytes);
   hipError_t e = hipFuncSetAttribute((const void*)k_align_skew<F, W, K, P, STREAM>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;

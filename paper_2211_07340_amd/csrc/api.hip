@@ -474,8 +474,9 @@ static std::vector<LaunchGroup> launch_groups(const sdtw_plan_s* p) {
 
 // Resident waves per CU for a skew launch: whole workgroups of `bands` waves
 // within the CU's 160 KiB of LDS, at most 16 waves (four per SIMD).
-static int skew_waves_per_cu(int strip, int chains, int bands, int max_band) {
-  const size_t per = skew_lds_bytes(strip, chains, bands, max_band);
+static int skew_waves_per_cu(int strip, int chains, int bands, int max_band,
+                             bool stream = false) {
+  const size_t per = skew_lds_bytes(strip, chains, bands, max_band, stream);
   const int groups = (int)std::min<size_t>(16 / bands, (160 * 1024) / std::max<size_t>(per, 1));
   return std::max(groups, 1) * bands;
 }
@@ -1183,15 +1184,17 @@ int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk
   });
   // One chain per lane.  Automatic shape: more waves per chunk the fewer
   // chunks there are (a chunk's latency shrinks with its bands while the
-  // device is not full), one per chunk from four chunks per compute unit on;
-  // strip 32 for references of 2^20 columns and more (half the tiles per
-  // chunk), else 16, whose workgroups need a third of strip 32's LDS, so that
-  // short-reference calls find room beside long-reference ones.
+  // device is not full): four bands up to two chunks per compute unit (two
+  // workgroups of four bands fit on a CU, two waves per SIMD), two up to
+  // four, then one; strip 32 for references of 2^20 columns and more (half
+  // the tiles per chunk), else 16, whose workgroups need a third of strip
+  // 32's LDS, so that short-reference calls find room beside long-reference
+  // ones.
   constexpr int kChains = 1;
   const int cus = std::max(cu_count(), 1);
   int bands = ref->stream_bands.load();
   if (bands == 0) bands = g_stream_bands.load();
-  if (bands == 0) bands = ns <= cus ? 4 : (ns < 4 * cus ? 2 : 1);
+  if (bands == 0) bands = ns <= 2 * cus ? 4 : (ns <= 4 * cus ? 2 : 1);
   int kStrip = ref->stream_strip.load();
   if (kStrip == 0) kStrip = g_stream_strip.load();
   if (kStrip == 0) kStrip = ref->n >= (int64_t(1) << 20) ? 32 : 16;
@@ -1201,7 +1204,7 @@ int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk
     ++nbig;
   }
   const size_t lds_max = (size_t)max_lds_bytes();
-  SDTW_REQUIRE(skew_lds_bytes(kStrip, kChains, bands, max_band) <= lds_max &&
+  SDTW_REQUIRE(skew_lds_bytes(kStrip, kChains, bands, max_band, true) <= lds_max &&
                    plain_lds_bytes(dtype, kStrip, max_m) <= lds_max,
                "sdtw_stream_extend: chunk of %d rows needs more LDS than available", max_m);
 
@@ -1243,7 +1246,7 @@ int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk
     a.max_band = max_band;
     // no LDS reservation (spread_lds): calls in flight on other HIP streams
     // (other targets, the next batch) must find room on every CU
-    const int wpc = skew_waves_per_cu(kStrip, kChains, bands, max_band);
+    const int wpc = skew_waves_per_cu(kStrip, kChains, bands, max_band, true);
     const int blocks = (int)std::min<int64_t>((int64_t)cus * (wpc / bands), nbig);
     a.lds_bytes = 0;
     rc = check_hip(launch_align_skew(dtype, kStrip, kChains, bands, blocks, a, st, true),

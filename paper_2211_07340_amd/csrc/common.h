@@ -66,14 +66,25 @@ inline int32_t skew_band_rows(int32_t m, int chains, int bands, int32_t target =
   return (m + pe - 1) / pe;
 }
 
-// LDS words of the skew kernel: shared part (zeros and a +inf cell; the
+// LDS words of the skew kernel: a shared part (zeros and a +inf cell; the
 // band-to-band rings) and, per band, the finished-row stage and the
-// query/boundary entries of up to band_rows rows.
+// query/boundary entries of up to band_rows rows.  Extending resident rows
+// (stream), the shared part also holds the first band's copy of the
+// resident row's next tile and the value left of it, and one finished-row
+// stage serves every band (only a read's last band uses it), so that two
+// workgroups of four bands fit on a CU.
+__host__ __device__ constexpr int skew_entry_words(int chains, int band_rows) {
+  return (2 * (band_rows + 64 * chains) + 3) & ~3;
+}
 __host__ __device__ constexpr int skew_band_words(int strip, int chains, int band_rows) {
   return (64 * strip + 2 * (band_rows + 64 * chains) + 3) & ~3;
 }
-inline size_t skew_lds_bytes(int strip, int chains, int bands, int band_rows) {
-  const size_t shared = (size_t)strip + 4 + (size_t)(bands - 1) * (2 * 64 * (size_t)strip + 4);
+inline size_t skew_lds_bytes(int strip, int chains, int bands, int band_rows,
+                             bool stream = false) {
+  const size_t tile = 64 * (size_t)strip;
+  const size_t shared = (size_t)strip + 4 + (size_t)(bands - 1) * (2 * tile + 4);
+  if (stream)
+    return 4 * (shared + 2 * tile + 4 + (size_t)bands * skew_entry_words(chains, band_rows));
   return 4 * (shared + (size_t)bands * (size_t)skew_band_words(strip, chains, band_rows));
 }
 
