@@ -177,6 +177,9 @@ struct DescRing {
   std::mutex mu;
   std::vector<std::unique_ptr<DescSlot>> slot;
   int next = 0;  // round-robin victim when all kMaxDescSlots are busy
+  // long-reference stream extensions enqueued and perhaps still running, with
+  // their workgroup counts
+  std::vector<std::pair<std::shared_ptr<CallToken>, int>> long_inflight;
 };
 static DescRing g_ring[kMaxDevices];
 static std::atomic<int> g_stream_bands{0};  // sdtw_stream_set_config (0: automatic)
@@ -1239,18 +1242,46 @@ int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk
   a.counter = (int32_t*)(sl.dev + sl.cap);
   a.cost = cost_dev;
   a.end = end_dev;
+  int long_blocks = 0;
   if (!rc && nbig) {
     a.items = sl.dev;
     a.nwork = nbig;
     a.max_m = (int32_t)len(order[0]);
     a.max_band = max_band;
-    // no LDS reservation (spread_lds): calls in flight on other HIP streams
-    // (other targets, the next batch) must find room on every CU
+    // No LDS reservation (spread_lds): calls in flight on other HIP streams
+    // (other targets, the next batch) must find room on every CU.  Except
+    // for long references while this launch and the long-reference launches
+    // still running have at most one workgroup per CU between them: two
+    // long-reference workgroups fit on a CU (two waves per SIMD), which pays
+    // once the device is full, but with CUs idle the dispatcher would also
+    // put the next batch's workgroups beside this one's, each then slower
+    // than alone on a CU of its own.  Such a launch reserves enough LDS that
+    // no second long-reference workgroup joins one of its CUs (short-
+    // reference ones, a third of the size, still do).
     const int wpc = skew_waves_per_cu(kStrip, kChains, bands, max_band, true);
     const int blocks = (int)std::min<int64_t>((int64_t)cus * (wpc / bands), nbig);
+    int64_t running = 0;
+    if (kStrip == 32) {
+      auto& v = ring.long_inflight;
+      v.erase(std::remove_if(v.begin(), v.end(),
+                             [](const std::pair<std::shared_ptr<CallToken>, int>& e) {
+                               if (!e.first->ev) return true;
+                               if (hipEventQuery(e.first->ev) != hipErrorNotReady) return true;
+                               (void)hipGetLastError();  // "not ready" is no error here
+                               return false;
+                             }),
+              v.end());
+      for (const auto& e : v) running += e.second;
+    }
     a.lds_bytes = 0;
+    if (kStrip == 32 && 2 * (blocks + running) <= cus) {
+      const size_t need = skew_lds_bytes(kStrip, kChains, bands, max_band, true);
+      const size_t alone = ((160 * 1024 - need + 1024 + 1023) & ~(size_t)1023);
+      if (alone > need && alone <= lds_max) a.lds_bytes = (int32_t)alone;
+    }
     rc = check_hip(launch_align_skew(dtype, kStrip, kChains, bands, blocks, a, st, true),
                    "sdtw_stream_extend: launch");
+    if (kStrip == 32) long_blocks = blocks;
   }
   if (!rc && nbig < ns) {
     a.items = sl.dev + nbig;
@@ -1263,6 +1294,7 @@ int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk
   if (!rc_ev) sl.last = tok;
   if (!rc) rc = rc_ev;
   if (rc) return rc;
+  if (long_blocks) ring.long_inflight.emplace_back(tok, long_blocks);
   for (int32_t i = 0; i < ns; ++i) {
     streams[i]->rows += (int32_t)len(i);
     streams[i]->last = tok;
