@@ -17,9 +17,10 @@ its last group of columns, done at the top of its own step after its right
 neighbours have read their edge from them, as the kernel does.  Where the
 previous row comes from is also the kernel's: band 0 takes gamma(0, .) = 0
 as every other column cleared with the diagonal set to 0, or, streaming,
-the resident row's strip and the value left of it, fetched with the tile's
-reference values once every lane has entered the current tile; the other
-bands read the ring.  The reference values of the next tile are held apart
+the resident row's strip and the value left of it from one copy of the
+next tile (a single buffer, refilled once every lane has entered the
+current tile, when the copy of the current tile has had its last read);
+the other bands read the ring.  The reference values of the next tile are held apart
 from the last band's staged last rows.
 
 Timing: the workgroup runs global periods G = 0, 1, ... with one barrier
