@@ -375,3 +375,53 @@ def test_extend_wide_rejections(dev):
     finally:
         fs.close()
         fref.close()
+
+
+def test_long_reference_batches_at_once(dev):
+    # two batched extensions of 256 resident rows each against a reference of
+    # more than 2^20 columns (strip 32, four bands), issued at once on two HIP
+    # streams so that their workgroups share CUs (together they cover more
+    # than half the device: no LDS reservation), give what the same
+    # extensions give one after another, and sampled rows match the oracle
+    budget0 = sd.row_budget_info()[0]
+    sd.set_row_budget(16 << 30)  # 512 rows of about 4 MB at a time
+    rng = np.random.default_rng(23)
+    n = (1 << 20) + 12345
+    ref_np = rng.integers(-3000, 3000, size=n).astype(np.int16)
+    ref = sd.Reference(torch.from_numpy(ref_np).to(dev))
+    k, m = 256, 400
+    chunks = [rng.integers(-3000, 3000, size=(2, 2 * k, m)).astype(np.int16)]
+    offs = np.arange(k + 1, dtype=np.int64) * m
+    hs = [torch.cuda.Stream(), torch.cuda.Stream()]
+
+    def run(together):
+        st = [sd.Stream(ref) for _ in range(2 * k)]
+        res = []
+        for c in range(2):
+            qa = torch.from_numpy(chunks[0][c, :k].reshape(-1)).to(dev)
+            qb = torch.from_numpy(chunks[0][c, k:].reshape(-1)).to(dev)
+            torch.cuda.synchronize()
+            ca, ea = sd.stream_extend(st[:k], qa, offs, stream=hs[0])
+            if not together:
+                hs[0].synchronize()
+            cb, eb = sd.stream_extend(st[k:], qb, offs, stream=hs[1])
+            torch.cuda.synchronize()
+            res.append((ca.cpu().numpy(), ea.cpu().numpy(), cb.cpu().numpy(), eb.cpu().numpy()))
+        for s in st:
+            s.close()
+        return res
+
+    note("two long-reference batches one after another, then at once")
+    apart = run(False)
+    together = run(True)
+    for a, b in zip(apart, together):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+    for i in (0, k - 1, k, 2 * k - 1):
+        prefix = np.concatenate([chunks[0][0, i], chunks[0][1, i]])
+        wc, we = oracle.sdtw_i64(prefix, ref_np)
+        half = 0 if i < k else 1
+        t = i if i < k else i - k
+        assert (int(together[1][2 * half][t]), int(together[1][2 * half + 1][t])) == (wc, we), i
+    ref.close()
+    sd.set_row_budget(budget0)
