@@ -465,7 +465,12 @@ int sdtw_stream_copy_row(sdtw_stream s, void* dst_dev, void* stream);
  * must share one reference.  Outputs, per stream in call order: the cost
  * and 0-based end of the new last row (as sdtw_align_batch).  A stream's
  * row count advances when the call returns; calls on the same streams must
- * be issued in order on one HIP stream (or ordered by the caller).
+ * be issued in order on one HIP stream (or ordered by the caller).  Calls
+ * on other streams may run at once on other HIP streams: against
+ * references of 2^20 columns or more two calls' workgroups share a CU once
+ * the calls in flight (the library counts its own) cover more than half
+ * the CUs, and take CUs of their own below that.  Placement never changes
+ * results.
  */
 int sdtw_stream_extend(const sdtw_stream* streams, int32_t ns, const void* chunk_dev,
                        const int64_t* chunk_offsets_host, void* cost_dev, int32_t* end_dev,
