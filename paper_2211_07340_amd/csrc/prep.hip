@@ -67,20 +67,38 @@ __global__ void k_zero_i64(int64_t* p) {
 // One wave per read.  Events are staged through LDS in coalesced chunks and
 // lane 0 accumulates the sum and then the sum of squared deviations in index
 // order, so the statistics come from the same sequence of double operations
-// as a plain sequential loop; all lanes then normalise and quantise.
+// as a plain sequential loop; all lanes then normalise and quantise.  The
+// next chunk's loads are issued before lane 0 sums the current one (two LDS
+// buffers), so memory latency hides behind the sequential sum.
 constexpr int kQChunk = 512;
+constexpr int kQPer = kQChunk / 64;
 
 __device__ __forceinline__ double wave_seq_sum(const float* __restrict__ raw, int64_t a, int64_t b,
                                                double mean, bool squares, float* buf) {
   const int lane = (int)threadIdx.x;
   double acc = 0.0;
+  float pre[kQPer];
+  auto fetch = [&](int64_t base) {
+#pragma unroll
+    for (int j = 0; j < kQPer; ++j) {
+      const int64_t i = base + lane + 64 * j;
+      pre[j] = i < b ? raw[i] : 0.0f;
+    }
+  };
+  fetch(a);
+  int cur = 0;
   for (int64_t base = a; base < b; base += kQChunk) {
     const int n = (int)min<int64_t>(kQChunk, b - base);
-    for (int k = lane; k < n; k += 64) buf[k] = raw[base + k];
+    float* const cb = buf + cur * kQChunk;
+#pragma unroll
+    for (int j = 0; j < kQPer; ++j) cb[lane + 64 * j] = pre[j];
+    // one barrier per chunk: the other buffer, written next, was last read
+    // by lane 0 before it reached this barrier
     __syncthreads();
+    if (base + kQChunk < b) fetch(base + kQChunk);
     if (lane == 0) {
       for (int k = 0; k < n; ++k) {
-        const double v = (double)buf[k];
+        const double v = (double)cb[k];
         if (squares) {
           const double d = v - mean;
           acc += d * d;
@@ -89,8 +107,9 @@ __device__ __forceinline__ double wave_seq_sum(const float* __restrict__ raw, in
         }
       }
     }
-    __syncthreads();
+    cur ^= 1;
   }
+  __syncthreads();  // lane 0 is done with both buffers before they are reused
   return __shfl(acc, 0);
 }
 
@@ -99,7 +118,7 @@ __device__ __forceinline__ double wave_seq_sum(const float* __restrict__ raw, in
 __global__ __launch_bounds__(64) void k_seq_stats(const float* __restrict__ x, int64_t n,
                                                   double* __restrict__ stats,
                                                   int64_t* __restrict__ nsat) {
-  __shared__ float buf[kQChunk];
+  __shared__ float buf[2 * kQChunk];
   const double mean = wave_seq_sum(x, 0, n, 0.0, false, buf) / (double)n;
   const double sd = sqrt(wave_seq_sum(x, 0, n, mean, true, buf) / (double)n);
   if (threadIdx.x == 0) {
@@ -119,7 +138,7 @@ __global__ __launch_bounds__(64) void k_prep_queries(const float* __restrict__ r
                                                      float* __restrict__ z,
                                                      int16_t* __restrict__ codes,
                                                      int64_t* __restrict__ nsat) {
-  __shared__ float buf[kQChunk];
+  __shared__ float buf[2 * kQChunk];
   const int32_t r = (int32_t)blockIdx.x;
   if (r >= nq) return;
   const int64_t a = offs[r], b = offs[r + 1];
