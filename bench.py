@@ -446,6 +446,8 @@ def extras(sd, torch, dev, w, reads, zref, cref, args, stream):
         res["single_query_whole_device"] = {
             "query_values": m1, "reference_values": ref0.n, "ms": round(ms1, 4),
             "paper_accelerator_model_ms": round((ref0.n + m1 - 1) / 1e8 * 1e3, 4)}
+        if ref0.n > 1_000_000:
+            res["stream_extension"] = stream_extension_leg(sd, torch, dev, ref0, stream)
     # pre-processing on the device: event detection and trimming of raw reads
     import synth
     sg = synth.make_genome(synth.SMALL_GENOME, synth.SMALL_GENOME)
@@ -460,6 +462,44 @@ def extras(sd, torch, dev, w, reads, zref, cref, args, stream):
     ref0.close()
     ref.close()
     return res
+
+
+def stream_extension_leg(sd, torch, dev, ref, stream, k=256, m=400):
+    """Resident-row extension on the long reference: k streams (one per CU
+    on an MI355X) extended by an m-value chunk each in one batched launch
+    (HIP events on the launch stream, median of three after the first
+    chunk), and two such batches issued at once on two HIP streams
+    (host clock), as the Read Until server keeps two per target in flight."""
+    progress("extras: resident-row extension")
+    budget0 = sd.row_budget_info()[0]
+    sd.set_row_budget(max(budget0, 2 * k * 4 * (ref.n + 8192) + (1 << 30)))
+    rng = np.random.default_rng(5)
+    streams = [sd.Stream(ref) for _ in range(2 * k)]
+    offs = np.arange(k + 1, dtype=np.int64) * m
+    qa = torch.from_numpy(rng.integers(-300, 300, size=k * m).astype(np.int16)).to(dev)
+    qb = torch.from_numpy(rng.integers(-300, 300, size=k * m).astype(np.int16)).to(dev)
+    sd.stream_extend(streams[k:], qb, offs)  # first chunk of the second set
+    torch.cuda.synchronize()
+    ms = _median_event_ms(torch, stream, lambda: sd.stream_extend(streams[:k], qa, offs,
+                                                                  stream=stream), 3)
+    hs = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sd.stream_extend(streams[:k], qa, offs, stream=hs[0])
+    sd.stream_extend(streams[k:], qb, offs, stream=hs[1])
+    torch.cuda.synchronize()
+    two = (time.perf_counter() - t0) * 1e3
+    for st in streams:
+        st.close()
+    torch.cuda.synchronize()
+    sd.row_pool_trim()  # about 20 GB of rows back to the device
+    sd.set_row_budget(budget0)
+    cells = float(k) * m * ref.n
+    peak = valu_peak_tcups("i16")
+    return {"chunks": k, "chunk_values": m, "reference_values": ref.n,
+            "one_batch_ms": round(ms, 3), "frac_valu_peak": round(cells / ms / 1e9 / peak, 4),
+            "two_batches_at_once_ms": round(two, 3),
+            "two_batches_frac_valu_peak": round(2 * cells / two / 1e9 / peak, 4)}
 
 
 def _median_event_ms(torch, stream, fn, reps):
