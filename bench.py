@@ -482,7 +482,11 @@ def stream_extension_leg(sd, torch, dev, ref, stream, k=256, m=400):
     torch.cuda.synchronize()
     ms = _median_event_ms(torch, stream, lambda: sd.stream_extend(streams[:k], qa, offs,
                                                                   stream=stream), 3)
-    hs = [torch.cuda.Stream(), torch.cuda.Stream()]
+    # the server's own HIP streams: a stream created beyond the hardware
+    # queues shares one with an older stream, and the serving leg that
+    # follows would then find its streams serialised
+    from paper_2211_07340_amd import server as srv
+    hs = srv._server_streams(torch, 0, 2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sd.stream_extend(streams[:k], qa, offs, stream=hs[0])
